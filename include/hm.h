@@ -1,0 +1,208 @@
+/*
+ * hm.h -- C ABI of the MI355X (gfx950) hierarchical-matrix product engine.
+ *
+ * The library computes the update  y := alpha * M * x + y  (eq. 4 of
+ * Kriemann, "Floating Point Compression of Hierarchical Matrix Formats and
+ * its Impact on Matrix-Vector Multiplication", Sec. 3) for a hierarchical
+ * matrix M stored in one of three forms:
+ *   H   (Sec. 2.2, Def. 2.3, eq. 3): dense inadmissible leaves D and
+ *        low-rank admissible leaves U V^T,
+ *   UH  (Sec. 2.3): shared orthonormal cluster bases W_t, X_s and a
+ *        coupling matrix S per admissible leaf, M_b = W_t S_b X_s^T,
+ *   H2  (Sec. 2.4): nested bases; explicit bases at leaf clusters only and
+ *        transfer matrices E (rows) / F (columns) above them:
+ *        W_t = [W_t0 E_t0 ; W_t1 E_t1].
+ * The block structure is a block tree over a cluster tree (Def. 2.1, 2.2).
+ *
+ * Conventions for every call:
+ *   - Every call returns an hm_status; nothing aborts or throws across the ABI.
+ *     On failure hm_last_error() returns a thread-local message.
+ *   - Callers own every array they pass; the library copies what it keeps.
+ *     Objects returned through out-pointers are owned by the library until
+ *     the matching *_free / *_destroy call.
+ *   - Matrices are column-major with leading dimension = row count.
+ *   - Index vectors are in original point order unless HM_CLUSTER_ORDER is
+ *     given; perm[i] is the original index of cluster position i.
+ *   - Device work is enqueued on the given HIP stream and never synchronises
+ *     the host, except hm_upload which returns after the copy completes.
+ */
+#ifndef HM_H
+#define HM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hm_stream_t; /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+    HM_OK = 0,
+    HM_EINVAL = -1,     /* bad argument (null pointer, size, id, dtype) */
+    HM_ENOMEM = -2,     /* host or device allocation failed */
+    HM_EDEVICE = -3,    /* a HIP runtime call failed */
+    HM_ELAYOUT = -4,    /* partition or value set inconsistent with the layout */
+    HM_EBUSY = -5,      /* serving queue full */
+    HM_ENOTREADY = -6   /* result not available yet */
+} hm_status;
+
+typedef enum { HM_FMT_H = 0, HM_FMT_UH = 1, HM_FMT_H2 = 2 } hm_format;
+
+/* Storage formats (Table 1).  FP8 is OCP E4M3 (no infinities, max 448).
+ * HM_VALR_AUTO picks per column the cheapest format whose measured error
+ * meets delta_i = delta / sigma_i (Sec. 4.2, eq. 6-7). */
+typedef enum {
+    HM_F64 = 0, HM_F32 = 1, HM_BF16 = 2, HM_F16 = 3, HM_FP8E4M3 = 4, HM_VALR_AUTO = 5
+} hm_dtype;
+
+typedef enum { HM_ACC_AUTO = 0, HM_ACC_F32 = 1, HM_ACC_F64 = 2 } hm_accum;
+
+/* hm_mvm flags */
+#define HM_CLUSTER_ORDER 1u   /* x and y are already in cluster order */
+
+/* ---------------------------------------------------------------- layout */
+
+typedef struct {
+    int32_t leaf_size;   /* a cluster with at most leaf_size points is a leaf (default 64) */
+    double eta;          /* admissibility min(diam) <= eta * dist (default 2) */
+} hm_layout_opts;
+
+typedef struct hm_layout hm_layout;
+
+/* Cluster tree by geometric bisection and block tree with standard
+ * admissibility (Def. 2.1, 2.2):
+ *   - a cluster's box is the tight axis-aligned box of its points;
+ *   - clusters larger than leaf_size split along the axis of largest extent
+ *     (lowest axis on ties) at 0.5*(lo+hi); points with coordinate < mid go
+ *     to son 0, keeping their order; an empty side splits at half the size;
+ *   - a block (t,s) is low rank if min(diam_t^2, diam_s^2) <= eta^2 dist^2
+ *     and dist^2 > 0 (squared box diameters/distance, summed x,y,z), else a
+ *     dense leaf if t or s is a leaf, else it recurses over son pairs.
+ * points: n x 3 row-major float64, caller-owned, n >= 1.  opts may be NULL.
+ * Deterministic: the same points give bit-identical layouts.
+ * Errors: HM_EINVAL (n < 1, null, non-finite point, leaf_size < 1, eta <= 0). */
+hm_status hm_build_layout(const double* points, int64_t n, const hm_layout_opts* opts,
+                          hm_layout** out);
+
+/* Read-only view of a layout (arrays owned by the layout).  Nodes are in
+ * depth-first pre-order (node 0 = root); node t covers cluster positions
+ * [node_begin[t], node_end[t]).  Blocks are the block-tree leaves in
+ * depth-first order (son pairs tau-son major). */
+typedef struct {
+    int64_t n, nnodes, nblocks;
+    int32_t depth;                  /* largest node level */
+    const int64_t* perm;            /* [n] original index of cluster position i */
+    const int64_t* node_begin;      /* [nnodes] */
+    const int64_t* node_end;        /* [nnodes] */
+    const int32_t* node_level;      /* [nnodes] */
+    const int32_t* node_parent;     /* [nnodes] -1 at the root */
+    const int32_t* node_son0;       /* [nnodes] -1 at leaves */
+    const int32_t* node_son1;       /* [nnodes] -1 at leaves */
+    const int32_t* blk_tau;         /* [nblocks] row cluster */
+    const int32_t* blk_sigma;       /* [nblocks] column cluster */
+    const int32_t* blk_adm;         /* [nblocks] 1 = admissible (low rank) */
+} hm_layout_view;
+
+hm_status hm_layout_export(const hm_layout* layout, hm_layout_view* view);
+void hm_layout_free(hm_layout* layout);
+
+/* --------------------------------------------------------------- values */
+
+/* float64 values of one matrix, indexed by the layout's node and block ids.
+ * Entries not used by the chosen format may be NULL.  All matrices are
+ * column-major.
+ *   dense[b]           inadmissible b: |t| x |s|
+ *   H:   rank[b], W[b] (|t| x k, orthonormal columns), sigma[b] (k),
+ *        X[b] (|s| x k); the block is W diag(sigma) X^T (Sec. 4.2 form)
+ *   UH:  row_rank[v], col_rank[v]; row_basis[v] (|v| x k_v) and
+ *        col_basis[v] for every node; coupling[b] (k_t x k_s)
+ *   H2:  row_rank, col_rank; row_basis / col_basis at leaf nodes only;
+ *        row_transfer[v] = E_v (k_v x k_parent) and col_transfer[v] = F_v
+ *        (k_v x k_parent) at every non-root node; coupling[b]
+ *   row_sv / col_sv (optional): per-node weights of the basis columns
+ *        (singular values from the basis construction), used by VALR. */
+typedef struct {
+    const double* const* dense;
+    const int32_t* rank;
+    const double* const* W;
+    const double* const* sigma;
+    const double* const* X;
+    const int32_t* row_rank;
+    const int32_t* col_rank;
+    const double* const* row_basis;
+    const double* const* col_basis;
+    const double* const* row_transfer;
+    const double* const* col_transfer;
+    const double* const* row_sv;
+    const double* const* col_sv;
+    const double* const* coupling;
+} hm_values;
+
+/* Storage policy.  Dense leaves with t == s use diag_dtype, other dense
+ * leaves dense_dtype; low-rank factors (H), cluster bases (UH) and leaf
+ * bases (H2) use factor_dtype; coupling and transfer matrices use
+ * coupling_dtype (direct compression, Sec. 4.1).  Stored columns in FP16
+ * or FP8 carry one scale c = max(fl32(max|col| / largest finite), 2^-126);
+ * codes are round-to-nearest-even of col/c, saturated (FP64/FP32/BF16: c = 1).
+ * For H2 column transfers the scaled axis is the row of F (the column of
+ * F^T).  The singular values of H factors are folded into the column
+ * scales of W.
+ * accum: HM_ACC_AUTO = float64 accumulators if eps < 1e-7 or every dtype is
+ * HM_F64, else float32 accumulators (float64 dense diagonal leaves keep a
+ * float64 accumulator). */
+typedef struct {
+    double eps;
+    int32_t dense_dtype;
+    int32_t diag_dtype;
+    int32_t factor_dtype;
+    int32_t coupling_dtype;
+    int32_t accum;
+} hm_precision;
+
+typedef struct hm_matrix hm_matrix;
+
+/* Quantise on the host per `prec`, pack into level- and row-cluster-ordered
+ * streams and copy to the current HIP device.  Blocks whose value pointers
+ * are required but NULL, ranks that are negative or exceed the block size,
+ * and non-finite values give HM_EINVAL / HM_ELAYOUT.  The layout must stay
+ * alive as long as the matrix.  Returns after the copy has completed. */
+hm_status hm_upload(const hm_layout* layout, int32_t format, const hm_values* values,
+                    const hm_precision* prec, hm_stream_t stream, hm_matrix** out);
+void hm_matrix_free(hm_matrix* m);
+
+/* Storage statistics of an uploaded matrix (bytes as stored on the device). */
+typedef struct {
+    int64_t n, nblocks, ndense, nlowrank;
+    int64_t bytes_dense, bytes_factors, bytes_coupling, bytes_transfer, bytes_scales;
+    int64_t bytes_meta, bytes_workspace;
+    int64_t bytes_per_dtype[5];     /* stored matrix data by dtype (HM_F64..HM_FP8E4M3) */
+    int64_t sum_rank;               /* sum of block ranks (H) or basis ranks (UH/H2) */
+    int32_t max_rank;
+    int32_t accum;                  /* resolved accumulation (HM_ACC_F32 / HM_ACC_F64) */
+    int32_t nlaunch;                /* kernel launches per hm_mvm */
+    double algorithmic_bytes;       /* bytes one hm_mvm must move: data + scales + vectors + metadata */
+} hm_stats;
+
+hm_status hm_matrix_stats(const hm_matrix* m, hm_stats* s);
+
+/* ------------------------------------------------------------- products */
+
+/* y := alpha * M * x + y.  x, y: device float64 arrays of length n
+ * (caller-owned, e.g. PyTorch tensors), x != y.  Enqueued on `stream`;
+ * calls on one matrix must not overlap in time (they share its workspace). */
+hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double* y, uint32_t flags,
+                 hm_stream_t stream);
+
+/* Host-side helper used by tests: round float64 values to `dtype` exactly as
+ * hm_upload does (scale already applied); writes float64 results. */
+hm_status hm_round_host(int32_t dtype, const double* in, double* out, int64_t count);
+
+const char* hm_last_error(void);
+const char* hm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HM_H */

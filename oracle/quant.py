@@ -16,10 +16,11 @@ Formats (code: mantissa bits, smallest normal exponent, largest finite):
   3 FP16  10  -14    65504
   4 FP8 E4M3 (OCP, no infinities)  3  -6  448
 
-Column scaling: columns stored in BF16/FP16/FP8 carry one scale
-c = fl32(max|col| / largest finite) (c = 1 for an all-zero column), and the
-stored code is q = sat(round(col / c)), saturated at the largest finite value.
-FP32/FP64 columns use c = 1.  The dequantised entry c*q is exact in float64
+Column scaling: the narrow-exponent formats FP16 and FP8 carry one scale per
+column, c = max(fl32(max|col| / largest finite), 2^-126) (c = 1 for an
+all-zero column), so the column's largest entry lands on the top of the
+format's range; the stored code is q = sat(round(col / c)), saturated at the
+largest finite value.  FP64, FP32 and BF16 (FP32's exponent range) use c = 1.  The dequantised entry c*q is exact in float64
 (at most 11 significant bits times 24), so the stored matrix the product
 must reach is known exactly.
 """
@@ -64,10 +65,11 @@ def round_fmt(v: np.ndarray, fmt: int) -> np.ndarray:
 
 def column_scales(A: np.ndarray, fmt: int) -> np.ndarray:
     A = np.asarray(A, dtype=np.float64)
-    if fmt in (F64, F32) or A.shape[0] == 0:
+    if fmt in (F64, F32, BF16) or A.shape[0] == 0:
         return np.ones(A.shape[1])
     m = np.abs(A).max(axis=0)
     c = (m / MAXF[fmt]).astype(np.float32).astype(np.float64)
+    c = np.maximum(c, 2.0 ** -126)
     c[m == 0.0] = 1.0
     return c
 

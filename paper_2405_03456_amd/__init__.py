@@ -1,0 +1,211 @@
+"""MI355X (gfx950) engine for the hierarchical-matrix product y += alpha*M*x.
+
+Thin Python binding over the C ABI of libhm.so (include/hm.h): argument
+marshalling only, every step of the product runs in the library's HIP
+kernels.  PyTorch is used for device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (HM_ACC_AUTO, HM_ACC_F32, HM_ACC_F64, HM_BF16, HM_CLUSTER_ORDER,  # noqa: F401
+                   HM_F16, HM_F32, HM_F64, HM_FMT_H, HM_FMT_H2, HM_FMT_UH, HM_FP8E4M3, HMError)
+
+FORMATS = {"h": HM_FMT_H, "uh": HM_FMT_UH, "h2": HM_FMT_H2}
+DTYPES = {"f64": HM_F64, "f32": HM_F32, "bf16": HM_BF16, "f16": HM_F16, "fp8": HM_FP8E4M3}
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Layout:
+    """Cluster tree + block tree built by the library (hm_build_layout)."""
+
+    def __init__(self, points, leaf_size: int = 64, eta: float = 2.0):
+        L = _lib.lib()
+        self._pts = np.ascontiguousarray(points, dtype=np.float64)
+        if self._pts.ndim != 2 or self._pts.shape[1] != 3:
+            raise ValueError("points must be n x 3")
+        opts = _lib.LayoutOpts(leaf_size, eta)
+        h = ctypes.c_void_p()
+        _lib.check(L.hm_build_layout(_dptr(self._pts), self._pts.shape[0], ctypes.byref(opts),
+                                     ctypes.byref(h)))
+        self._h = h
+        self.n = self._pts.shape[0]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self) -> dict:
+        """Copies of the layout arrays (see hm_layout_view)."""
+        v = _lib.LayoutView()
+        _lib.check(_lib.lib().hm_layout_export(self._h, ctypes.byref(v)))
+
+        def arr(p, count, dt):
+            return np.ctypeslib.as_array(p, shape=(count,)).astype(dt, copy=True) if count else np.zeros(0, dt)
+        N, B = v.nnodes, v.nblocks
+        return dict(n=v.n, depth=v.depth, perm=arr(v.perm, v.n, np.int64),
+                    begin=arr(v.node_begin, N, np.int64), end=arr(v.node_end, N, np.int64),
+                    level=arr(v.node_level, N, np.int64), parent=arr(v.node_parent, N, np.int64),
+                    son0=arr(v.node_son0, N, np.int64), son1=arr(v.node_son1, N, np.int64),
+                    blk_tau=arr(v.blk_tau, B, np.int64), blk_sigma=arr(v.blk_sigma, B, np.int64),
+                    blk_adm=arr(v.blk_adm, B, np.int64).astype(bool))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None and _lib._lib is not None:
+            _lib._lib.hm_layout_free(h)
+            self._h = None
+
+
+class _PtrTable:
+    """Array of double* (one per node/block) keeping the arrays alive."""
+
+    def __init__(self, arrays):
+        self.keep = []
+        self.addr = np.zeros(len(arrays), dtype=np.uint64)
+        for i, a in enumerate(arrays):
+            if a is None:
+                continue
+            a = np.asfortranarray(a, dtype=np.float64)
+            if a.size == 0:
+                continue
+            self.keep.append(a)
+            self.addr[i] = a.ctypes.data
+
+    @property
+    def ptr(self):
+        return self.addr.ctypes.data
+
+
+def _ranks(arrays, axis=1):
+    return np.array([0 if a is None else (a.shape[axis] if np.ndim(a) == 2 else len(a)) for a in arrays],
+                    dtype=np.int32)
+
+
+def marshal_values(fmt: str, values):
+    """hm_values for `values` (see Matrix) plus the arrays that must stay alive."""
+    f = FORMATS[fmt]
+    v = _lib.Values()
+    tabs = []
+
+    def tab(arrs):
+        t = _PtrTable(arrs)
+        tabs.append(t)
+        return t.ptr
+
+    def ints(a):
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        tabs.append(a)
+        return a.ctypes.data
+
+    v.dense = tab(values.dense)
+    if f == HM_FMT_H:
+        v.rank = ints(_ranks(values.sigma, 0))
+        v.W, v.sigma, v.X = tab(values.W), tab(values.sigma), tab(values.X)
+    elif f == HM_FMT_UH:
+        v.row_rank = ints(_ranks(values.row_basis))
+        v.col_rank = ints(_ranks(values.col_basis))
+        v.row_basis, v.col_basis = tab(values.row_basis), tab(values.col_basis)
+        v.coupling = tab(values.coupling)
+    else:
+        v.row_rank, v.col_rank = ints(values.row_rank), ints(values.col_rank)
+        v.row_basis, v.col_basis = tab(values.row_leaf_basis), tab(values.col_leaf_basis)
+        v.row_transfer, v.col_transfer = tab(values.row_transfer), tab(values.col_transfer)
+        v.coupling = tab(values.coupling)
+    return v, tabs
+
+
+def make_precision(eps=0.0, dense="f64", diag=None, factor="f64", coupling=None, accum=HM_ACC_AUTO):
+    return _lib.Precision(eps, DTYPES[dense], DTYPES[diag or dense], DTYPES[factor],
+                          DTYPES[coupling or factor], accum)
+
+
+class Matrix:
+    """A hierarchical matrix uploaded to the current HIP device (hm_upload).
+
+    `values` is any object with the attributes of the chosen format:
+      h:  dense, W, sigma, X                       (per block)
+      uh: dense, row_basis, col_basis, coupling    (per block / node)
+      h2: dense, row_rank, col_rank, row_leaf_basis, row_transfer,
+          col_leaf_basis, col_transfer, coupling
+    """
+
+    def __init__(self, layout: Layout, fmt: str, values, eps: float = 0.0, dense="f64", diag=None,
+                 factor="f64", coupling=None, accum: int = HM_ACC_AUTO, stream=None):
+        L = _lib.lib()
+        self.layout = layout
+        self.fmt = fmt
+        f = FORMATS[fmt]
+        v, tabs = marshal_values(fmt, values)
+        prec = make_precision(eps, dense, diag, factor, coupling, accum)
+        h = ctypes.c_void_p()
+        _lib.check(L.hm_upload(layout.handle, f, ctypes.byref(v), ctypes.byref(prec),
+                               _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        _lib.check(_lib.lib().hm_matrix_stats(self._h, ctypes.byref(s)))
+        out = {k: getattr(s, k) for k, _ in _lib.Stats._fields_}
+        out["bytes_per_dtype"] = list(s.bytes_per_dtype)
+        return out
+
+    def mvm(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None):
+        """y += alpha * M * x for device float64 tensors (enqueued, asynchronous)."""
+        xp, yp = _dev_ptr(x, self.layout.n), _dev_ptr(y, self.layout.n)
+        _lib.check(_lib.lib().hm_mvm(self._h, float(alpha), xp, yp,
+                                     HM_CLUSTER_ORDER if cluster_order else 0, _stream_ptr(stream)))
+
+    def free(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None and _lib._lib is not None:
+            _lib._lib.hm_matrix_free(h)
+        self._h = None
+
+    def __del__(self):
+        self.free()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_ptr(t, n):
+    if isinstance(t, int):
+        return t
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == n):
+        raise ValueError("vectors must be contiguous float64 device tensors of length n")
+    return t.data_ptr()
+
+
+def round_host(dtype: str, values) -> np.ndarray:
+    """The library's storage rounding (host), for tests."""
+    a = np.ascontiguousarray(values, dtype=np.float64)
+    out = np.empty_like(a)
+    _lib.check(_lib.lib().hm_round_host(DTYPES[dtype], _dptr(a), _dptr(out), a.size))
+    return out
+
+
+def version() -> str:
+    return _lib.lib().hm_version().decode()

@@ -1,0 +1,105 @@
+"""ctypes declarations of the C ABI in include/hm.h.
+
+Loading fails loudly when libhm.so has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhm.so")
+
+c_int32, c_int64, c_double, c_void_p, c_uint32 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                                  ctypes.c_void_p, ctypes.c_uint32)
+P = ctypes.POINTER
+
+HM_OK, HM_EINVAL, HM_ENOMEM, HM_EDEVICE, HM_ELAYOUT, HM_EBUSY, HM_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
+HM_FMT_H, HM_FMT_UH, HM_FMT_H2 = 0, 1, 2
+HM_F64, HM_F32, HM_BF16, HM_F16, HM_FP8E4M3, HM_VALR_AUTO = 0, 1, 2, 3, 4, 5
+HM_ACC_AUTO, HM_ACC_F32, HM_ACC_F64 = 0, 1, 2
+HM_CLUSTER_ORDER = 1
+
+
+class LayoutOpts(ctypes.Structure):
+    _fields_ = [("leaf_size", c_int32), ("eta", c_double)]
+
+
+class LayoutView(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("nnodes", c_int64), ("nblocks", c_int64), ("depth", c_int32),
+                ("perm", P(c_int64)), ("node_begin", P(c_int64)), ("node_end", P(c_int64)),
+                ("node_level", P(c_int32)), ("node_parent", P(c_int32)), ("node_son0", P(c_int32)),
+                ("node_son1", P(c_int32)), ("blk_tau", P(c_int32)), ("blk_sigma", P(c_int32)),
+                ("blk_adm", P(c_int32))]
+
+
+class Values(ctypes.Structure):
+    _fields_ = [("dense", c_void_p), ("rank", c_void_p), ("W", c_void_p), ("sigma", c_void_p),
+                ("X", c_void_p), ("row_rank", c_void_p), ("col_rank", c_void_p),
+                ("row_basis", c_void_p), ("col_basis", c_void_p), ("row_transfer", c_void_p),
+                ("col_transfer", c_void_p), ("row_sv", c_void_p), ("col_sv", c_void_p),
+                ("coupling", c_void_p)]
+
+
+class Precision(ctypes.Structure):
+    _fields_ = [("eps", c_double), ("dense_dtype", c_int32), ("diag_dtype", c_int32),
+                ("factor_dtype", c_int32), ("coupling_dtype", c_int32), ("accum", c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("nblocks", c_int64), ("ndense", c_int64), ("nlowrank", c_int64),
+                ("bytes_dense", c_int64), ("bytes_factors", c_int64), ("bytes_coupling", c_int64),
+                ("bytes_transfer", c_int64), ("bytes_scales", c_int64), ("bytes_meta", c_int64),
+                ("bytes_workspace", c_int64), ("bytes_per_dtype", c_int64 * 5), ("sum_rank", c_int64),
+                ("max_rank", c_int32), ("accum", c_int32), ("nlaunch", c_int32),
+                ("algorithmic_bytes", c_double)]
+
+
+# name -> (restype, argtypes); every exported symbol of include/hm.h
+SIGNATURES = {
+    "hm_build_layout": (c_int32, [P(c_double), c_int64, P(LayoutOpts), P(c_void_p)]),
+    "hm_layout_export": (c_int32, [c_void_p, P(LayoutView)]),
+    "hm_layout_free": (None, [c_void_p]),
+    "hm_upload": (c_int32, [c_void_p, c_int32, P(Values), P(Precision), c_void_p, P(c_void_p)]),
+    "hm_matrix_free": (None, [c_void_p]),
+    "hm_matrix_stats": (c_int32, [c_void_p, P(Stats)]),
+    "hm_mvm": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p]),
+    "hm_round_host": (c_int32, [c_int32, P(c_double), P(c_double), c_int64]),
+    "hm_last_error": (ctypes.c_char_p, []),
+    "hm_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class HMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hm status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        # PyTorch ships its own HIP runtime under the same soname
+        # (libamdhip64.so.7).  Loading torch first makes libhm bind to that
+        # copy, so the process has a single HIP runtime and device context.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2405_03456_amd.build.build() "
+                              "(there is no fallback path)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != HM_OK:
+        raise HMError(status, lib().hm_last_error().decode(errors="replace"))

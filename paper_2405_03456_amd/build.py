@@ -1,0 +1,67 @@
+"""Build the HIP library libhm.so for gfx950 in-tree.
+
+Host translation units are compiled with -ffp-contract=off so that the
+layout's geometric predicates round exactly as written.  Device code is built
+for gfx950 only, with packed-FP32 instructions disabled.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libhm.so")
+ARCH = os.environ.get("HM_OFFLOAD_ARCH", "gfx950")
+
+HOST_SRCS = ["hm_layout.cpp", "hm_quant.cpp", "hm_pack.cpp"]
+DEVICE_SRCS = ["hm_runtime.hip"]
+HEADERS = ["hm_internal.h", "hm_plan.h", "hm_pack.h"]
+
+COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-ffp-contract=off"]
+DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-munsafe-fp-atomics"]
+
+
+def _hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
+        if c and os.path.exists(c):
+            return c
+    return "hipcc"
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        sys.stderr.write(out + "\n")
+        raise RuntimeError("build failed: " + " ".join(cmd))
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source and link libhm.so.  Always recompiles."""
+    os.makedirs(BUILD, exist_ok=True)
+    hipcc = _hipcc()
+    objs = []
+    inc = ["-I", os.path.join(HERE, "..", "include"), "-I", CSRC]
+    for s in HOST_SRCS:
+        o = os.path.join(BUILD, s + ".o")
+        _run([hipcc, *COMMON, *inc, "-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    for s in DEVICE_SRCS:
+        o = os.path.join(BUILD, s + ".o")
+        _run([hipcc, *COMMON, *DEVICE_FLAGS, *inc, "-x", "hip", "-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    tmp = LIB + ".tmp"
+    _run([hipcc, "-shared", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-lpthread"])
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

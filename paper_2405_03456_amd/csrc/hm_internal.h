@@ -1,0 +1,43 @@
+// Internal declarations shared by the host-side translation units of the
+// hierarchical-matrix engine.  Not part of the ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hm.h"
+
+namespace hm {
+
+void set_error(const std::string& msg);
+
+struct Layout {
+    int64_t n = 0;
+    int32_t leaf_size = 64;
+    double eta = 2.0;
+    int32_t depth = 0;
+    std::vector<int64_t> perm;
+    // nodes, depth-first pre-order
+    std::vector<int64_t> node_begin, node_end;
+    std::vector<int32_t> node_level, node_parent, node_son0, node_son1;
+    std::vector<double> node_lo, node_hi;   // 3 per node
+    // block-tree leaves, depth-first order
+    std::vector<int32_t> blk_tau, blk_sigma, blk_adm;
+
+    int64_t size(int32_t v) const { return node_end[v] - node_begin[v]; }
+    bool leaf(int32_t v) const { return node_son0[v] < 0; }
+};
+
+// Storage rounding shared by hm_upload and hm_round_host.
+double round_to(int32_t dtype, double v);
+double dtype_max(int32_t dtype);
+int dtype_bytes(int32_t dtype);
+// encode a value that is already representable in dtype into its bit pattern
+uint64_t encode(int32_t dtype, double v);
+
+}  // namespace hm
+
+struct hm_layout {
+    hm::Layout L;
+};

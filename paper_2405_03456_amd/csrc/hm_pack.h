@@ -1,0 +1,27 @@
+// Host packing of an H / UH / H2 matrix into the execution plan.
+#pragma once
+
+#include "hm_internal.h"
+#include "hm_plan.h"
+
+namespace hm {
+
+struct PackOptions {
+    int64_t task_bytes = 32768;   // target matrix bytes per task (one wavefront)
+};
+
+struct Packed {
+    int32_t format = 0;
+    int32_t acc64 = 1;
+    std::vector<Phase> phases;
+    std::vector<uint8_t> data;     // quantised matrix data, column-major slabs
+    std::vector<double> scales;    // per-column / per-row scales
+    int64_t ws_elems = 0;          // x in cluster order + coefficient vectors
+    int64_t part_elems = 0;        // partial-sum buffer (max over phases)
+    hm_stats stats{};
+};
+
+hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_precision* p,
+               const PackOptions& opt, Packed& out);
+
+}  // namespace hm

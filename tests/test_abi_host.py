@@ -1,0 +1,76 @@
+"""Host-side checks of the C ABI (no GPU needed): every declared symbol is
+exported, the library's layout equals the oracle's bit for bit (P-2), its
+storage rounding equals the oracle's, and bad inputs give error codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2405_03456_amd as hm
+from paper_2405_03456_amd import _lib
+from oracle import quant, trees
+from synth import sphere_points
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "hm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    names = declared_symbols()
+    assert "hm_mvm" in names and "hm_build_layout" in names
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in _lib.SIGNATURES, name
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (64, 2), (65, 3), (2048, 1001), (32768, 1002),
+                                    (131072, 1004), (262144, 1003)])
+def test_layout_bit_exact(n, seed):
+    p = sphere_points(n, seed)
+    e = hm.Layout(p).export()
+    st = trees.build_structure(p)
+    for k in ["perm", "begin", "end", "level", "parent", "son0", "son1", "blk_tau", "blk_sigma", "blk_adm"]:
+        assert np.array_equal(e[k], getattr(st, k)), k
+    assert e["depth"] == st.max_level()
+
+
+def test_layout_leaf_size_and_degenerate_points():
+    for p, leaf in [(np.ones((300, 3)), 16), (np.zeros((1, 3)), 64),
+                    (np.column_stack([np.arange(50.0), np.zeros(50), np.zeros(50)]), 3)]:
+        e = hm.Layout(p, leaf_size=leaf).export()
+        st = trees.build_structure(p, leaf)
+        for k in ["perm", "begin", "end", "blk_tau", "blk_sigma", "blk_adm"]:
+            assert np.array_equal(e[k], getattr(st, k)), k
+
+
+def test_layout_errors():
+    with pytest.raises(hm.HMError) as ex:
+        hm.Layout(np.zeros((0, 3)))
+    assert ex.value.status == _lib.HM_EINVAL
+    bad = sphere_points(10, 1)
+    bad[3, 1] = np.nan
+    with pytest.raises(hm.HMError):
+        hm.Layout(bad)
+    with pytest.raises(hm.HMError):
+        hm.Layout(sphere_points(10, 1), leaf_size=0)
+
+
+@pytest.mark.parametrize("name,fmt", [("f32", quant.F32), ("bf16", quant.BF16), ("f16", quant.F16),
+                                      ("fp8", quant.FP8)])
+def test_storage_rounding_matches_oracle(name, fmt):
+    rng = np.random.default_rng(fmt)
+    v = rng.standard_normal(200000) * np.exp(rng.uniform(-40, 40, 200000))
+    # exact midpoints and neighbours of representable values
+    grid = quant.round_fmt(rng.standard_normal(20000) * 4.0, fmt)
+    up = np.nextafter(grid, np.inf)
+    mid = 0.5 * (grid + quant.round_fmt(up * (1 + 2 ** -(quant.MANT[fmt])), fmt))
+    v = np.concatenate([v, grid, mid, np.nextafter(mid, 0), [0.0, -0.0, 1e-320, 5e-324, 1e300, -1e300]])
+    assert np.array_equal(hm.round_host(name, v), quant.round_fmt(v, fmt))

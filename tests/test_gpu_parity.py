@@ -1,0 +1,120 @@
+"""GPU parity: the HIP product against the oracle on the same stored matrix.
+
+Tolerances (relative L2 of the increment y_out - y_in):
+  * float64 storage and float64 accumulation: 1e-10,
+  * every other policy: 1e-6 (float32 accumulation; the oracle sees the
+    dequantised stored values exactly, so only accumulation order and the
+    float32 products differ, Sec. 4.1/4.2 storage error is not part of it).
+The layout and the oracle's trees are compared bit for bit before use."""
+import numpy as np
+import pytest
+
+from conftest import cached
+from oracle import stored, trees
+from synth import (KERNEL_IDENTITY, KERNEL_LAPLACE, compress_h, gaussian_vector, sphere_points,
+                   to_h2, to_uh)
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-6
+
+
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def make(n, eps, kernel=KERNEL_LAPLACE, seed=1001, leaf=64):
+    def build():
+        import paper_2405_03456_amd as hm
+        p = sphere_points(n, seed)
+        st = trees.build_structure(p, leaf)
+        lay = hm.Layout(p, leaf_size=leaf)
+        e = lay.export()
+        for k in ["perm", "begin", "end", "blk_tau", "blk_sigma", "blk_adm"]:
+            assert np.array_equal(e[k], getattr(st, k))
+        h = compress_h(p, kernel, st, eps, method="svd" if n <= 8192 else "auto")
+        vals = {"h": h}
+        if kernel != KERNEL_IDENTITY or True:
+            vals["uh"] = to_uh(h, st)
+            vals["h2"] = to_h2(h, st)
+        return p, st, lay, vals
+    return cached(("gpu", n, eps, kernel, seed, leaf), build)
+
+
+def run_gpu(lay, fmt, values, x, y, alpha, cluster=False, **policy):
+    import paper_2405_03456_amd as hm
+    torch = torch_cuda()
+    M = hm.Matrix(lay, fmt, values, **policy)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.from_numpy(y.copy()).cuda()
+    M.mvm(xd, yd, alpha=alpha, cluster_order=cluster)
+    torch.cuda.synchronize()
+    out = yd.cpu().numpy()
+    M.free()
+    return out
+
+
+def rel(a, b, y0):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b - y0), 1e-300)
+
+
+POLICIES = {
+    "f64": dict(dense="f64", factor="f64", eps=1e-8),
+    "f32": dict(dense="f32", factor="f32", eps=1e-6),
+    "bf16": dict(dense="f32", diag="f64", factor="bf16", coupling="f32", eps=1e-6),
+    "f16": dict(dense="f32", diag="f64", factor="f16", coupling="f16", eps=1e-6),
+    "fp8": dict(dense="f32", diag="f64", factor="fp8", coupling="fp8", eps=1e-6),
+    "f32acc64": dict(dense="f32", factor="f32", eps=1e-8),
+}
+
+
+@pytest.mark.parametrize("fmt", ["h", "uh", "h2"])
+@pytest.mark.parametrize("pol", list(POLICIES))
+def test_parity_n2048(fmt, pol):
+    n = 2048
+    p, st, lay, vals = make(n, 1e-8)
+    pp = dict(POLICIES[pol])
+    print(f"case fmt={fmt} policy={pol} n={n}", flush=True)
+    x, y = gaussian_vector(n, 2001), gaussian_vector(n, 3001)
+    sv = stored.stored_values(st, fmt, vals[fmt], dense=pp["dense"], diag=pp.get("diag"),
+                              factor=pp["factor"], coupling=pp.get("coupling"))
+    ref = stored.product(st, fmt, sv, -0.5, x, y)
+    out = run_gpu(lay, fmt, vals[fmt], x, y, -0.5, **pp)
+    tol = TOL64 if pol == "f64" or pol == "f32acc64" else TOL32
+    err = rel(out, ref, y)
+    print(f"  rel err {err:.3e} (tol {tol:g})", flush=True)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("fmt", ["h", "uh", "h2"])
+def test_cluster_order_and_determinism(fmt):
+    n = 2048
+    p, st, lay, vals = make(n, 1e-8)
+    x, y = gaussian_vector(n, 5), gaussian_vector(n, 6)
+    a = run_gpu(lay, fmt, vals[fmt], x, y, 1.0)
+    b = run_gpu(lay, fmt, vals[fmt], x, y, 1.0)
+    assert np.array_equal(a, b)                      # bitwise reproducible
+    c = run_gpu(lay, fmt, vals[fmt], x[st.perm], y[st.perm], 1.0, cluster=True)
+    assert np.array_equal(c, a[st.perm])
+
+
+@pytest.mark.parametrize("n", [1, 64, 65, 300])
+def test_small_and_ragged(n):
+    p, st, lay, vals = make(n, 1e-10, seed=77)
+    x, y = gaussian_vector(n, 8), gaussian_vector(n, 9)
+    for fmt in ("h", "uh", "h2"):
+        ref = stored.product(st, fmt, vals[fmt], 2.0, x, y)
+        out = run_gpu(lay, fmt, vals[fmt], x, y, 2.0)
+        assert rel(out, ref, y) <= TOL64, (n, fmt)
+
+
+def test_identity_kernel_rank_zero_blocks():
+    n = 1500
+    p, st, lay, vals = make(n, 1e-10, kernel=KERNEL_IDENTITY, seed=78)
+    x, y = gaussian_vector(n, 10), gaussian_vector(n, 11)
+    for fmt in ("h", "uh", "h2"):
+        out = run_gpu(lay, fmt, vals[fmt], x, y, -0.5)
+        assert np.array_equal(out, y - 0.5 * x), fmt
