@@ -61,6 +61,7 @@ typedef enum { HM_ACC_AUTO = 0, HM_ACC_F32 = 1, HM_ACC_F64 = 2 } hm_accum;
 
 /* hm_mvm flags */
 #define HM_CLUSTER_ORDER 1u   /* x and y are already in cluster order */
+#define HM_TIMING 2u          /* record HIP events around every phase kernel (hm_timing_read) */
 
 /* ---------------------------------------------------------------- layout */
 
@@ -194,6 +195,35 @@ hm_status hm_matrix_stats(const hm_matrix* m, hm_stats* s);
  * calls on one matrix must not overlap in time (they share its workspace). */
 hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double* y, uint32_t flags,
                  hm_stream_t stream);
+
+/* A product captured into a HIP graph: the kernels of one hm_mvm call with
+ * fixed (alpha, x, y, flags) recorded once and replayed with one launch.
+ * Replays read x and update y in place exactly like hm_mvm; results are
+ * bitwise identical to the eager call.  The matrix must outlive the graph.
+ * The graph records no memset nodes.  Errors: HM_EINVAL, HM_EDEVICE. */
+typedef struct hm_graph hm_graph;
+hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x, double* y, uint32_t flags,
+                          hm_stream_t stream, hm_graph** out);
+hm_status hm_graph_launch(hm_graph* g, hm_stream_t stream);
+void hm_graph_free(hm_graph* g);
+
+/* Per-phase kernel timing.  Every hm_mvm call made with HM_TIMING records a
+ * HIP event pair on its stream around each phase's main kernel; this call
+ * waits for the recorded events, returns the accumulated times and clears
+ * them.  out[i] for i < min(cap, number of phases); *nphase = number of
+ * phases.  Names are owned by the matrix.  algorithmic_bytes is what the
+ * phase kernel must move per launch: its stored matrix data, the scales and
+ * distinct input elements it reads, and the outputs it writes. */
+typedef struct {
+    const char* name;
+    double ms_total;
+    int64_t launches;
+    double algorithmic_bytes;
+    int32_t ntasks;
+    int32_t nowners;
+} hm_phase_timing;
+
+hm_status hm_timing_read(hm_matrix* m, hm_phase_timing* out, int32_t cap, int32_t* nphase);
 
 /* Host-side helper used by tests: round float64 values to `dtype` exactly as
  * hm_upload does (scale already applied); writes float64 results. */

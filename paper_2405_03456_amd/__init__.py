@@ -160,16 +160,56 @@ class Matrix:
         out["bytes_per_dtype"] = list(s.bytes_per_dtype)
         return out
 
-    def mvm(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None):
+    def mvm(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None, timing: bool = False):
         """y += alpha * M * x for device float64 tensors (enqueued, asynchronous)."""
         xp, yp = _dev_ptr(x, self.layout.n), _dev_ptr(y, self.layout.n)
-        _lib.check(_lib.lib().hm_mvm(self._h, float(alpha), xp, yp,
-                                     HM_CLUSTER_ORDER if cluster_order else 0, _stream_ptr(stream)))
+        flags = (HM_CLUSTER_ORDER if cluster_order else 0) | (_lib.HM_TIMING if timing else 0)
+        _lib.check(_lib.lib().hm_mvm(self._h, float(alpha), xp, yp, flags, _stream_ptr(stream)))
+
+    def graph(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None) -> "Graph":
+        """Capture one product (fixed x, y, alpha) into a replayable HIP graph."""
+        return Graph(self, x, y, alpha, cluster_order, stream)
+
+    def timing(self) -> list:
+        """Per-phase kernel times of the calls made with timing=True (and clears them)."""
+        cap = 4096
+        arr = (_lib.PhaseTiming * cap)()
+        n = ctypes.c_int32()
+        _lib.check(_lib.lib().hm_timing_read(self._h, arr, cap, ctypes.byref(n)))
+        return [dict(name=arr[i].name.decode(), ms_total=arr[i].ms_total, launches=arr[i].launches,
+                     algorithmic_bytes=arr[i].algorithmic_bytes, ntasks=arr[i].ntasks, nowners=arr[i].nowners)
+                for i in range(min(n.value, cap))]
 
     def free(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value and _lib is not None and _lib._lib is not None:
             _lib._lib.hm_matrix_free(h)
+        self._h = None
+
+    def __del__(self):
+        self.free()
+
+
+class Graph:
+    """hm_graph: a captured product, replayed with launch()."""
+
+    def __init__(self, M: Matrix, x, y, alpha, cluster_order, stream):
+        self.matrix = M           # keeps the matrix alive
+        self._xy = (x, y)         # keeps the vectors alive
+        h = ctypes.c_void_p()
+        flags = HM_CLUSTER_ORDER if cluster_order else 0
+        _lib.check(_lib.lib().hm_graph_create(M.handle, float(alpha), _dev_ptr(x, M.layout.n),
+                                              _dev_ptr(y, M.layout.n), flags, _stream_ptr(stream),
+                                              ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _lib.check(_lib.lib().hm_graph_launch(self._h, _stream_ptr(stream)))
+
+    def free(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None and _lib._lib is not None:
+            _lib._lib.hm_graph_free(h)
         self._h = None
 
     def __del__(self):

@@ -55,6 +55,13 @@ class Stats(ctypes.Structure):
                 ("algorithmic_bytes", c_double)]
 
 
+class PhaseTiming(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("ms_total", c_double), ("launches", c_int64),
+                ("algorithmic_bytes", c_double), ("ntasks", c_int32), ("nowners", c_int32)]
+
+
+HM_TIMING = 2
+
 # name -> (restype, argtypes); every exported symbol of include/hm.h
 SIGNATURES = {
     "hm_build_layout": (c_int32, [P(c_double), c_int64, P(LayoutOpts), P(c_void_p)]),
@@ -64,6 +71,10 @@ SIGNATURES = {
     "hm_matrix_free": (None, [c_void_p]),
     "hm_matrix_stats": (c_int32, [c_void_p, P(Stats)]),
     "hm_mvm": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p]),
+    "hm_graph_create": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p, P(c_void_p)]),
+    "hm_graph_launch": (c_int32, [c_void_p, c_void_p]),
+    "hm_graph_free": (None, [c_void_p]),
+    "hm_timing_read": (c_int32, [c_void_p, P(PhaseTiming), c_int32, P(c_int32)]),
     "hm_round_host": (c_int32, [c_int32, P(c_double), P(c_double), c_int64]),
     "hm_last_error": (ctypes.c_char_p, []),
     "hm_version": (ctypes.c_char_p, []),

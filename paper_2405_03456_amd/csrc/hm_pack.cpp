@@ -25,7 +25,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <deque>
 #include <thread>
 
 #include "hm_pack.h"
@@ -51,6 +50,12 @@ struct Source {
     int64_t cls = 0;             // stats class: 0 dense, 1 factor, 2 coupling, 3 transfer
 };
 
+// Slabs are stored in 16-byte tiles: tile t of an item holds columns
+// [t*V, t*V+V) of all its rows, row-major (one 16-byte chunk per row), with
+// V = 16 / element size.  Missing columns of the last tile are zero.
+int tile_cols(int32_t dt) { return 16 / dtype_bytes(dt); }
+int64_t tile_count(int32_t dt, int64_t ncols) { return (ncols + tile_cols(dt) - 1) / tile_cols(dt); }
+
 // formats whose columns carry a range scale (narrow exponent range)
 bool range_scaled(int32_t dt) { return dt == HM_F16 || dt == HM_FP8E4M3; }
 
@@ -60,7 +65,6 @@ struct Builder {
     const hm_values* V;
     PackOptions opt;
     int32_t dense_dt, diag_dt, factor_dt, coup_dt;
-    std::deque<Phase> phases;      // deque: owners keep references while they are built
     std::vector<Source> src;
     int64_t data_bytes = 0;
     int64_t nscales = 0;
@@ -93,6 +97,21 @@ struct Builder {
         return (int32_t)src.size() - 1;
     }
 
+    // scales[dst + j] = scales[a + j] * scales[b + j] (a or b < 0: factor 1),
+    // evaluated after every source has been quantised
+    struct Fold {
+        int64_t dst, a, b, k;
+    };
+    std::vector<Fold> folds;
+    int32_t fold_scales(int32_t a, int32_t b, int64_t k) {
+        if (a < 0 && b < 0) return -1;
+        if (a < 0 || b < 0) return a < 0 ? b : a;
+        int32_t dst = (int32_t)nscales;
+        nscales += k;
+        folds.push_back(Fold{dst, a, b, k});
+        return dst;
+    }
+
     // host transpose (for F^T), stored inside the source
     int32_t add_source_transposed(const double* A, int64_t m, int64_t k, int32_t dt, int cls) {
         int32_t id = add_source(nullptr, k, m, dt, nullptr, cls);
@@ -105,101 +124,156 @@ struct Builder {
     }
 
     // ---- owner construction
-    Phase* ph = nullptr;
+    // Owners and items go straight into the global tables.  Tasks go to the
+    // stage the owner was begun in, except tasks made only of floating items
+    // (dense leaves: they read nothing but x), which are kept aside and later
+    // spread over all stages to fill each launch (see place_floating).
+    std::vector<DOwner> owners;
+    std::vector<DItem> items;
+    std::vector<uint8_t> item_floating;
+    std::vector<std::vector<DTask>> stage_tasks;
+    std::vector<int64_t> stage_bytes;
+    std::vector<std::string> stage_names;
+    std::vector<std::pair<DTask, int64_t>> floating;   // (task, bytes)
+    int64_t part_elems = 0;
+    int32_t cur_stage = -1;
     DOwner cur{};
     int32_t cur_cols = 0;
+    int32_t cur_tiles = 0;
 
-    Phase& new_phase(const char* name) {
-        phases.emplace_back();
-        phases.back().name = name;
-        return phases.back();
+    int32_t new_stage(const char* name) {
+        stage_tasks.emplace_back();
+        stage_bytes.push_back(0);
+        stage_names.push_back(name);
+        return (int32_t)stage_tasks.size() - 1;
     }
 
-    void begin_owner(Phase& p, int32_t nrows, int32_t mode, int32_t out_off, int32_t rscale_off) {
-        ph = &p;
+    void begin_owner(int32_t stage, int32_t nrows, int32_t mode, int32_t out_off, int32_t rscale_off) {
+        cur_stage = stage;
         cur = DOwner{};
         cur.nrows = nrows;
-        cur.item0 = (int32_t)p.items.size();
+        cur.item0 = (int32_t)items.size();
         cur.nitems = 0;
         cur.out_off = out_off;
         cur.mode = mode;
         cur.rscale_off = rscale_off;
         cur_cols = 0;
-        if (nrows > p.max_rows) p.max_rows = nrows;
+        cur_tiles = 0;
     }
 
     // item = rows [r0, r0+nr) of source s (all its columns), or the transpose
-    void add_item(int32_t s, int64_t r0, bool transposed, int32_t vec_off) {
+    // unscaled: the source's column scales were folded into the producer of
+    // the item's input vector (see fold_scales), so the item multiplies none.
+    void add_item(int32_t s, int64_t r0, bool transposed, int32_t vec_off, bool unscaled = false,
+                  bool floats = false) {
         Source& S = src[s];
         const int64_t nr = cur.nrows;
         const int64_t ncols = transposed ? S.m : S.k;
         if (ncols == 0 || nr == 0) return;
-        const int64_t bytes = nr * ncols * dtype_bytes(S.dtype);
+        const int64_t bytes = tile_count(S.dtype, ncols) * nr * 16;
         DItem it{};
         it.data_off = alloc_data(bytes);
+        it.tile0 = cur_tiles;
+        cur_tiles += (int32_t)tile_count(S.dtype, ncols);
         it.col0 = cur_cols;
         it.ncols = (int32_t)ncols;
         it.vec_off = vec_off;
-        it.scale_off = transposed ? -1 : S.scale_off;
+        it.scale_off = (transposed || unscaled) ? -1 : S.scale_off;
         it.dtype = (int16_t)S.dtype;
         it.acc64 = S.dtype == HM_F64 ? 1 : 0;
-        ph->items.push_back(it);
-        ph->data_bytes += bytes;
+        items.push_back(it);
+        item_floating.push_back(floats ? 1 : 0);
         cur.nitems++;
         cur_cols += (int32_t)ncols;
         S.uses.push_back(Use{it.data_off, r0, nr, transposed});
     }
 
     void end_owner() {
-        Phase& p = *ph;
-        const int32_t owner_id = (int32_t)p.owners.size();
-        // cut the owner's columns into tasks of about opt.task_bytes
-        int32_t ntasks = 0;
+        const int32_t owner_id = (int32_t)owners.size();
+        // cut the owner's columns into tasks of about opt.task_bytes, on tile
+        // boundaries, never mixing floating and fixed items in one task
+        std::vector<std::pair<DTask, int64_t>> made;
         int32_t start_col = 0, start_item = cur.item0;
         int64_t acc = 0;
-        for (int32_t i = 0; i < cur.nitems; ++i) {
-            const DItem& it = p.items[cur.item0 + i];
-            const int64_t bpc = (int64_t)cur.nrows * dtype_bytes(it.dtype);
-            int32_t j = 0;
-            while (j < it.ncols) {
-                int64_t room = opt.task_bytes - acc;
-                int64_t take = std::max<int64_t>(1, room / bpc);
-                take = std::min<int64_t>(take, it.ncols - j);
-                acc += take * bpc;
-                j += (int32_t)take;
-                if (acc >= opt.task_bytes) {
-                    DTask t{};
-                    t.owner = owner_id;
-                    t.c0 = start_col;
-                    t.c1 = it.col0 + j;
-                    t.item_start = start_item;
-                    t.local = ntasks++;
-                    p.tasks.push_back(t);
-                    start_col = t.c1;
-                    start_item = (j == it.ncols) ? cur.item0 + i + 1 : cur.item0 + i;
-                    acc = 0;
-                }
-            }
-        }
-        if (start_col < cur_cols || ntasks == 0) {
+        auto emit = [&](int32_t c1) {
             DTask t{};
             t.owner = owner_id;
             t.c0 = start_col;
-            t.c1 = cur_cols;
-            t.item_start = std::min(start_item, cur.item0 + std::max(cur.nitems - 1, 0));
-            t.local = ntasks++;
-            p.tasks.push_back(t);
+            t.c1 = c1;
+            t.item_start = start_item;
+            t.local = (int32_t)made.size();
+            made.push_back({t, acc});
+            start_col = c1;
+            acc = 0;
+        };
+        for (int32_t i = 0; i < cur.nitems; ++i) {
+            const int32_t ii = cur.item0 + i;
+            const DItem& it = items[ii];
+            // a task never mixes floating and fixed items, nor two dtypes
+            if (i > 0 && start_col < it.col0 &&
+                (item_floating[ii] != item_floating[ii - 1] || it.dtype != items[ii - 1].dtype)) {
+                emit(it.col0);
+                start_item = ii;
+            }
+            const int V = tile_cols(it.dtype);
+            const int64_t bpt = (int64_t)cur.nrows * 16;     // bytes per tile
+            // narrow owners stage their task's inputs in LDS: at most
+            // MAX_TASK_INPUTS input values (tiles * V) per task
+            const int64_t cap = cur.nrows <= 32 ? (int64_t)(MAX_TASK_INPUTS / V) * bpt : INT64_MAX;
+            const int64_t target = std::min<int64_t>(opt.task_bytes, cap);
+            int32_t j = 0;
+            while (j < it.ncols) {
+                int64_t room = target - acc;
+                int64_t take = std::max<int64_t>(1, room / bpt) * V;   // whole tiles
+                take = std::min<int64_t>(take, it.ncols - j);
+                acc += ((take + V - 1) / V) * bpt;
+                j += (int32_t)take;
+                if (acc >= target) {
+                    emit(it.col0 + j);
+                    start_item = (j == it.ncols) ? ii + 1 : ii;
+                }
+            }
         }
-        cur.ntasks = ntasks;
-        if (ntasks > 1) {
-            cur.part_off = (int32_t)p.part_elems;
-            p.part_elems += (int64_t)ntasks * cur.nrows;
-            p.reduce_owners.push_back(owner_id);
-        } else {
-            cur.part_off = 0;
+        if (start_col < cur_cols || made.empty()) {
+            start_item = std::min(start_item, cur.item0 + std::max(cur.nitems - 1, 0));
+            emit(cur_cols);
         }
-        p.owners.push_back(cur);
-        ph = nullptr;
+        cur.ntasks = (int32_t)made.size();
+        cur.part_off = 0;
+        if (cur.ntasks > 1) {
+            cur.part_off = (int32_t)part_elems;
+            part_elems += (int64_t)cur.ntasks * cur.nrows;
+        }
+        // column -> tile of the owner's stream (task bounds are tile aligned
+        // inside an item; an item's end maps to its last tile + 1)
+        auto tile_of = [&](int32_t c) -> int32_t {
+            for (int32_t i = 0; i < cur.nitems; ++i) {
+                const DItem& it = items[cur.item0 + i];
+                if (c < it.col0 + it.ncols) return it.tile0 + (c - it.col0) / tile_cols(it.dtype);
+            }
+            return cur_tiles;
+        };
+        const int64_t stream = cur.nitems ? items[cur.item0].data_off : 0;
+        for (auto& tb : made) {
+            DTask& t = tb.first;
+            t.k0 = tile_of(t.c0);
+            t.k1 = tile_of(t.c1);
+            t.stream = stream;
+            t.nrows = cur.nrows;
+            t.mode = cur.mode;
+            t.out_off = cur.out_off;
+            t.ntasks = cur.ntasks;
+            t.part_off = cur.part_off;
+            t.rscale_off = cur.rscale_off;
+            const bool fl = t.c0 < t.c1 && item_floating[t.item_start];
+            if (fl) {
+                floating.push_back(tb);
+            } else {
+                stage_tasks[cur_stage].push_back(t);
+                stage_bytes[cur_stage] += tb.second;
+            }
+        }
+        owners.push_back(cur);
     }
 
     // ---- helpers
@@ -227,6 +301,18 @@ struct Builder {
         return add_source(V->dense[b], L.size(t), L.size(s), dt, nullptr, 0);
     }
 
+    // the dense leaves whose row cluster contains rho (floating items)
+    void add_dense_items(int32_t rho, const std::vector<int32_t>& anc, std::vector<int32_t>& dsrc) {
+        for (int32_t t : anc) {
+            const int64_t r0 = L.node_begin[rho] - L.node_begin[t];
+            for (int32_t b : row_blocks[t]) {
+                if (L.blk_adm[b]) continue;
+                if (dsrc[b] < 0) dsrc[b] = dense_source(b);
+                add_item(dsrc[b], r0, false, (int32_t)L.node_begin[L.blk_sigma[b]], false, true);
+            }
+        }
+    }
+
     bool check(bool ok, const char* msg) {
         if (!ok && err.empty()) err = msg;
         return ok;
@@ -251,37 +337,66 @@ struct Builder {
             const int64_t mt = L.size(L.blk_tau[b]), ms = L.size(L.blk_sigma[b]);
             if (k < 0 || k > std::min(mt, ms)) return check(false, "rank out of range");
             if (k > 0 && (!V->W[b] || !V->sigma[b] || !V->X[b])) return check(false, "missing factor");
-            if (k > 0) {
-                tb_off[b] = (int32_t)ws;
-                ws += k;
-            }
         }
-        Phase& pa = new_phase("h_vt");
-        for (int64_t b = 0; b < nb; ++b) {
-            if (!L.blk_adm[b] || V->rank[b] == 0) continue;
-            const int32_t k = V->rank[b];
-            const int32_t s = L.blk_sigma[b];
-            int32_t xs = add_source(V->X[b], L.size(s), k, factor_dt, nullptr, 1);
-            begin_owner(pa, k, 0, tb_off[b], src[xs].scale_off);
+        // t_b = X_b^T x|s for all low-rank blocks of one block column s at
+        // once: the X_b^T are stacked into one owner (they read the same x|s),
+        // and the t_b of a block column are laid out consecutively.
+        std::vector<std::vector<int32_t>> col_lr(L.node_begin.size());
+        for (int64_t b = 0; b < nb; ++b)
+            if (L.blk_adm[b] && V->rank[b] > 0) col_lr[L.blk_sigma[b]].push_back((int32_t)b);
+        ws = L.n;
+        for (auto& bl : col_lr)
+            for (int32_t b : bl) {
+                tb_off[b] = (int32_t)ws;
+                ws += V->rank[b];
+            }
+        const int32_t pa = new_stage("h_vt");
+        for (int32_t s = 0; s < (int32_t)col_lr.size(); ++s) {
+            if (col_lr[s].empty()) continue;
+            const int64_t ms = L.size(s);
+            int64_t K = 0;
+            for (int32_t b : col_lr[s]) K += V->rank[b];
+            // stacked X = [X_b1 X_b2 ...] (|s| x K); its per-column scales are
+            // those of the individual X_b columns
+            int32_t xs = add_source(nullptr, ms, K, factor_dt, nullptr, 1);
+            src[xs].own.resize((size_t)(ms * K));
+            int64_t c0 = 0;
+            for (int32_t b : col_lr[s]) {
+                const int32_t k = V->rank[b];
+                std::memcpy(src[xs].own.data() + c0 * ms, V->X[b], sizeof(double) * (size_t)(ms * k));
+                c0 += k;
+            }
+            src[xs].A = src[xs].own.data();
+            // row scale of the stacked owner: X's range scale times the U-side
+            // column scale (sigma_j and W's range scale) of each block
+            int32_t rs = -1;
+            std::vector<int32_t> us;
+            for (int32_t b : col_lr[s]) {
+                usrc[b] = add_source(V->W[b], L.size(L.blk_tau[b]), V->rank[b], factor_dt, V->sigma[b], 1);
+                us.push_back(src[usrc[b]].scale_off);
+            }
+            rs = (int32_t)nscales;
+            nscales += K;
+            int64_t r0 = 0;
+            for (size_t i = 0; i < col_lr[s].size(); ++i) {
+                const int32_t k = V->rank[col_lr[s][i]];
+                folds.push_back(Fold{rs + r0, src[xs].scale_off >= 0 ? src[xs].scale_off + r0 : -1, us[i], k});
+                r0 += k;
+            }
+            begin_owner(pa, (int32_t)K, 0, tb_off[col_lr[s][0]], rs);
             add_item(xs, 0, true, (int32_t)L.node_begin[s]);
             end_owner();
-            usrc[b] = add_source(V->W[b], L.size(L.blk_tau[b]), k, factor_dt, V->sigma[b], 1);
         }
-        Phase& pb = new_phase("h_rows");
+        const int32_t pb = new_stage("h_rows");
         for (int32_t rho : leaves) {
             begin_owner(pb, (int32_t)L.size(rho), 1, (int32_t)L.node_begin[rho], -1);
-            for (int32_t t : ancestors_root_first(rho)) {
+            const std::vector<int32_t> anc = ancestors_root_first(rho);
+            for (int32_t t : anc) {
                 const int64_t r0 = L.node_begin[rho] - L.node_begin[t];
-                for (int32_t b : row_blocks[t]) {
-                    const int32_t s = L.blk_sigma[b];
-                    if (L.blk_adm[b]) {
-                        if (V->rank[b] > 0) add_item(usrc[b], r0, false, tb_off[b]);
-                    } else {
-                        if (dsrc[b] < 0) dsrc[b] = dense_source(b);
-                        add_item(dsrc[b], r0, false, (int32_t)L.node_begin[s]);
-                    }
-                }
+                for (int32_t b : row_blocks[t])
+                    if (L.blk_adm[b] && V->rank[b] > 0) add_item(usrc[b], r0, false, tb_off[b], true);
             }
+            add_dense_items(rho, anc, dsrc);
             end_owner();
         }
         return true;
@@ -307,7 +422,7 @@ struct Builder {
                 const int32_t kr = V->row_rank[L.blk_tau[b]], kc = V->col_rank[L.blk_sigma[b]];
                 if (kr > 0 && kc > 0 && !V->coupling[b]) return check(false, "missing coupling");
             }
-        Phase& pf = new_phase("uh_fwd");
+        const int32_t pf = new_stage("uh_fwd");
         for (int32_t v = 0; v < N; ++v) {
             const int32_t kc = V->col_rank[v];
             if (kc == 0) continue;
@@ -316,11 +431,13 @@ struct Builder {
             add_item(xs, 0, true, (int32_t)L.node_begin[v]);
             end_owner();
         }
-        Phase& pc = new_phase("uh_coup");
+        for (int32_t v = 0; v < N; ++v)
+            if (V->row_rank[v] > 0) wsrc[v] = add_source(V->row_basis[v], L.size(v), V->row_rank[v], factor_dt, nullptr, 1);
+        const int32_t pc = new_stage("uh_coup");
         for (int32_t t = 0; t < N; ++t) {
             const int32_t kr = V->row_rank[t];
             if (kr == 0) continue;
-            begin_owner(pc, kr, 0, t_off[t], -1);
+            begin_owner(pc, kr, 0, t_off[t], src[wsrc[t]].scale_off);
             for (int32_t b : row_blocks[t]) {
                 if (!L.blk_adm[b]) continue;
                 const int32_t s = L.blk_sigma[b];
@@ -331,20 +448,13 @@ struct Builder {
             }
             end_owner();
         }
-        for (int32_t v = 0; v < N; ++v)
-            if (V->row_rank[v] > 0) wsrc[v] = add_source(V->row_basis[v], L.size(v), V->row_rank[v], factor_dt, nullptr, 1);
-        Phase& pr = new_phase("uh_rows");
+        const int32_t pr = new_stage("uh_rows");
         for (int32_t rho : leaves) {
             begin_owner(pr, (int32_t)L.size(rho), 1, (int32_t)L.node_begin[rho], -1);
-            for (int32_t t : ancestors_root_first(rho)) {
-                const int64_t r0 = L.node_begin[rho] - L.node_begin[t];
-                if (wsrc[t] >= 0) add_item(wsrc[t], r0, false, t_off[t]);
-                for (int32_t b : row_blocks[t]) {
-                    if (L.blk_adm[b]) continue;
-                    if (dsrc[b] < 0) dsrc[b] = dense_source(b);
-                    add_item(dsrc[b], r0, false, (int32_t)L.node_begin[L.blk_sigma[b]]);
-                }
-            }
+            const std::vector<int32_t> anc = ancestors_root_first(rho);
+            for (int32_t t : anc)
+                if (wsrc[t] >= 0) add_item(wsrc[t], L.node_begin[rho] - L.node_begin[t], false, t_off[t], true);
+            add_dense_items(rho, anc, dsrc);
             end_owner();
         }
         return true;
@@ -373,7 +483,7 @@ struct Builder {
             if (kc > 0) { s_off[v] = (int32_t)ws; ws += kc; }
             if (kr > 0) { t_off[v] = (int32_t)ws; ws += kr; }
         }
-        Phase& pl = new_phase("h2_up_leaf");
+        const int32_t pl = new_stage("h2_up_leaf");
         for (int32_t g : leaves) {
             const int32_t kc = V->col_rank[g];
             if (kc == 0) continue;
@@ -388,7 +498,7 @@ struct Builder {
             bool any = false;
             for (int32_t v : by_level[lv]) any |= (!L.leaf(v) && V->col_rank[v] > 0);
             if (!any) continue;
-            Phase& pu = new_phase("h2_up");
+            const int32_t pu = new_stage("h2_up");
             for (int32_t v : by_level[lv]) {
                 const int32_t kc = V->col_rank[v];
                 if (L.leaf(v) || kc == 0) continue;
@@ -403,15 +513,20 @@ struct Builder {
                 end_owner();
             }
         }
+        std::vector<int32_t> lsrc(N, -1);
+        for (int32_t rho : leaves)
+            if (V->row_rank[rho] > 0)
+                lsrc[rho] = add_source(V->row_basis[rho], L.size(rho), V->row_rank[rho], factor_dt, nullptr, 1);
         for (int32_t lv = 0; lv <= L.depth; ++lv) {
             bool any = false;
             for (int32_t v : by_level[lv]) any |= V->row_rank[v] > 0;
             if (!any) continue;
-            Phase& pd = new_phase("h2_down");
+            const int32_t pd = new_stage("h2_down");
             for (int32_t t : by_level[lv]) {
                 const int32_t kr = V->row_rank[t];
                 if (kr == 0) continue;
-                begin_owner(pd, kr, 0, t_off[t], -1);
+                // a leaf's coefficients feed only its own basis: fold its column scales
+                begin_owner(pd, kr, 0, t_off[t], lsrc[t] >= 0 ? src[lsrc[t]].scale_off : -1);
                 const int32_t p = L.node_parent[t];
                 if (p >= 0 && V->row_rank[p] > 0) {
                     int32_t es = add_source(V->row_transfer[t], kr, V->row_rank[p], coup_dt, nullptr, 3);
@@ -429,22 +544,12 @@ struct Builder {
                 end_owner();
             }
         }
-        Phase& pr = new_phase("h2_rows");
+        const int32_t pr = new_stage("h2_rows");
         for (int32_t rho : leaves) {
             begin_owner(pr, (int32_t)L.size(rho), 1, (int32_t)L.node_begin[rho], -1);
             const int32_t kr = V->row_rank[rho];
-            if (kr > 0) {
-                int32_t ws_ = add_source(V->row_basis[rho], L.size(rho), kr, factor_dt, nullptr, 1);
-                add_item(ws_, 0, false, t_off[rho]);
-            }
-            for (int32_t t : ancestors_root_first(rho)) {
-                const int64_t r0 = L.node_begin[rho] - L.node_begin[t];
-                for (int32_t b : row_blocks[t]) {
-                    if (L.blk_adm[b]) continue;
-                    if (dsrc[b] < 0) dsrc[b] = dense_source(b);
-                    add_item(dsrc[b], r0, false, (int32_t)L.node_begin[L.blk_sigma[b]]);
-                }
-            }
+            if (kr > 0) add_item(lsrc[rho], 0, false, t_off[rho], true);
+            add_dense_items(rho, ancestors_root_first(rho), dsrc);
             end_owner();
         }
         return true;
@@ -489,21 +594,21 @@ struct Builder {
                     for (int64_t j = 0; j < k; ++j)
                         scales[(size_t)(S.scale_off + j)] = c[(size_t)j] * (S.colfactor ? S.colfactor[j] : 1.0);
                 const int eb = dtype_bytes(S.dtype);
+                const int V = tile_cols(S.dtype);
+                // slab element (row a, column b) of an R-row slab, tiled
+                auto put = [&](uint8_t* dst, int64_t R, int64_t a, int64_t b, double v) {
+                    uint64_t bits = encode(S.dtype, v);
+                    std::memcpy(dst + (size_t)(((b / V) * R + a) * 16 + (b % V) * eb), &bits, (size_t)eb);
+                };
                 for (const Use& u : S.uses) {
                     uint8_t* dst = data.data() + u.data_off;
                     if (!u.transposed) {
                         for (int64_t j = 0; j < k; ++j)
-                            for (int64_t i = 0; i < u.nr; ++i) {
-                                uint64_t bits = encode(S.dtype, codes[(size_t)(u.r0 + i + j * m)]);
-                                std::memcpy(dst + (size_t)((i + j * u.nr) * eb), &bits, (size_t)eb);
-                            }
+                            for (int64_t i = 0; i < u.nr; ++i) put(dst, u.nr, i, j, codes[(size_t)(u.r0 + i + j * m)]);
                     } else {
-                        // slab = A^T (k x m), column stride k
+                        // slab = A^T (k rows, m columns)
                         for (int64_t i = 0; i < m; ++i)
-                            for (int64_t j = 0; j < k; ++j) {
-                                uint64_t bits = encode(S.dtype, codes[(size_t)(i + j * m)]);
-                                std::memcpy(dst + (size_t)((j + i * k) * eb), &bits, (size_t)eb);
-                            }
+                            for (int64_t j = 0; j < k; ++j) put(dst, k, j, i, codes[(size_t)(i + j * m)]);
                     }
                 }
             }
@@ -520,10 +625,14 @@ struct Builder {
         for (auto& t : th) t.join();
         for (size_t si = 0; si < src.size(); ++si)
             if (bad[si]) return check(false, "non-finite value in matrix data");
+        for (const Fold& f : folds)
+            for (int64_t j = 0; j < f.k; ++j)
+                scales[(size_t)(f.dst + j)] = (f.a >= 0 ? scales[(size_t)(f.a + j)] : 1.0) *
+                                              (f.b >= 0 ? scales[(size_t)(f.b + j)] : 1.0);
         for (const Source& S : src) {
             int64_t bytes = 0;
             for (const Use& u : S.uses)
-                bytes += (u.transposed ? S.m * S.k : u.nr * S.k) * dtype_bytes(S.dtype);
+                bytes += u.transposed ? tile_count(S.dtype, S.m) * S.k * 16 : tile_count(S.dtype, S.k) * u.nr * 16;
             per_dtype[S.dtype] += bytes;
             per_class[S.cls] += bytes;
         }
@@ -532,53 +641,108 @@ struct Builder {
 };
 
 // Every index a kernel will form from the tables must stay inside its
-// buffer; checked on the host before anything is uploaded.
+// buffer; checked on the host before anything is uploaded.  Also checks the
+// schedule: every owner's tasks are all placed, a split coefficient owner is
+// reduced in the stage of its tasks, and every split y owner in the last.
 bool validate(const Packed& P, int64_t n, std::string& why) {
     const int64_t nsc = (int64_t)P.scales.size();
     const int64_t nd = (int64_t)P.data.size();
-    for (const Phase& ph : P.phases) {
-        const int64_t no = (int64_t)ph.owners.size(), ni = (int64_t)ph.items.size();
-        for (int64_t o = 0; o < no; ++o) {
-            const DOwner& ow = ph.owners[o];
-            if (ow.nrows <= 0 || ow.nitems < 0 || ow.item0 < 0 || ow.item0 + ow.nitems > ni || ow.ntasks < 1) {
-                why = "owner table";
-                return false;
-            }
-            const int64_t lim = ow.mode == 0 ? P.ws_elems : n;
-            if (ow.out_off < 0 || ow.out_off + ow.nrows > lim) { why = "owner output range"; return false; }
-            if (ow.rscale_off >= 0 && ow.rscale_off + ow.nrows > nsc) { why = "row scales"; return false; }
-            if (ow.ntasks > 1 && (ow.part_off < 0 || ow.part_off + (int64_t)ow.ntasks * ow.nrows > P.part_elems)) {
-                why = "partial range";
-                return false;
-            }
-            int32_t col = 0;
-            for (int32_t i = 0; i < ow.nitems; ++i) {
-                const DItem& it = ph.items[ow.item0 + i];
-                const int eb = dtype_bytes(it.dtype);
-                if (eb == 0 || it.col0 != col || it.ncols <= 0) { why = "item columns"; return false; }
-                if (it.data_off < 0 || it.data_off + (int64_t)ow.nrows * it.ncols * eb > nd) { why = "item data"; return false; }
-                if (it.vec_off < 0 || it.vec_off + (int64_t)it.ncols > P.ws_elems) { why = "item input"; return false; }
-                if (it.scale_off >= 0 && it.scale_off + (int64_t)it.ncols > nsc) { why = "item scales"; return false; }
-                col += it.ncols;
-            }
+    const int64_t no = (int64_t)P.owners.size(), ni = (int64_t)P.items.size();
+    for (int64_t o = 0; o < no; ++o) {
+        const DOwner& ow = P.owners[o];
+        if (ow.nrows <= 0 || ow.nitems < 0 || ow.item0 < 0 || ow.item0 + ow.nitems > ni || ow.ntasks < 1) {
+            why = "owner table";
+            return false;
         }
-        std::vector<int32_t> seen(no, 0);
-        for (const DTask& t : ph.tasks) {
+        const int64_t lim = ow.mode == 0 ? P.ws_elems : n;
+        if (ow.out_off < 0 || ow.out_off + ow.nrows > lim) { why = "owner output range"; return false; }
+        if (ow.rscale_off >= 0 && ow.rscale_off + ow.nrows > nsc) { why = "row scales"; return false; }
+        if (ow.ntasks > 1 && (ow.part_off < 0 || ow.part_off + (int64_t)ow.ntasks * ow.nrows > P.part_elems)) {
+            why = "partial range";
+            return false;
+        }
+        int32_t col = 0, tile = 0;
+        for (int32_t i = 0; i < ow.nitems; ++i) {
+            const DItem& it = P.items[ow.item0 + i];
+            const int eb = dtype_bytes(it.dtype);
+            if (eb == 0 || it.col0 != col || it.ncols <= 0) { why = "item columns"; return false; }
+            if (it.tile0 != tile || it.data_off != P.items[ow.item0].data_off + (int64_t)tile * ow.nrows * 16) {
+                why = "owner stream not contiguous";
+                return false;
+            }
+            tile += (int32_t)tile_count(it.dtype, it.ncols);
+            const int64_t padded = tile_count(it.dtype, it.ncols) * (16 / eb);
+            if (it.data_off < 0 || (it.data_off & 15) || it.data_off + (int64_t)ow.nrows * 16 * (padded * eb / 16) > nd) {
+                why = "item data";
+                return false;
+            }
+            // the last tile's padding columns read inputs/scales past the item
+            // (multiplied by zero data); buffers carry TILE_PAD extra entries
+            if (it.vec_off < 0 || it.vec_off + padded > P.ws_elems + TILE_PAD) { why = "item input"; return false; }
+            if (it.scale_off >= 0 && it.scale_off + padded > nsc + TILE_PAD) { why = "item scales"; return false; }
+            col += it.ncols;
+        }
+    }
+    std::vector<int32_t> seen(no, 0), stage_of(no, -1), reduced(no, -1);
+    const int32_t ns = (int32_t)P.stages.size();
+    for (int32_t si = 0; si < ns; ++si) {
+        const Stage& st = P.stages[si];
+        if (st.t0 < 0 || st.t0 > st.t1 || st.t1 > (int64_t)P.tasks.size()) { why = "stage range"; return false; }
+        for (int64_t k = st.t0; k < st.t1; ++k) {
+            const DTask& t = P.tasks[k];
             if (t.owner < 0 || t.owner >= no) { why = "task owner"; return false; }
-            const DOwner& ow = ph.owners[t.owner];
+            const DOwner& ow = P.owners[t.owner];
+            if (t.nrows != ow.nrows || t.mode != ow.mode || t.out_off != ow.out_off || t.ntasks != ow.ntasks ||
+                t.part_off != ow.part_off || t.rscale_off != ow.rscale_off) {
+                why = "task copy of owner fields";
+                return false;
+            }
             int32_t ncols = 0;
-            if (ow.nitems) ncols = ph.items[ow.item0 + ow.nitems - 1].col0 + ph.items[ow.item0 + ow.nitems - 1].ncols;
-            if (t.c0 < 0 || t.c0 > t.c1 || t.c1 > ncols || t.local != seen[t.owner]++) { why = "task columns"; return false; }
+            if (ow.nitems) ncols = P.items[ow.item0 + ow.nitems - 1].col0 + P.items[ow.item0 + ow.nitems - 1].ncols;
+            if (t.c0 < 0 || t.c0 > t.c1 || t.c1 > ncols || t.local < 0 || t.local >= ow.ntasks) {
+                why = "task columns";
+                return false;
+            }
+            int32_t otiles = 0;
+            if (ow.nitems) {
+                const DItem& last = P.items[ow.item0 + ow.nitems - 1];
+                otiles = last.tile0 + (int32_t)tile_count(last.dtype, last.ncols);
+            }
+            if (t.k0 < 0 || t.k0 > t.k1 || t.k1 > otiles || (t.k0 < t.k1) != (t.c0 < t.c1) ||
+                (ow.nitems && t.stream != P.items[ow.item0].data_off)) {
+                why = "task tiles";
+                return false;
+            }
             if (t.c0 < t.c1) {
                 if (t.item_start < ow.item0 || t.item_start >= ow.item0 + ow.nitems) { why = "task item"; return false; }
-                const DItem& it = ph.items[t.item_start];
+                const DItem& fi = P.items[t.item_start];
+                if (t.k0 != fi.tile0 + (t.c0 - fi.col0) / (16 / dtype_bytes(fi.dtype))) { why = "task first tile"; return false; }
+                const DItem& it = P.items[t.item_start];
                 if (t.c0 < it.col0 || t.c0 >= it.col0 + it.ncols) { why = "task first item"; return false; }
+                if ((t.c0 - it.col0) % (16 / dtype_bytes(it.dtype))) { why = "task not tile aligned"; return false; }
+                // one dtype per task; narrow owners' inputs fit the LDS slice
+                for (int32_t j = t.item_start; j < ow.item0 + ow.nitems && P.items[j].col0 < t.c1; ++j)
+                    if (P.items[j].dtype != it.dtype) { why = "task mixes dtypes"; return false; }
+                if (ow.nrows <= 32 && (int64_t)(t.k1 - t.k0) * (16 / dtype_bytes(it.dtype)) > MAX_TASK_INPUTS) {
+                    why = "task inputs exceed LDS slice";
+                    return false;
+                }
+            }
+            ++seen[t.owner];
+            if (ow.mode == 0) {
+                if (stage_of[t.owner] >= 0 && stage_of[t.owner] != si) { why = "coefficient owner spans stages"; return false; }
+                stage_of[t.owner] = si;
             }
         }
-        for (int64_t o = 0; o < no; ++o)
-            if (seen[o] != ph.owners[o].ntasks) { why = "task count"; return false; }
-        for (int32_t r : ph.reduce_owners)
-            if (r < 0 || r >= no || ph.owners[r].ntasks < 2) { why = "reduce list"; return false; }
+        for (int32_t r : st.reduce) {
+            if (r < 0 || r >= no || P.owners[r].ntasks < 2 || reduced[r] >= 0) { why = "reduce list"; return false; }
+            reduced[r] = si;
+            if (P.owners[r].mode == 0 ? stage_of[r] != si : si != ns - 1) { why = "reduce placement"; return false; }
+        }
+    }
+    for (int64_t o = 0; o < no; ++o) {
+        if (seen[o] != P.owners[o].ntasks) { why = "task count"; return false; }
+        if (P.owners[o].ntasks > 1 && reduced[o] < 0) { why = "split owner never reduced"; return false; }
     }
     return true;
 }
@@ -638,9 +802,84 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
         out.acc64 = (p->eps < 1e-7 || all64) ? 1 : 0;
     out.format = format;
     out.ws_elems = B.ws;
-    out.part_elems = 0;
-    for (auto& ph : B.phases) out.part_elems = std::max(out.part_elems, ph.part_elems);
-    out.phases.assign(std::make_move_iterator(B.phases.begin()), std::make_move_iterator(B.phases.end()));
+    out.part_elems = B.part_elems;
+    // Water-fill the floating (dense) tasks into the stages, least-loaded
+    // stage first, so every launch carries independent work behind its
+    // dependent tasks; then lay the stages out as consecutive task ranges.
+    {
+        const int32_t ns = (int32_t)B.stage_tasks.size();
+        if (ns == 0) {
+            set_error("hm_upload: empty plan");
+            return HM_ELAYOUT;
+        }
+        std::vector<int64_t> load = B.stage_bytes;
+        int32_t dense_stage = -1;
+        if (opt.concurrent_dense && !B.floating.empty()) {
+            // the dense leaves read only x: one stage of their own, run on a
+            // second stream next to the chain of dependent stages
+            dense_stage = B.new_stage("dense");
+            for (auto& tb : B.floating) B.stage_tasks[dense_stage].push_back(tb.first);
+        } else {
+            for (auto& tb : B.floating) {
+                int32_t best = 0;
+                for (int32_t si = 1; si < ns; ++si)
+                    if (load[si] < load[best]) best = si;
+                B.stage_tasks[best].push_back(tb.first);
+                load[best] += tb.second;
+            }
+        }
+        const int32_t nst = (int32_t)B.stage_tasks.size();
+        out.owners = std::move(B.owners);
+        out.items = std::move(B.items);
+        out.tasks.clear();
+        out.stages.clear();
+        for (int32_t si = 0; si < nst; ++si) {
+            Stage st;
+            st.name = B.stage_names[si];
+            st.aux = si == dense_stage;
+            st.t0 = (int64_t)out.tasks.size();
+            out.tasks.insert(out.tasks.end(), B.stage_tasks[si].begin(), B.stage_tasks[si].end());
+            st.t1 = (int64_t)out.tasks.size();
+            out.stages.push_back(std::move(st));
+        }
+        // coefficient owners are reduced right after their stage, y owners at the end
+        Stage fin;
+        fin.name = "y_reduce";
+        fin.t0 = fin.t1 = (int64_t)out.tasks.size();
+        std::vector<int32_t> stage_of(out.owners.size(), -1);
+        for (int32_t si = 0; si < nst; ++si)
+            for (int64_t k = out.stages[si].t0; k < out.stages[si].t1; ++k) stage_of[out.tasks[k].owner] = si;
+        for (int32_t o = 0; o < (int32_t)out.owners.size(); ++o) {
+            if (out.owners[o].ntasks < 2) continue;
+            if (out.owners[o].mode == 0)
+                out.stages[stage_of[o]].reduce.push_back(o);
+            else
+                fin.reduce.push_back(o);
+        }
+        if (!fin.reduce.empty()) out.stages.push_back(std::move(fin));
+        for (auto& st : out.stages) {
+            for (int64_t k = st.t0; k < st.t1; ++k) {
+                const DTask& t = out.tasks[k];
+                const DOwner& ow = out.owners[t.owner];
+                // tiles of the task's column range
+                int32_t c = t.c0;
+                for (int32_t it = t.item_start; c < t.c1; ++it) {
+                    const DItem& item = out.items[it];
+                    const int V = tile_cols(item.dtype);
+                    const int32_t jb = c - item.col0, je = std::min(item.ncols, t.c1 - item.col0);
+                    st.data_bytes += (int64_t)((je + V - 1) / V - jb / V) * ow.nrows * 16;
+                    st.dtype_mask |= 1 << item.dtype;
+                    c = item.col0 + je;
+                }
+                st.alg_bytes += 8.0 * ow.nrows * (t.ntasks > 1 ? 1 : (ow.mode == 0 ? 2 : 3)) + sizeof(DTask);
+            }
+            for (int32_t o : st.reduce) {
+                const DOwner& ow = out.owners[o];
+                st.alg_bytes += 8.0 * ow.nrows * (ow.ntasks + (ow.mode == 0 ? 2 : 3));
+            }
+            st.alg_bytes += (double)st.data_bytes;
+        }
+    }
     hm_stats& s = out.stats;
     s = hm_stats{};
     s.n = L.n;
@@ -652,10 +891,9 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
     s.bytes_transfer = per_class[3];
     for (int d = 0; d < 5; ++d) s.bytes_per_dtype[d] = per_dtype[d];
     s.bytes_scales = (int64_t)out.scales.size() * 8;
-    int64_t meta = 0;
-    for (auto& ph : out.phases)
-        meta += (int64_t)(ph.owners.size() * sizeof(DOwner) + ph.items.size() * sizeof(DItem) +
-                          ph.tasks.size() * sizeof(DTask) + ph.reduce_owners.size() * 4);
+    int64_t meta = (int64_t)(out.owners.size() * sizeof(DOwner) + out.items.size() * sizeof(DItem) +
+                             out.tasks.size() * sizeof(DTask));
+    for (auto& st : out.stages) meta += (int64_t)st.reduce.size() * 4;
     s.bytes_meta = meta + L.n * 8;   // + permutation
     s.bytes_workspace = (out.ws_elems + out.part_elems) * 8;
     if (format == HM_FMT_H) {

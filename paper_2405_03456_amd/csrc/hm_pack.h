@@ -8,16 +8,20 @@ namespace hm {
 
 struct PackOptions {
     int64_t task_bytes = 32768;   // target matrix bytes per task (one wavefront)
+    bool concurrent_dense = true; // dense leaves as one independent stage (else spread over the stages)
 };
 
 struct Packed {
     int32_t format = 0;
     int32_t acc64 = 1;
-    std::vector<Phase> phases;
+    std::vector<DOwner> owners;
+    std::vector<DItem> items;
+    std::vector<DTask> tasks;      // stage after stage
+    std::vector<Stage> stages;
     std::vector<uint8_t> data;     // quantised matrix data, column-major slabs
     std::vector<double> scales;    // per-column / per-row scales
     int64_t ws_elems = 0;          // x in cluster order + coefficient vectors
-    int64_t part_elems = 0;        // partial-sum buffer (max over phases)
+    int64_t part_elems = 0;        // partial sums, one region per split owner
     hm_stats stats{};
 };
 

@@ -15,6 +15,7 @@
 #pragma once
 
 #include <cstdint>
+#include <string>
 #include <vector>
 
 namespace hm {
@@ -27,7 +28,7 @@ struct DItem {            // 32 bytes
     int32_t scale_off;    // index of column 0's scale, -1 = none
     int16_t dtype;
     int16_t acc64;        // accumulate in float64 even in float32 mode
-    int32_t pad;
+    int32_t tile0;        // first tile within the owner's tile stream
 };
 
 struct DOwner {           // 32 bytes
@@ -41,30 +42,43 @@ struct DOwner {           // 32 bytes
     int32_t rscale_off;   // per-row output scale, -1 = none
 };
 
-struct DTask {            // 32 bytes
-    int32_t owner;
+// The items of one owner are stored back to back and share its row count,
+// so the owner's data is one stream of tiles of nrows*16 bytes; a task is
+// the tile range [k0, k1) of that stream (columns [c0, c1)).
+struct DTask {            // 64 bytes; carries its owner's fields so a wave
+    int32_t owner;        // starts streaming after one descriptor load
     int32_t c0, c1;       // owner columns [c0, c1)
     int32_t item_start;   // absolute index of the item holding column c0
     int32_t local;        // task index within its owner
-    int32_t pad[3];
+    int32_t nrows, mode, out_off, ntasks, part_off, rscale_off;
+    int32_t k0, k1;       // owner tiles [k0, k1)
+    int32_t pad;
+    int64_t stream;       // byte offset of the owner's tile 0 in the data arena
 };
+
+// Input vectors and scale arrays carry this many trailing entries so that
+// the zero-padded columns of a last tile read in-bounds finite values.
+constexpr int64_t TILE_PAD = 16;
+
+// Owners with at most 32 rows stage a task's inputs in LDS; a task of such
+// an owner reads at most this many input values (tiles * columns per tile).
+constexpr int64_t MAX_TASK_INPUTS = 1024;
 
 static_assert(sizeof(DItem) == 32, "DItem layout");
 static_assert(sizeof(DOwner) == 32, "DOwner layout");
-static_assert(sizeof(DTask) == 32, "DTask layout");
+static_assert(sizeof(DTask) == 64, "DTask layout");
 
-struct Phase {
-    // host copies
-    std::vector<DOwner> owners;
-    std::vector<DItem> items;
-    std::vector<DTask> tasks;
-    std::vector<int32_t> reduce_owners;   // owners with ntasks > 1
-    int64_t part_elems = 0;
-    int32_t max_rows = 0;
-    int64_t data_bytes = 0;               // matrix bytes this phase streams
-    // device offsets (bytes) inside the metadata buffer
-    int64_t d_owners = 0, d_items = 0, d_tasks = 0, d_reduce = 0;
-    const char* name = "";
+// One kernel launch of the product: tasks [t0, t1) of the global task table
+// (all mutually independent), followed by the reduction of the split owners
+// in `reduce` (owners whose every task ran in this or an earlier stage).
+struct Stage {
+    std::string name;
+    int64_t t0 = 0, t1 = 0;
+    std::vector<int32_t> reduce;
+    int64_t data_bytes = 0;      // matrix bytes streamed by its tasks
+    double alg_bytes = 0;        // data + partial/output writes
+    int32_t dtype_mask = 0;      // dtypes of the items its tasks touch
+    bool aux = false;            // independent of the other stages: runs on a second stream
 };
 
 }  // namespace hm

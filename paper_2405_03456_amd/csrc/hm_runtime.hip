@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <array>
+#include <utility>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -44,128 +45,293 @@ __device__ __forceinline__ float fp8_to_f32(uint8_t b) {
     return (b & 0x80u) ? -mag : mag;
 }
 
-template <int DT> struct Elem;
-template <> struct Elem<HM_F64> { using T = double; __device__ static double f(T v) { return v; } };
-template <> struct Elem<HM_F32> { using T = float; __device__ static float f(T v) { return v; } };
-template <> struct Elem<HM_BF16> { using T = uint16_t; __device__ static float f(T v) { return bf16_to_f32(v); } };
-template <> struct Elem<HM_F16> { using T = uint16_t; __device__ static float f(T v) { return f16_to_f32(v); } };
-template <> struct Elem<HM_FP8E4M3> { using T = uint8_t; __device__ static float f(T v) { return fp8_to_f32(v); } };
-
-// Accumulate columns [jb, je) of one item for row rr.
-template <int DT, bool WIDE, bool SCALED>
-__device__ __forceinline__ void item_dot(const uint8_t* __restrict__ base, int nrows, int rr, int jb, int je,
-                                         const double* __restrict__ w, const double* __restrict__ sc,
-                                         double& a64, float& a32) {
-    using E = Elem<DT>;
-    using T = typename E::T;
-    const T* __restrict__ A = reinterpret_cast<const T*>(base) + rr;
-    int j = jb;
-    constexpr int U = 8;
-    for (; j + U <= je; j += U) {
-        T v[U];
+// A 16-byte tile row holds V = 16 / element-size consecutive columns of one
+// slab row.  decode<DT> widens the V stored values (float32 for the
+// narrow formats, float64 for FP64).
+template <int DT> struct Tile;
+template <> struct Tile<HM_F64> {
+    static constexpr int V = 2;
+    using R = double;
+    __device__ static void decode(const uint4& q, R* o) {
+        o[0] = __hiloint2double((int)q.y, (int)q.x);
+        o[1] = __hiloint2double((int)q.w, (int)q.z);
+    }
+};
+template <> struct Tile<HM_F32> {
+    static constexpr int V = 4;
+    using R = float;
+    __device__ static void decode(const uint4& q, R* o) {
+        o[0] = __uint_as_float(q.x);
+        o[1] = __uint_as_float(q.y);
+        o[2] = __uint_as_float(q.z);
+        o[3] = __uint_as_float(q.w);
+    }
+};
+template <> struct Tile<HM_BF16> {
+    static constexpr int V = 8;
+    using R = float;
+    __device__ static void decode(const uint4& q, R* o) {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = A[(int64_t)(j + u) * nrows];
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = __uint_as_float(w[i] << 16);
+            o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        }
+    }
+};
+template <> struct Tile<HM_F16> {
+    static constexpr int V = 8;
+    using R = float;
+    __device__ static void decode(const uint4& q, R* o) {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = f16_to_f32((uint16_t)(w[i] & 0xffffu));
+            o[2 * i + 1] = f16_to_f32((uint16_t)(w[i] >> 16));
+        }
+    }
+};
+template <> struct Tile<HM_FP8E4M3> {
+    static constexpr int V = 16;
+    using R = float;
+    __device__ static void decode(const uint4& q, R* o) {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) o[4 * i + b] = fp8_to_f32((uint8_t)(w[i] >> (8 * b)));
+    }
+};
+
+// Accumulate one tile row.  WIDE: float64 accumulator with float64 inputs
+// w; otherwise float32 accumulator with the float32 mirror of the inputs.
+template <int DT, bool WIDE, bool SCALED, typename WT>
+__device__ __forceinline__ void tile_acc(const uint4& q, const WT* __restrict__ w, const double* __restrict__ sc,
+                                         double& a64, float& a32) {
+    using TT = Tile<DT>;
+    typename TT::R v[TT::V];
+    TT::decode(q, v);
+#pragma unroll
+    for (int i = 0; i < TT::V; ++i) {
+        if (WIDE) {
+            double wi = (double)w[i];
+            if (SCALED) wi *= sc[i];
+            a64 = fma((double)v[i], wi, a64);
+        } else {
+            float wi = (float)w[i];
+            if (SCALED) wi *= (float)sc[i];
+            a32 = fmaf((float)v[i], wi, a32);
+        }
+    }
+}
+
+// Where the current item sits in the owner's tile stream.
+struct ItemPos {
+    int it, k0, k1, vec, sc;
+};
+
+template <int DT>
+__device__ __forceinline__ ItemPos item_pos(const DItem* __restrict__ items, int it) {
+    const DItem d = items[it];
+    constexpr int V = Tile<DT>::V;
+    return ItemPos{it, d.tile0, d.tile0 + (d.ncols + V - 1) / V, d.vec_off, d.scale_off};
+}
+
+__device__ __forceinline__ void finalize(int mode, int out_off, int r, double v, double* __restrict__ vout,
+                                         float* __restrict__ vout32, double* __restrict__ y,
+                                         const int64_t* __restrict__ perm, double alpha) {
+    if (mode == 0) {
+        vout[out_off + r] = v;
+        vout32[out_off + r] = (float)v;
+    } else if (mode == 1) {
+        y[perm ? perm[out_off + r] : (int64_t)(out_off + r)] += alpha * v;
+    } else {
+        y[out_off + r] += alpha * v;
+    }
+}
+
+// Accumulate one tile row with inputs already in registers/LDS (grouped path).
+template <int DT, bool WIDE>
+__device__ __forceinline__ void tile_acc_w(const uint4& q, const double* wv, double& a64, float& a32) {
+    using TT = Tile<DT>;
+    typename TT::R v[TT::V];
+    TT::decode(q, v);
+#pragma unroll
+    for (int i = 0; i < TT::V; ++i) {
+        if (WIDE)
+            a64 = fma((double)v[i], wv[i], a64);
+        else
+            a32 = fmaf((float)v[i], (float)wv[i], a32);
+    }
+}
+
+// Wide owners (more than 32 rows): the wave walks the task's tiles together,
+// a prefetched batch of U tiles always in flight; item bookkeeping is
+// uniform and the inputs are scalar loads (lgkmcnt), so waiting for them
+// never drains the data prefetch (vmcnt).
+template <int DT, bool WIDE>
+__device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __restrict__ items,
+                                               const uint8_t* __restrict__ sb, int64_t rt,
+                                               const double* __restrict__ vin, const float* __restrict__ vin32,
+                                               const double* __restrict__ scales, double& a64, float& a32) {
+    constexpr int V = Tile<DT>::V;
+    constexpr int U = Tile<DT>::V <= 4 ? 8 : 4;
+    const int k0 = tk.k0, k1 = tk.k1;
+    ItemPos st = item_pos<DT>(items, tk.item_start);
+    uint4 qa[U], qb[U];
+    auto issue = [&](uint4* q, int kb) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = *reinterpret_cast<const uint4*>(sb + (int64_t)min(kb + u, k1 - 1) * rt);
+    };
+    auto consume = [&](const uint4* q, int kb) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            double wj = w[j + u];
-            if (SCALED) wj *= sc[j + u];
-            if (WIDE)
-                a64 = fma((double)E::f(v[u]), wj, a64);
-            else
-                a32 = fmaf((float)E::f(v[u]), (float)wj, a32);
+            const int kk = kb + u;
+            if (kk < k1) {
+                while (kk >= st.k1) st = item_pos<DT>(items, st.it + 1);
+                const int c = (kk - st.k0) * V;
+                if (WIDE) {
+                    if (st.sc >= 0)
+                        tile_acc<DT, true, true>(q[u], vin + st.vec + c, scales + st.sc + c, a64, a32);
+                    else
+                        tile_acc<DT, true, false>(q[u], vin + st.vec + c, scales, a64, a32);
+                } else {
+                    if (st.sc >= 0)
+                        tile_acc<DT, false, true>(q[u], vin32 + st.vec + c, scales + st.sc + c, a64, a32);
+                    else
+                        tile_acc<DT, false, false>(q[u], vin32 + st.vec + c, scales, a64, a32);
+                }
+            }
         }
-    }
-    for (; j < je; ++j) {
-        T v = A[(int64_t)j * nrows];
-        double wj = w[j];
-        if (SCALED) wj *= sc[j];
-        if (WIDE)
-            a64 = fma((double)E::f(v), wj, a64);
-        else
-            a32 = fmaf((float)E::f(v), (float)wj, a32);
+    };
+    issue(qa, k0);
+    for (int k = k0; k < k1; k += 2 * U) {
+        issue(qb, k + U);
+        __builtin_amdgcn_sched_barrier(0);
+        consume(qa, k);
+        issue(qa, k + 2 * U);
+        __builtin_amdgcn_sched_barrier(0);
+        consume(qb, k + U);
     }
 }
 
+// Narrow owners (at most 32 rows): G = 64/P lane groups take tiles
+// k0+g, k0+g+G, ...  The task's inputs (times their column scales) are first
+// staged in this wave's LDS slice in tile order, so each lane reads its
+// group's inputs from LDS and the data prefetch is never drained.
 template <int DT, bool WIDE>
-__device__ __forceinline__ void item_dispatch_scale(const uint8_t* base, int nrows, int rr, int jb, int je,
-                                                    const double* w, const double* sc, double& a64, float& a32) {
-    if (sc)
-        item_dot<DT, WIDE, true>(base, nrows, rr, jb, je, w, sc, a64, a32);
-    else
-        item_dot<DT, WIDE, false>(base, nrows, rr, jb, je, w, sc, a64, a32);
+__device__ __forceinline__ void stream_grouped(const DTask& tk, const DItem* __restrict__ items,
+                                               const uint8_t* __restrict__ sb, int64_t rt, int g, int G, int lane,
+                                               const double* __restrict__ vin, const double* __restrict__ scales,
+                                               double* __restrict__ lw, double& a64, float& a32) {
+    constexpr int V = Tile<DT>::V;
+    constexpr int U = 4;
+    const int k0 = tk.k0, k1 = tk.k1;
+    // stage: lw[(t - k0) * V + i] = input of column i of tile t (zero past an
+    // item's last column is not needed: its data is zero)
+    {
+        const int nval = (k1 - k0) * V;
+        ItemPos st = item_pos<DT>(items, tk.item_start);
+        for (int idx = lane; idx < nval; idx += 64) {
+            const int t = k0 + idx / V;
+            while (t >= st.k1) st = item_pos<DT>(items, st.it + 1);
+            const int c = (t - st.k0) * V + idx % V;
+            double v = vin[st.vec + c];
+            if (st.sc >= 0) v *= scales[st.sc + c];
+            lw[idx] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    const int step = U * G;
+    uint4 qa[U], qb[U];
+    auto issue = [&](uint4* q, int kb) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            q[u] = *reinterpret_cast<const uint4*>(sb + (int64_t)min(kb + u * G + g, k1 - 1) * rt);
+    };
+    auto consume = [&](const uint4* q, int kb) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kk = kb + u * G + g;
+            if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw + (kk - k0) * V, a64, a32);
+        }
+    };
+    issue(qa, k0);
+    for (int k = k0; k < k1; k += 2 * step) {
+        issue(qb, k + step);
+        __builtin_amdgcn_sched_barrier(0);
+        consume(qa, k);
+        issue(qa, k + 2 * step);
+        __builtin_amdgcn_sched_barrier(0);
+        consume(qb, k + step);
+    }
 }
 
-__device__ __forceinline__ void finalize(const DOwner& ow, int r, double v, double* __restrict__ vout,
-                                         double* __restrict__ y, const int64_t* __restrict__ perm, double alpha) {
-    if (ow.mode == 0)
-        vout[ow.out_off + r] = v;
-    else if (ow.mode == 1)
-        y[perm ? perm[ow.out_off + r] : (int64_t)(ow.out_off + r)] += alpha * v;
+template <int DT, bool ACC64>
+__device__ __forceinline__ void stream_task(const DTask& tk, const DItem* items, const uint8_t* sb, int64_t rt,
+                                            int g, int G, int lane, const double* vin, const float* vin32,
+                                            const double* scales, double* lw, double& a64, float& a32) {
+    constexpr bool WIDE = ACC64 || DT == HM_F64;
+    if (G == 1)
+        stream_uniform<DT, WIDE>(tk, items, sb, rt, vin, vin32, scales, a64, a32);
     else
-        y[ow.out_off + r] += alpha * v;
+        stream_grouped<DT, WIDE>(tk, items, sb, rt, g, G, lane, vin, scales, lw, a64, a32);
 }
 
-template <bool ACC64>
-__global__ __launch_bounds__(256) void k_owner_tasks(const DTask* __restrict__ tasks, int ntasks,
-                                                     const DOwner* __restrict__ owners,
-                                                     const DItem* __restrict__ items,
-                                                     const uint8_t* __restrict__ data,
-                                                     const double* __restrict__ scales,
-                                                     const double* __restrict__ vin, double* vout,
-                                                     double* __restrict__ part, double* __restrict__ y,
-                                                     const int64_t* __restrict__ perm, double alpha) {
+// One wavefront per task.  Lane geometry: P = rows per group (next power of
+// two >= nrows, at most 64), G = 64 / P column groups.  Tasks hold one dtype.
+// MASK: bit d set = tasks of dtype d may occur in the launched stage; the
+// host launches the instantiation whose mask is the stage's dtype set.
+template <bool ACC64, int MASK>
+__global__ __launch_bounds__(256) void k_owner_tasks(
+    const DTask* __restrict__ tasks, int ntasks, const DOwner* __restrict__ owners,
+    const DItem* __restrict__ items, const uint8_t* __restrict__ data, const double* __restrict__ scales,
+    const double* __restrict__ vin, const float* __restrict__ vin32, double* vout, float* vout32,
+    double* __restrict__ part, double* __restrict__ y, const int64_t* __restrict__ perm, double alpha) {
+    __shared__ double lds_w[4][MAX_TASK_INPUTS];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int t = blockIdx.x * 4 + wave;
     if (t >= ntasks) return;
     const DTask tk = tasks[t];
-    const DOwner ow = owners[tk.owner];
-    for (int r0 = 0; r0 < ow.nrows; r0 += 64) {
-        const int r = r0 + lane;
-        const bool act = r < ow.nrows;
-        const int rr = act ? r : ow.nrows - 1;   // inactive lanes re-read a valid row
+    const int nrows = tk.nrows;
+    int lp = 0;                         // log2 P
+    while ((1 << lp) < nrows && lp < 6) ++lp;
+    const int P = 1 << lp;
+    const int G = 64 >> lp;
+    const int g = lane >> lp;
+    const int rl = lane & (P - 1);
+    const int dt = tk.k0 < tk.k1 ? (int)items[tk.item_start].dtype : -1;
+    for (int r0 = 0; r0 < nrows; r0 += P) {
+        const int r = r0 + rl;
+        const bool act = r < nrows;
+        const int rr = act ? r : nrows - 1;   // idle lanes re-read a valid row
         double a64 = 0.0;
         float a32 = 0.0f;
-        int it = tk.item_start;
-        int c = tk.c0;
-        while (c < tk.c1) {
-            const DItem item = items[it];
-            const int jb = c - item.col0;
-            const int je = min(item.ncols, tk.c1 - item.col0);
-            const uint8_t* base = data + item.data_off;
-            const double* w = vin + item.vec_off;
-            const double* sc = item.scale_off >= 0 ? scales + item.scale_off : nullptr;
-            const bool wide = ACC64 || item.acc64;
-            switch (item.dtype) {
-                case HM_F64:
-                    item_dispatch_scale<HM_F64, true>(base, ow.nrows, rr, jb, je, w, sc, a64, a32);
-                    break;
-                case HM_F32:
-                    if (wide) item_dispatch_scale<HM_F32, true>(base, ow.nrows, rr, jb, je, w, sc, a64, a32);
-                    else item_dispatch_scale<HM_F32, false>(base, ow.nrows, rr, jb, je, w, sc, a64, a32);
-                    break;
-                case HM_BF16:
-                    if (wide) item_dispatch_scale<HM_BF16, true>(base, ow.nrows, rr, jb, je, w, sc, a64, a32);
-                    else item_dispatch_scale<HM_BF16, false>(base, ow.nrows, rr, jb, je, w, sc, a64, a32);
-                    break;
-                case HM_F16:
-                    if (wide) item_dispatch_scale<HM_F16, true>(base, ow.nrows, rr, jb, je, w, sc, a64, a32);
-                    else item_dispatch_scale<HM_F16, false>(base, ow.nrows, rr, jb, je, w, sc, a64, a32);
-                    break;
-                default:
-                    if (wide) item_dispatch_scale<HM_FP8E4M3, true>(base, ow.nrows, rr, jb, je, w, sc, a64, a32);
-                    else item_dispatch_scale<HM_FP8E4M3, false>(base, ow.nrows, rr, jb, je, w, sc, a64, a32);
-                    break;
-            }
-            c = item.col0 + je;
-            ++it;
-        }
+        const int64_t rt = (int64_t)nrows * 16;
+        const uint8_t* sb = data + tk.stream + (uint32_t)(rr * 16);
+        double* lw = lds_w[wave];
+        if constexpr ((MASK & (1 << HM_F64)) != 0)
+            if (dt == HM_F64) stream_task<HM_F64, ACC64>(tk, items, sb, rt, g, G, lane, vin, vin32, scales, lw, a64, a32);
+        if constexpr ((MASK & (1 << HM_F32)) != 0)
+            if (dt == HM_F32) stream_task<HM_F32, ACC64>(tk, items, sb, rt, g, G, lane, vin, vin32, scales, lw, a64, a32);
+        if constexpr ((MASK & (1 << HM_BF16)) != 0)
+            if (dt == HM_BF16) stream_task<HM_BF16, ACC64>(tk, items, sb, rt, g, G, lane, vin, vin32, scales, lw, a64, a32);
+        if constexpr ((MASK & (1 << HM_F16)) != 0)
+            if (dt == HM_F16) stream_task<HM_F16, ACC64>(tk, items, sb, rt, g, G, lane, vin, vin32, scales, lw, a64, a32);
+        if constexpr ((MASK & (1 << HM_FP8E4M3)) != 0)
+            if (dt == HM_FP8E4M3)
+                stream_task<HM_FP8E4M3, ACC64>(tk, items, sb, rt, g, G, lane, vin, vin32, scales, lw, a64, a32);
         double v = a64 + (double)a32;
-        if (act) {
-            if (ow.rscale_off >= 0) v *= scales[ow.rscale_off + r];
-            if (ow.ntasks == 1)
-                finalize(ow, r, v, vout, y, perm, alpha);
+        for (int off = P; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);   // across column groups
+        if (act && g == 0) {
+            if (tk.rscale_off >= 0) v *= scales[tk.rscale_off + r];
+            if (tk.ntasks == 1)
+                finalize(tk.mode, tk.out_off, r, v, vout, vout32, y, perm, alpha);
             else
-                part[ow.part_off + (int64_t)tk.local * ow.nrows + r] = v;
+                part[tk.part_off + (int64_t)tk.local * nrows + r] = v;
         }
     }
 }
@@ -173,7 +339,7 @@ __global__ __launch_bounds__(256) void k_owner_tasks(const DTask* __restrict__ t
 // Sum the partial results of split owners in task order, one wave per owner.
 __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list, int nlist,
                                                 const DOwner* __restrict__ owners,
-                                                const double* __restrict__ part, double* vout,
+                                                const double* __restrict__ part, double* vout, float* vout32,
                                                 double* __restrict__ y, const int64_t* __restrict__ perm,
                                                 double alpha) {
     const int lane = threadIdx.x & 63;
@@ -184,27 +350,47 @@ __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list
         const double* p = part + ow.part_off + r;
         double v = 0.0;
         for (int l = 0; l < ow.ntasks; ++l) v += p[(int64_t)l * ow.nrows];
-        finalize(ow, r, v, vout, y, perm, alpha);
+        finalize(ow.mode, ow.out_off, r, v, vout, vout32, y, perm, alpha);
     }
 }
 
 // x in cluster order: ws[i] = x[perm[i]]  (or a straight copy)
 __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ x, const int64_t* __restrict__ perm,
-                                                double* __restrict__ ws, int64_t n, int cluster_order) {
+                                                double* __restrict__ ws, float* __restrict__ ws32, int64_t n,
+                                                int cluster_order) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) ws[i] = cluster_order ? x[i] : x[perm[i]];
+    if (i < n) {
+        const double v = cluster_order ? x[i] : x[perm[i]];
+        ws[i] = v;
+        ws32[i] = (float)v;
+    }
 }
+
+using TaskKernel = void (*)(const DTask*, int, const DOwner*, const DItem*, const uint8_t*, const double*,
+                           const double*, const float*, double*, float*, double*, double*, const int64_t*,
+                           double);
+
+template <bool ACC64, int... M>
+constexpr std::array<TaskKernel, sizeof...(M)> task_kernels(std::integer_sequence<int, M...>) {
+    return {{&k_owner_tasks<ACC64, M>...}};
+}
+
+// [acc64][dtype mask]
+static const std::array<TaskKernel, 32> kTasks[2] = {task_kernels<false>(std::make_integer_sequence<int, 32>{}),
+                                                      task_kernels<true>(std::make_integer_sequence<int, 32>{})};
 
 }  // namespace dev
 
-struct DevPhase {
-    const DOwner* owners;
-    const DItem* items;
-    const DTask* tasks;
+struct DevStage {
+    bool aux;
+    int64_t t0;
+    int32_t ntasks, nreduce, nowners;
     const int32_t* reduce;
-    int32_t ntasks, nreduce;
+    int32_t dtype_mask;
     int64_t data_bytes;
+    double alg_bytes;
     std::string name;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;   // HM_TIMING event pairs
 };
 
 }  // namespace hm
@@ -221,8 +407,16 @@ struct hm_matrix {
     uint8_t* data = nullptr;
     double* scales = nullptr;
     double* ws = nullptr;
+    float* ws32 = nullptr;
     double* part = nullptr;
-    std::vector<hm::DevPhase> phases;
+    const hm::DOwner* owners = nullptr;
+    const hm::DItem* items = nullptr;
+    const hm::DTask* tasks = nullptr;
+    std::vector<hm::DevStage> phases;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+    // second stream for the independent dense stage, with fork/join events
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hm_stats stats{};
 };
 
@@ -262,21 +456,26 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
 
     // one device allocation: metadata | perm | data | scales | workspace | partials
     size_t meta = 0;
-    std::vector<std::array<size_t, 4>> offs;
-    for (auto& ph : P.phases) {
-        std::array<size_t, 4> o;
-        o[0] = meta; meta = align256(meta + ph.owners.size() * sizeof(hm::DOwner));
-        o[1] = meta; meta = align256(meta + ph.items.size() * sizeof(hm::DItem));
-        o[2] = meta; meta = align256(meta + ph.tasks.size() * sizeof(hm::DTask));
-        o[3] = meta; meta = align256(meta + ph.reduce_owners.size() * sizeof(int32_t));
-        offs.push_back(o);
+    const size_t o_owners = meta;
+    meta = align256(meta + P.owners.size() * sizeof(hm::DOwner));
+    const size_t o_items = meta;
+    meta = align256(meta + P.items.size() * sizeof(hm::DItem));
+    const size_t o_tasks = meta;
+    meta = align256(meta + P.tasks.size() * sizeof(hm::DTask));
+    std::vector<size_t> o_red;
+    for (auto& st : P.stages) {
+        o_red.push_back(meta);
+        meta = align256(meta + st.reduce.size() * sizeof(int32_t));
     }
     const int64_t n = layout->L.n;
     size_t o_perm = meta;
     size_t o_data = align256(o_perm + n * sizeof(int64_t));
+    // scales and workspace carry TILE_PAD trailing entries (see hm_plan.h)
+    P.scales.resize(P.scales.size() + hm::TILE_PAD, 0.0);
     size_t o_scales = align256(o_data + P.data.size());
     size_t o_ws = align256(o_scales + P.scales.size() * sizeof(double));
-    size_t o_part = align256(o_ws + P.ws_elems * sizeof(double));
+    size_t o_ws32 = align256(o_ws + (P.ws_elems + hm::TILE_PAD) * sizeof(double));
+    size_t o_part = align256(o_ws32 + (P.ws_elems + hm::TILE_PAD) * sizeof(float));
     size_t total = align256(o_part + std::max<int64_t>(P.part_elems, 1) * sizeof(double));
 
     hm_matrix* m = new (std::nothrow) hm_matrix();
@@ -300,18 +499,20 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         if (!bytes) return hipSuccess;
         return hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice);
     };
-    for (size_t i = 0; i < P.phases.size() && e == hipSuccess; ++i) {
-        auto& ph = P.phases[i];
-        e = copy(offs[i][0], ph.owners.data(), ph.owners.size() * sizeof(hm::DOwner));
-        if (e == hipSuccess) e = copy(offs[i][1], ph.items.data(), ph.items.size() * sizeof(hm::DItem));
-        if (e == hipSuccess) e = copy(offs[i][2], ph.tasks.data(), ph.tasks.size() * sizeof(hm::DTask));
-        if (e == hipSuccess) e = copy(offs[i][3], ph.reduce_owners.data(), ph.reduce_owners.size() * sizeof(int32_t));
-    }
+    e = copy(o_owners, P.owners.data(), P.owners.size() * sizeof(hm::DOwner));
+    if (e == hipSuccess) e = copy(o_items, P.items.data(), P.items.size() * sizeof(hm::DItem));
+    if (e == hipSuccess) e = copy(o_tasks, P.tasks.data(), P.tasks.size() * sizeof(hm::DTask));
+    for (size_t i = 0; i < P.stages.size() && e == hipSuccess; ++i)
+        e = copy(o_red[i], P.stages[i].reduce.data(), P.stages[i].reduce.size() * sizeof(int32_t));
     if (e == hipSuccess) e = copy(o_perm, layout->L.perm.data(), n * sizeof(int64_t));
     if (e == hipSuccess) e = copy(o_data, P.data.data(), P.data.size());
     if (e == hipSuccess) e = copy(o_scales, P.scales.data(), P.scales.size() * sizeof(double));
+    // every workspace entry must hold a finite value before the first product:
+    // zero-data padding columns multiply whatever they read
+    if (e == hipSuccess) e = hipMemset(base + o_ws, 0, (P.ws_elems + hm::TILE_PAD) * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(base + o_ws32, 0, (P.ws_elems + hm::TILE_PAD) * sizeof(float));
     if (e != hipSuccess) {
-        hipFree(m->arena);
+        (void)hipFree(m->arena);
         delete m;
         return hip_fail("hm_upload: hipMemcpy", e);
     }
@@ -324,21 +525,38 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     m->data = base + o_data;
     m->scales = (double*)(base + o_scales);
     m->ws = (double*)(base + o_ws);
+    m->ws32 = (float*)(base + o_ws32);
     m->part = (double*)(base + o_part);
+    m->owners = (const hm::DOwner*)(base + o_owners);
+    m->items = (const hm::DItem*)(base + o_items);
+    m->tasks = (const hm::DTask*)(base + o_tasks);
     int32_t nlaunch = 1;
-    for (size_t i = 0; i < P.phases.size(); ++i) {
-        auto& ph = P.phases[i];
-        hm::DevPhase d;
-        d.owners = (const hm::DOwner*)(base + offs[i][0]);
-        d.items = (const hm::DItem*)(base + offs[i][1]);
-        d.tasks = (const hm::DTask*)(base + offs[i][2]);
-        d.reduce = (const int32_t*)(base + offs[i][3]);
-        d.ntasks = (int32_t)ph.tasks.size();
-        d.nreduce = (int32_t)ph.reduce_owners.size();
-        d.data_bytes = ph.data_bytes;
-        d.name = ph.name;
-        nlaunch += 1 + (d.nreduce > 0);
+    for (size_t i = 0; i < P.stages.size(); ++i) {
+        auto& st = P.stages[i];
+        hm::DevStage d;
+        d.aux = st.aux;
+        d.t0 = st.t0;
+        d.ntasks = (int32_t)(st.t1 - st.t0);
+        d.reduce = (const int32_t*)(base + o_red[i]);
+        d.nreduce = (int32_t)st.reduce.size();
+        d.nowners = 0;
+        d.dtype_mask = st.dtype_mask;
+        d.data_bytes = st.data_bytes;
+        d.alg_bytes = st.alg_bytes;
+        d.name = st.name;
+        nlaunch += (d.ntasks > 0) + (d.nreduce > 0);
         m->phases.push_back(d);
+    }
+    bool any_aux = false;
+    for (auto& d : m->phases) any_aux |= d.aux;
+    if (any_aux) {
+        e = hipStreamCreateWithFlags(&m->aux, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            hm_matrix_free(m);
+            return hip_fail("hm_upload: stream/event creation", e);
+        }
     }
     m->stats = P.stats;
     m->stats.nlaunch = nlaunch;
@@ -352,7 +570,16 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
 
 extern "C" void hm_matrix_free(hm_matrix* m) {
     if (!m) return;
-    if (m->arena) hipFree(m->arena);
+    for (auto& ph : m->phases)
+        for (auto& e : ph.pending) m->event_pool.push_back(e);
+    for (auto& e : m->event_pool) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+    if (m->ev_join) (void)hipEventDestroy(m->ev_join);
+    if (m->aux) (void)hipStreamDestroy(m->aux);
+    if (m->arena) (void)hipFree(m->arena);
     delete m;
 }
 
@@ -380,25 +607,157 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
     const int cluster = (flags & HM_CLUSTER_ORDER) ? 1 : 0;
     const int64_t n = m->n;
     hipLaunchKernelGGL(hm::dev::k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, x, m->perm,
-                       m->ws, n, cluster);
+                       m->ws, m->ws32, n, cluster);
     const int64_t* perm = cluster ? nullptr : m->perm;
-    for (const auto& ph : m->phases) {
+    const bool timing = (flags & HM_TIMING) != 0;
+    const hipStream_t main_stream = stream;
+    if (m->aux) {
+        // fork: the dense stage runs on the second stream after x is gathered
+        (void)hipEventRecord(m->ev_fork, main_stream);
+        (void)hipStreamWaitEvent(m->aux, m->ev_fork, 0);
+    }
+    bool joined = m->aux == nullptr;
+    for (auto& ph : m->phases) {
+        stream = ph.aux ? m->aux : main_stream;
+        if (!joined && !ph.aux && ph.ntasks == 0 && &ph == &m->phases.back()) {
+            // join before the final reduction of the row owners
+            (void)hipEventRecord(m->ev_join, m->aux);
+            (void)hipStreamWaitEvent(main_stream, m->ev_join, 0);
+            joined = true;
+        }
         if (ph.ntasks > 0) {
             dim3 grid((unsigned)((ph.ntasks + 3) / 4));
-            if (m->acc64)
-                hipLaunchKernelGGL(hm::dev::k_owner_tasks<true>, grid, dim3(256), 0, stream, ph.tasks, ph.ntasks,
-                                   ph.owners, ph.items, m->data, m->scales, m->ws, m->ws, m->part, y, perm, alpha);
-            else
-                hipLaunchKernelGGL(hm::dev::k_owner_tasks<false>, grid, dim3(256), 0, stream, ph.tasks, ph.ntasks,
-                                   ph.owners, ph.items, m->data, m->scales, m->ws, m->ws, m->part, y, perm, alpha);
+            std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+            if (timing) {
+                if (m->event_pool.empty()) {
+                    if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+                        hm::set_error("hm_mvm: hipEventCreate failed");
+                        return HM_EDEVICE;
+                    }
+                } else {
+                    ev = m->event_pool.back();
+                    m->event_pool.pop_back();
+                }
+                (void)hipEventRecord(ev.first, stream);
+            }
+            hipLaunchKernelGGL(hm::dev::kTasks[m->acc64 ? 1 : 0][ph.dtype_mask & 31], grid, dim3(256), 0, stream,
+                               m->tasks + ph.t0, ph.ntasks, m->owners, m->items, m->data, m->scales, m->ws, m->ws32,
+                               m->ws, m->ws32, m->part, y, perm, alpha);
+            if (timing) {
+                (void)hipEventRecord(ev.second, stream);
+                ph.pending.push_back(ev);
+            }
         }
         if (ph.nreduce > 0) {
             dim3 grid((unsigned)((ph.nreduce + 3) / 4));
-            hipLaunchKernelGGL(hm::dev::k_reduce, grid, dim3(256), 0, stream, ph.reduce, ph.nreduce, ph.owners,
-                               m->part, m->ws, y, perm, alpha);
+            hipLaunchKernelGGL(hm::dev::k_reduce, grid, dim3(256), 0, stream, ph.reduce, ph.nreduce, m->owners,
+                               m->part, m->ws, m->ws32, y, perm, alpha);
         }
+    }
+    if (!joined) {   // no final reduction stage: still join the second stream
+        (void)hipEventRecord(m->ev_join, m->aux);
+        (void)hipStreamWaitEvent(main_stream, m->ev_join, 0);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail("hm_mvm: kernel launch", e);
     return HM_OK;
+}
+
+extern "C" hm_status hm_timing_read(hm_matrix* m, hm_phase_timing* out, int32_t cap, int32_t* nphase) {
+    if (!m || (cap > 0 && !out)) {
+        hm::set_error("hm_timing_read: null argument");
+        return HM_EINVAL;
+    }
+    int32_t i = 0;
+    for (auto& ph : m->phases) {
+        double ms = 0.0;
+        int64_t cnt = 0;
+        for (auto& e : ph.pending) {
+            hipError_t err = hipEventSynchronize(e.second);
+            float t = 0.0f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&t, e.first, e.second);
+            if (err != hipSuccess) return hip_fail("hm_timing_read", err);
+            ms += t;
+            ++cnt;
+            m->event_pool.push_back(e);
+        }
+        ph.pending.clear();
+        if (i < cap) {
+            out[i].name = ph.name.c_str();
+            out[i].ms_total = ms;
+            out[i].launches = cnt;
+            out[i].algorithmic_bytes = ph.alg_bytes;
+            out[i].ntasks = ph.ntasks;
+            out[i].nowners = ph.nowners;
+        }
+        ++i;
+    }
+    if (nphase) *nphase = i;
+    return HM_OK;
+}
+
+struct hm_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x, double* y, uint32_t flags,
+                                     hm_stream_t stream_, hm_graph** out) {
+    if (!m || !x || !y || !out || (flags & HM_TIMING)) {
+        hm::set_error("hm_graph_create: null argument or HM_TIMING requested");
+        return HM_EINVAL;
+    }
+    *out = nullptr;
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail("hm_graph_create: hipStreamCreate", e);
+    // order the capture after work already queued on the caller's stream
+    hipEvent_t dep = nullptr;
+    e = hipEventCreateWithFlags(&dep, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(dep, (hipStream_t)stream_);
+    if (e == hipSuccess) e = hipStreamWaitEvent(cap, dep, 0);
+    if (e == hipSuccess) e = hipStreamSynchronize(cap);
+    hm_graph* g = new (std::nothrow) hm_graph();
+    hm_status st = HM_OK;
+    if (e == hipSuccess && g) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess && g) {
+        st = hm_mvm(m, alpha, x, y, flags, (hm_stream_t)cap);
+        hipError_t e2 = hipStreamEndCapture(cap, &g->graph);
+        if (st == HM_OK && e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess && st == HM_OK && g) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (dep) (void)hipEventDestroy(dep);
+    (void)hipStreamDestroy(cap);
+    if (!g || e != hipSuccess || st != HM_OK) {
+        if (g) {
+            if (g->exec) (void)hipGraphExecDestroy(g->exec);
+            if (g->graph) (void)hipGraphDestroy(g->graph);
+            delete g;
+        }
+        if (st != HM_OK) return st;
+        if (!g) {
+            hm::set_error("hm_graph_create: out of host memory");
+            return HM_ENOMEM;
+        }
+        return hip_fail("hm_graph_create", e);
+    }
+    *out = g;
+    return HM_OK;
+}
+
+extern "C" hm_status hm_graph_launch(hm_graph* g, hm_stream_t stream) {
+    if (!g || !g->exec) {
+        hm::set_error("hm_graph_launch: null graph");
+        return HM_EINVAL;
+    }
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail("hm_graph_launch", e);
+    return HM_OK;
+}
+
+extern "C" void hm_graph_free(hm_graph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
