@@ -70,6 +70,9 @@ def make_values(fmt, points, st, eps):
 
 
 def run_variant(hm, torch, lay, fmt, vals, eps, pol, steps, warmup, x, target):
+    """Upload rotating copies, time `steps` graph-replayed products (the
+    throughput), then `steps` eager products with per-stage HIP events (the
+    per-kernel roofline)."""
     mats = [hm.Matrix(lay, fmt, vals, eps=eps, **pol)]
     s0 = mats[0].stats()
     stored = s0["bytes_dense"] + s0["bytes_factors"] + s0["bytes_coupling"] + s0["bytes_transfer"]
@@ -77,17 +80,24 @@ def run_variant(hm, torch, lay, fmt, vals, eps, pol, steps, warmup, x, target):
     for _ in range(ncopies - 1):
         mats.append(hm.Matrix(lay, fmt, vals, eps=eps, **pol))
     y = torch.zeros_like(x)
+    graphs = [m.graph(x, y) for m in mats]
     for i in range(warmup):
-        mats[i % ncopies].mvm(x, y)
-    torch.cuda.synchronize()
-    for m in mats:
-        m.timing()
+        graphs[i % ncopies].launch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        mats[i % ncopies].mvm(x, y, timing=True)
+        graphs[i % ncopies].launch()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # eager products with per-stage event timing
+    for m in mats:
+        m.timing()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(steps):
+        mats[i % ncopies].mvm(x, y, timing=True)
+    torch.cuda.synchronize()
+    dt_eager = time.perf_counter() - t1
     phases = []
     for m in mats:
         for i, ph in enumerate(m.timing()):
@@ -101,16 +111,19 @@ def run_variant(hm, torch, lay, fmt, vals, eps, pol, steps, warmup, x, target):
     mats[0].mvm(x, yv)
     torch.cuda.synchronize()
     y_out = yv.cpu().numpy()
+    for g in graphs:
+        g.free()
     for m in mats:
         m.free()
-    return dict(stats=s0, ncopies=ncopies, seconds=dt, phases=phases, y=y_out)
+    return dict(stats=s0, ncopies=ncopies, seconds=dt, seconds_eager=dt_eager, phases=phases, y=y_out)
 
 
 def summarize(res, steps):
     s = res["stats"]
     ms = res["seconds"] * 1e3 / steps
     gbs = s["algorithmic_bytes"] / (ms * 1e-3) / 1e9
-    dom = max(res["phases"], key=lambda p: p["ms_total"]) if res["phases"] else None
+    with_tasks = [p for p in res["phases"] if p["ntasks"] > 0 and p["launches"] > 0]
+    dom = max(with_tasks, key=lambda p: p["ms_total"]) if with_tasks else None
     roof = None
     if dom and dom["launches"]:
         avg_ms = dom["ms_total"] / dom["launches"]
@@ -120,10 +133,34 @@ def summarize(res, steps):
                 "kernel": f"k_owner_tasks[{dom['name']}]", "avg_launch_us": round(avg_ms * 1e3, 2),
                 "bytes_per_launch": int(dom["algorithmic_bytes"])}
     return dict(ms_per_step=ms, gbs=gbs, matvecs_per_s=1e3 / ms, roofline=roof,
+                eager_ms_per_step=res["seconds_eager"] * 1e3 / steps,
                 algorithmic_bytes=s["algorithmic_bytes"], copies=res["ncopies"],
-                phases=[{"name": p["name"], "us_avg": round(p["ms_total"] * 1e3 / max(p["launches"], 1), 2),
+                phases=[{"name": p["name"], "ntasks": p["ntasks"],
+                         "us_avg": round(p["ms_total"] * 1e3 / max(p["launches"], 1), 2),
                          "GBs": round(p["algorithmic_bytes"] / max(p["ms_total"] / max(p["launches"], 1), 1e-9)
                                       / 1e6, 1)} for p in res["phases"]])
+
+
+def measured_traffic(workload, policy):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary (FETCH_SIZE/WRITE_SIZE scaled by a copy-kernel calibration), or
+    None if there is none or the kernel/packer sources changed since."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+
+    def sha(p):
+        with open(os.path.join(here, p), "rb") as f:
+            return hashlib.sha256(f.read()).hexdigest()[:16]
+    cur = sha("paper_2405_03456_amd/csrc/hm_runtime.hip") + "+" + sha("paper_2405_03456_amd/csrc/hm_pack.cpp")
+    for path in glob.glob(os.path.join(here, "profiles", "*.md")):
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic_json:"):
+                    t = json.loads(line.split(":", 1)[1])
+                    if t["workload"] == workload and t["policy"] == policy and t["source_sha"] == cur:
+                        return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+    return None
 
 
 def cpu_baseline(fmt, st, vals, x, budget_s, gpu_results, points, eps):
@@ -171,6 +208,8 @@ def main():
     ap.add_argument("--workload", default="uh32768", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, run a plain 1 GiB device copy (known traffic) to scale PMC counters")
     ap.add_argument("--copies-bytes", type=float, default=2.0e9,
                     help="upload copies until the rotated set exceeds this many bytes")
     args = ap.parse_args()
@@ -203,7 +242,18 @@ def main():
         log(f"[bench] {name}: {sm['ms_per_step'] * 1e3:.1f} us/step, {sm['gbs']:.0f} GB/s, "
             f"copies={r['ncopies']}, phases={sm['phases']}")
 
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] calibration: 3 copies of 1 GiB (read 1 GiB + write 1 GiB each)")
+
     main_s = summarize(results["f64"], args.steps)
+    if main_s["roofline"] is not None:
+        tr = measured_traffic(args.workload, "f64")
+        main_s["roofline"]["traffic"] = None if tr is None else int(tr)
     f32_s = summarize(results["f32"], args.steps)
     out = {
         "metric": METRIC,
@@ -221,6 +271,8 @@ def main():
         "config": {"workload": desc, "format": fmt, "n": n, "eps": eps, "nrhs": 1,
                    "storage": "f64", "accumulation": "f64", "rotated_copies": main_s["copies"]},
         "matvecs_per_s": round(main_s["matvecs_per_s"], 1),
+        "timing": "graph replay (one hipGraph per rotated copy); roofline from event-timed eager products",
+        "eager_ms_per_step": round(main_s["eager_ms_per_step"], 5),
         "algorithmic_bytes_per_matvec": int(main_s["algorithmic_bytes"]),
         "roofline": main_s["roofline"],
         "phases_f64": main_s["phases"],
