@@ -179,6 +179,8 @@ typedef struct {
     int64_t bytes_dense, bytes_factors, bytes_coupling, bytes_transfer, bytes_scales;
     int64_t bytes_meta, bytes_workspace;
     int64_t bytes_per_dtype[5];     /* stored matrix data by dtype (HM_F64..HM_FP8E4M3) */
+    int64_t entries_per_dtype[5];   /* stored matrix entries by dtype, each source matrix once,
+                                       without tile padding */
     int64_t sum_rank;               /* sum of block ranks (H) or basis ranks (UH/H2) */
     int32_t max_rank;
     int32_t accum;                  /* resolved accumulation (HM_ACC_F32 / HM_ACC_F64) */
@@ -187,6 +189,14 @@ typedef struct {
 } hm_stats;
 
 hm_status hm_matrix_stats(const hm_matrix* m, hm_stats* s);
+
+/* Host-only dry run of hm_upload: quantise and pack exactly as hm_upload
+ * would (same storage choices, same plan), fill *out with the statistics
+ * of the resulting matrix and release everything.  Touches no device; the
+ * errors are those of hm_upload.  Used to inspect the per-dtype storage
+ * that VALR (Sec. 4.2) selects before committing device memory. */
+hm_status hm_plan_stats(const hm_layout* layout, int32_t format, const hm_values* values,
+                        const hm_precision* prec, hm_stats* out);
 
 /* ------------------------------------------------------------- products */
 

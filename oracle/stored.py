@@ -8,7 +8,10 @@ the per-column scale rule of oracle.quant.  The policy follows the storage
 classes of the paper: dense inadmissible blocks (diagonal blocks t == s may
 use their own format), low-rank factors / cluster bases (Sec. 4.2), and
 coupling and transfer matrices (direct compression, Sec. 4.1).  For the H^2
-column transfers F the scaled axis is a row of F.  The result is a copy of
+column transfers F the scaled axis is a row of F.  Under VALR (Sec. 4.2)
+each column of a low-rank factor or cluster basis gets the cheapest format
+that meets its own error budget, and the other classes the cheapest format
+whose unit roundoff is at most eps.  The result is a copy of
 the values with every stored matrix replaced by its dequantised version, so
 the products in oracle.mvm give the exact product of the stored matrix.
 """
@@ -20,37 +23,150 @@ import numpy as np
 
 from . import quant
 
-DT = {"f64": quant.F64, "f32": quant.F32, "bf16": quant.BF16, "f16": quant.F16, "fp8": quant.FP8}
+DT = {"f64": quant.F64, "f32": quant.F32, "bf16": quant.BF16, "f16": quant.F16, "fp8": quant.FP8,
+      "valr": quant.VALR}
 
 
-def _s(A, fmt):
-    return None if A is None else quant.stored(A, DT[fmt])
+def direct_format(eps: float) -> int:
+    """Direct compression (Sec. 4.1) under VALR: the cheapest format (fewest
+    bytes, then smallest unit roundoff) whose unit roundoff (Table 1) is at
+    most eps; FP64 if none is."""
+    for f in sorted((quant.FP8, quant.F16, quant.BF16, quant.F32),
+                    key=lambda f: (quant.BYTES[f], quant.unit_roundoff(f))):
+        if quant.unit_roundoff(f) <= eps:
+            return f
+    return quant.F64
 
 
-def _s_rows(A, fmt):
-    return None if A is None else np.asfortranarray(quant.stored(np.asarray(A).T, DT[fmt]).T)
+def valr_column_format(w: np.ndarray, delta: float) -> int:
+    """VALR (Sec. 4.2): the cheapest format whose stored column differs from
+    w by at most delta in the 2-norm, trying FP8, FP16, BF16, FP32 in that
+    order (FP64 otherwise).  The squared error is summed in row order and
+    compared with delta^2."""
+    w = np.asarray(w, dtype=np.float64)
+    for f in (quant.FP8, quant.F16, quant.BF16, quant.F32):
+        d = w - quant.stored(w[:, None], f)[:, 0]
+        e2 = np.cumsum(d * d)[-1] if len(d) else 0.0
+        if e2 <= delta * delta:
+            return f
+    return quant.F64
 
 
-def stored_values(st, fmt: str, values, dense="f64", diag=None, factor="f64", coupling=None):
+def _norm2(s) -> float:
+    s = np.asarray(s, dtype=np.float64)
+    return float(np.sqrt(np.cumsum(s * s)[-1])) if len(s) else 0.0
+
+
+def valr_deltas(weights, delta: float) -> np.ndarray:
+    """Per-column budgets delta_i = delta / weight_i (Sec. 4.2); a column of
+    zero weight contributes nothing and gets an unlimited budget."""
+    w = np.asarray(weights, dtype=np.float64)
+    out = np.full(len(w), np.inf)
+    nz = w > 0
+    out[nz] = delta / w[nz]
+    return out
+
+
+def h_block_deltas(sigma, eps: float) -> np.ndarray:
+    """Budgets of the columns of W_b and X_b of an H block with singular
+    values sigma: delta = eps ||sigma||_2 / (1 + 2k), so the bound of eq. (6)
+    on the stored block is the truncation error eps ||sigma||_2."""
+    k = len(sigma)
+    return valr_deltas(sigma, eps * _norm2(sigma) / (1.0 + 2.0 * k))
+
+
+def basis_deltas(sv, eps: float) -> np.ndarray:
+    """Budgets of the columns of a cluster basis with weights sv (the
+    singular values of its construction): delta = eps ||sv||_2 / k, eq. (7)."""
+    k = len(sv)
+    return valr_deltas(sv, eps * _norm2(sv) / k) if k else np.zeros(0)
+
+
+class _Store:
+    """Stores matrices under one policy and counts the entries per format."""
+
+    def __init__(self, eps, counts):
+        self.eps = eps
+        self.counts = counts
+
+    def _count(self, f, entries):
+        if self.counts is not None:
+            self.counts[f] += entries
+
+    def direct(self, A, fmt):
+        if A is None:
+            return None
+        f = DT[fmt]
+        if f == quant.VALR:
+            f = direct_format(self.eps)
+        A = np.asarray(A, dtype=np.float64)
+        self._count(f, A.size)
+        return quant.stored(A, f)
+
+    def direct_rows(self, A, fmt):
+        """Direct compression with the scaled axis along the rows of A."""
+        if A is None:
+            return None
+        return np.asfortranarray(self.direct(np.asarray(A).T, fmt).T)
+
+    def factor(self, A, fmt, deltas):
+        """A low-rank factor or cluster basis: one format for all columns,
+        or under VALR one format per column chosen from its budget."""
+        if A is None:
+            return None
+        f = DT[fmt]
+        if f != quant.VALR:
+            return self.direct(A, fmt)
+        A = np.asarray(A, dtype=np.float64)
+        out = np.zeros_like(A, order="F")
+        for j in range(A.shape[1]):
+            fj = valr_column_format(A[:, j], deltas[j])
+            self._count(fj, A.shape[0])
+            out[:, j] = quant.stored(A[:, j:j + 1], fj)[:, 0]
+        return out
+
+
+def stored_values(st, fmt: str, values, dense="f64", diag=None, factor="f64", coupling=None,
+                  eps: float = 0.0, counts=None):
+    """The values as stored.  `counts` (length >= 5, optional) accumulates
+    the stored entries per format code.  Under "valr" the dense and
+    coupling/transfer classes are direct-compressed at eps, the diagonal
+    dense blocks stay FP64, and factors/bases take VALR per column, which
+    needs the singular values (H: sigma; UH/H2: row_sv/col_sv)."""
     diag = diag or dense
     coupling = coupling or factor
+    if DT[diag] == quant.VALR:
+        diag = "f64"
+    if quant.VALR in (DT[dense], DT[factor], DT[coupling]) and not eps > 0:
+        raise ValueError("VALR storage needs eps > 0")
+    S = _Store(eps, counts)
+    valr = DT[factor] == quant.VALR
     out = copy.copy(values)
     out.dense = [None if values.dense[b] is None else
-                 _s(values.dense[b], diag if st.blk_tau[b] == st.blk_sigma[b] else dense)
+                 S.direct(values.dense[b], diag if st.blk_tau[b] == st.blk_sigma[b] else dense)
                  for b in range(st.nblocks)]
     if fmt == "h":
-        out.W = [_s(a, factor) for a in values.W]
-        out.X = [_s(a, factor) for a in values.X]
+        dl = [None if s is None else (h_block_deltas(s, eps) if valr else None) for s in values.sigma]
+        out.W = [S.factor(a, factor, d) for a, d in zip(values.W, dl)]
+        out.X = [S.factor(a, factor, d) for a, d in zip(values.X, dl)]
     elif fmt == "uh":
-        out.row_basis = [_s(a, factor) for a in values.row_basis]
-        out.col_basis = [_s(a, factor) for a in values.col_basis]
-        out.coupling = [_s(a, coupling) for a in values.coupling]
+        def bd(sv):
+            return [None if s is None else (basis_deltas(s, eps) if valr else None) for s in sv]
+        rd = bd(values.row_sv) if valr else [None] * len(values.row_basis)
+        cd = bd(values.col_sv) if valr else [None] * len(values.col_basis)
+        out.row_basis = [S.factor(a, factor, d) for a, d in zip(values.row_basis, rd)]
+        out.col_basis = [S.factor(a, factor, d) for a, d in zip(values.col_basis, cd)]
+        out.coupling = [S.direct(a, coupling) for a in values.coupling]
     else:
-        out.row_leaf_basis = [_s(a, factor) for a in values.row_leaf_basis]
-        out.col_leaf_basis = [_s(a, factor) for a in values.col_leaf_basis]
-        out.row_transfer = [_s(a, coupling) for a in values.row_transfer]
-        out.col_transfer = [_s_rows(a, coupling) for a in values.col_transfer]
-        out.coupling = [_s(a, coupling) for a in values.coupling]
+        def bd(basis, sv):
+            return [None if a is None else (basis_deltas(s, eps) if valr else None) for a, s in zip(basis, sv)]
+        rd = bd(values.row_leaf_basis, values.row_sv) if valr else [None] * len(values.row_leaf_basis)
+        cd = bd(values.col_leaf_basis, values.col_sv) if valr else [None] * len(values.col_leaf_basis)
+        out.row_leaf_basis = [S.factor(a, factor, d) for a, d in zip(values.row_leaf_basis, rd)]
+        out.col_leaf_basis = [S.factor(a, factor, d) for a, d in zip(values.col_leaf_basis, cd)]
+        out.row_transfer = [S.direct(a, coupling) for a in values.row_transfer]
+        out.col_transfer = [S.direct_rows(a, coupling) for a in values.col_transfer]
+        out.coupling = [S.direct(a, coupling) for a in values.coupling]
     return out
 
 

@@ -12,10 +12,12 @@ import numpy as np
 
 from . import _lib
 from ._lib import (HM_ACC_AUTO, HM_ACC_F32, HM_ACC_F64, HM_BF16, HM_CLUSTER_ORDER,  # noqa: F401
-                   HM_F16, HM_F32, HM_F64, HM_FMT_H, HM_FMT_H2, HM_FMT_UH, HM_FP8E4M3, HMError)
+                   HM_F16, HM_F32, HM_F64, HM_FMT_H, HM_FMT_H2, HM_FMT_UH, HM_FP8E4M3, HM_VALR_AUTO,
+                   HMError)
 
 FORMATS = {"h": HM_FMT_H, "uh": HM_FMT_UH, "h2": HM_FMT_H2}
-DTYPES = {"f64": HM_F64, "f32": HM_F32, "bf16": HM_BF16, "f16": HM_F16, "fp8": HM_FP8E4M3}
+DTYPES = {"f64": HM_F64, "f32": HM_F32, "bf16": HM_BF16, "f16": HM_F16, "fp8": HM_FP8E4M3,
+          "valr": HM_VALR_AUTO}
 
 
 def _dptr(a):
@@ -118,12 +120,38 @@ def marshal_values(fmt: str, values):
         v.row_basis, v.col_basis = tab(values.row_leaf_basis), tab(values.col_leaf_basis)
         v.row_transfer, v.col_transfer = tab(values.row_transfer), tab(values.col_transfer)
         v.coupling = tab(values.coupling)
+    if f != HM_FMT_H:
+        # basis weights for VALR (optional)
+        if getattr(values, "row_sv", None) is not None:
+            v.row_sv = tab(values.row_sv)
+        if getattr(values, "col_sv", None) is not None:
+            v.col_sv = tab(values.col_sv)
     return v, tabs
 
 
 def make_precision(eps=0.0, dense="f64", diag=None, factor="f64", coupling=None, accum=HM_ACC_AUTO):
     return _lib.Precision(eps, DTYPES[dense], DTYPES[diag or dense], DTYPES[factor],
                           DTYPES[coupling or factor], accum)
+
+
+def _stats_dict(s) -> dict:
+    out = {k: getattr(s, k) for k, _ in _lib.Stats._fields_}
+    out["bytes_per_dtype"] = list(s.bytes_per_dtype)
+    out["entries_per_dtype"] = list(s.entries_per_dtype)
+    return out
+
+
+def plan_stats(layout: "Layout", fmt: str, values, eps: float = 0.0, dense="f64", diag=None,
+               factor="f64", coupling=None, accum: int = HM_ACC_AUTO) -> dict:
+    """Storage statistics hm_upload would produce, computed on the host
+    only (hm_plan_stats): no device memory is touched."""
+    v, tabs = marshal_values(fmt, values)
+    prec = make_precision(eps, dense, diag, factor, coupling, accum)
+    s = _lib.Stats()
+    _lib.check(_lib.lib().hm_plan_stats(layout.handle, FORMATS[fmt], ctypes.byref(v), ctypes.byref(prec),
+                                        ctypes.byref(s)))
+    del tabs
+    return _stats_dict(s)
 
 
 class Matrix:
@@ -134,6 +162,7 @@ class Matrix:
       uh: dense, row_basis, col_basis, coupling    (per block / node)
       h2: dense, row_rank, col_rank, row_leaf_basis, row_transfer,
           col_leaf_basis, col_transfer, coupling
+    and for VALR storage ("valr") of UH/H2 bases also row_sv, col_sv.
     """
 
     def __init__(self, layout: Layout, fmt: str, values, eps: float = 0.0, dense="f64", diag=None,
@@ -156,9 +185,7 @@ class Matrix:
     def stats(self) -> dict:
         s = _lib.Stats()
         _lib.check(_lib.lib().hm_matrix_stats(self._h, ctypes.byref(s)))
-        out = {k: getattr(s, k) for k, _ in _lib.Stats._fields_}
-        out["bytes_per_dtype"] = list(s.bytes_per_dtype)
-        return out
+        return _stats_dict(s)
 
     def mvm(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None, timing: bool = False):
         """y += alpha * M * x for device float64 tensors (enqueued, asynchronous)."""

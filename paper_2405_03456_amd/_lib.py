@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("n", c_int64), ("nblocks", c_int64), ("ndense", c_int64), ("nlowrank", c_int64),
                 ("bytes_dense", c_int64), ("bytes_factors", c_int64), ("bytes_coupling", c_int64),
                 ("bytes_transfer", c_int64), ("bytes_scales", c_int64), ("bytes_meta", c_int64),
-                ("bytes_workspace", c_int64), ("bytes_per_dtype", c_int64 * 5), ("sum_rank", c_int64),
+                ("bytes_workspace", c_int64), ("bytes_per_dtype", c_int64 * 5),
+                ("entries_per_dtype", c_int64 * 5), ("sum_rank", c_int64),
                 ("max_rank", c_int32), ("accum", c_int32), ("nlaunch", c_int32),
                 ("algorithmic_bytes", c_double)]
 
@@ -70,6 +71,7 @@ SIGNATURES = {
     "hm_upload": (c_int32, [c_void_p, c_int32, P(Values), P(Precision), c_void_p, P(c_void_p)]),
     "hm_matrix_free": (None, [c_void_p]),
     "hm_matrix_stats": (c_int32, [c_void_p, P(Stats)]),
+    "hm_plan_stats": (c_int32, [c_void_p, c_int32, P(Values), P(Precision), P(Stats)]),
     "hm_mvm": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p]),
     "hm_graph_create": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p, P(c_void_p)]),
     "hm_graph_launch": (c_int32, [c_void_p, c_void_p]),

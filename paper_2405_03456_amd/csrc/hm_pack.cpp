@@ -24,7 +24,10 @@
 // so that every product is "one lane per output row".
 #include <algorithm>
 #include <cmath>
+#include <array>
+#include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <thread>
 
 #include "hm_pack.h"
@@ -58,6 +61,42 @@ int64_t tile_count(int32_t dt, int64_t ncols) { return (ncols + tile_cols(dt) - 
 
 // formats whose columns carry a range scale (narrow exponent range)
 bool range_scaled(int32_t dt) { return dt == HM_F16 || dt == HM_FP8E4M3; }
+
+// Storage scale of one column (1 for FP64/FP32/BF16) and its codes.
+double column_scale(const double* col, int64_t m, int32_t dt) {
+    if (!range_scaled(dt)) return 1.0;
+    double mx = 0.0;
+    for (int64_t i = 0; i < m; ++i) mx = std::max(mx, std::fabs(col[i]));
+    if (mx == 0.0) return 1.0;
+    double c = (double)(float)(mx / dtype_max(dt));
+    return c < 1.1754943508222875e-38 ? 1.1754943508222875e-38 : c;   // 2^-126
+}
+
+// VALR (Sec. 4.2): the cheapest format whose measured column error
+// ||w - c*q||_2 (squares summed in row order, float64) is at most delta.
+int32_t valr_choose(const double* col, int64_t m, double delta) {
+    static const int32_t ladder[4] = {HM_FP8E4M3, HM_F16, HM_BF16, HM_F32};
+    const double d2 = delta * delta;
+    for (int32_t dt : ladder) {
+        const double c = column_scale(col, m, dt);
+        double e2 = 0.0;
+        for (int64_t i = 0; i < m; ++i) {
+            const double q = round_to(dt, c == 1.0 ? col[i] : col[i] / c);
+            const double d = col[i] - c * q;
+            e2 = e2 + d * d;
+        }
+        if (e2 <= d2) return dt;
+    }
+    return HM_F64;
+}
+
+// Direct compression (Sec. 4.1): cheapest format with unit roundoff <= eps.
+int32_t direct_for_eps(double eps) {
+    if (eps >= 0.0625) return HM_FP8E4M3;
+    if (eps >= 0.00048828125) return HM_F16;
+    if (eps >= 5.9604644775390625e-08) return HM_F32;
+    return HM_F64;
+}
 
 struct Builder {
     const Layout& L;
@@ -95,6 +134,54 @@ struct Builder {
         }
         src.push_back(std::move(s));
         return (int32_t)src.size() - 1;
+    }
+
+    double eps = 0.0;
+    std::deque<std::vector<double>> pool;   // stable storage for host-made matrices
+
+    // A factor (low-rank factor or cluster basis) stored as runs of columns
+    // of one dtype: one run unless factor_dt is VALR_AUTO.
+    struct Run {
+        int32_t src, c0, k;
+    };
+    // deltas: per-column error budget delta_j of VALR (unused otherwise)
+    std::vector<Run> add_factor(const double* A, int64_t m, int64_t k, const double* colfactor, int cls,
+                                const std::vector<double>& deltas) {
+        std::vector<Run> runs;
+        if (k == 0) return runs;
+        if (factor_dt != HM_VALR_AUTO) {
+            runs.push_back(Run{add_source(A, m, k, factor_dt, colfactor, cls), 0, (int32_t)k});
+            return runs;
+        }
+        std::vector<int32_t> dts(k);
+        for (int64_t j = 0; j < k; ++j) dts[j] = valr_choose(A + j * m, m, deltas[(size_t)j]);
+        int64_t j0 = 0;
+        for (int64_t j = 1; j <= k; ++j)
+            if (j == k || dts[j] != dts[j0]) {
+                runs.push_back(Run{add_source(A + j0 * m, m, j - j0, dts[j0], colfactor ? colfactor + j0 : nullptr, cls),
+                                   (int32_t)j0, (int32_t)(j - j0)});
+                j0 = j;
+            }
+        return runs;
+    }
+
+    // scale index of column j of a factor (-1 = 1.0)
+    int64_t run_scale(const std::vector<Run>& runs, int32_t j) const {
+        for (const Run& r : runs)
+            if (j < r.c0 + r.k) return src[r.src].scale_off >= 0 ? src[r.src].scale_off + (j - r.c0) : -1;
+        return -1;
+    }
+
+    // element-wise scale products: scales[dst] = s(a) * s(b), s(-1) = 1
+    std::vector<std::array<int64_t, 3>> efolds;
+    int32_t fold_list(const std::vector<int64_t>& a, const std::vector<int64_t>& b) {
+        bool any = false;
+        for (size_t i = 0; i < a.size(); ++i) any |= a[i] >= 0 || b[i] >= 0;
+        if (!any) return -1;
+        const int32_t dst = (int32_t)nscales;
+        nscales += (int64_t)a.size();
+        for (size_t i = 0; i < a.size(); ++i) efolds.push_back({dst + (int64_t)i, a[i], b[i]});
+        return dst;
     }
 
     // scales[dst + j] = scales[a + j] * scales[b + j] (a or b < 0: factor 1),
@@ -325,12 +412,38 @@ struct Builder {
         return true;
     }
 
+    // VALR tolerances.  H block b = W diag(s) X^T: its columns w_j, x_j get
+    // delta_j = delta / s_j with delta = eps ||s||_2 / (1 + 2k), so the bound
+    // of eq. (6) stays at the truncation error eps ||s||_2.  Cluster bases
+    // with weights s: delta = eps ||s||_2 / k (eq. 7).
+    static double norm2(const double* w, int64_t k) {
+        double t = 0.0;
+        for (int64_t j = 0; j < k; ++j) t = t + w[j] * w[j];
+        return std::sqrt(t);
+    }
+    // delta_j = delta / w_j (a zero weight gives an unlimited budget)
+    static std::vector<double> deltas_for(const double* w, int64_t k, double delta) {
+        std::vector<double> d((size_t)k);
+        for (int64_t j = 0; j < k; ++j) d[(size_t)j] = w[j] > 0.0 ? delta / w[j] : HUGE_VAL;
+        return d;
+    }
+    bool need_sv(const double* const* sv, int32_t v, int32_t k) {
+        if (factor_dt != HM_VALR_AUTO || k == 0) return true;
+        return check(sv && sv[v], "VALR storage needs row_sv / col_sv basis weights");
+    }
+    std::vector<Run> basis_factor(const double* A, int64_t m, int64_t k, const double* const* sv, int32_t v) {
+        std::vector<double> d;
+        if (factor_dt == HM_VALR_AUTO) d = deltas_for(sv[v], k, eps * norm2(sv[v], k) / (double)k);
+        return add_factor(A, m, k, nullptr, 1, d);
+    }
+
     // --------------------------------------------------------------- H
     bool build_h() {
         if (!check_dense()) return false;
         if (!V->rank || !V->W || !V->sigma || !V->X) return check(false, "H needs rank, W, sigma, X");
         const int64_t nb = (int64_t)L.blk_tau.size();
-        std::vector<int32_t> tb_off(nb, -1), usrc(nb, -1), dsrc(nb, -1);
+        std::vector<int32_t> tb_off(nb, -1), dsrc(nb, -1);
+        std::vector<std::vector<Run>> urun(nb);
         for (int64_t b = 0; b < nb; ++b) {
             if (!L.blk_adm[b]) continue;
             const int32_t k = V->rank[b];
@@ -344,7 +457,6 @@ struct Builder {
         std::vector<std::vector<int32_t>> col_lr(L.node_begin.size());
         for (int64_t b = 0; b < nb; ++b)
             if (L.blk_adm[b] && V->rank[b] > 0) col_lr[L.blk_sigma[b]].push_back((int32_t)b);
-        ws = L.n;
         for (auto& bl : col_lr)
             for (int32_t b : bl) {
                 tb_off[b] = (int32_t)ws;
@@ -356,36 +468,36 @@ struct Builder {
             const int64_t ms = L.size(s);
             int64_t K = 0;
             for (int32_t b : col_lr[s]) K += V->rank[b];
-            // stacked X = [X_b1 X_b2 ...] (|s| x K); its per-column scales are
-            // those of the individual X_b columns
-            int32_t xs = add_source(nullptr, ms, K, factor_dt, nullptr, 1);
-            src[xs].own.resize((size_t)(ms * K));
+            // stacked X = [X_b1 X_b2 ...] (|s| x K) with per-column weights
+            pool.emplace_back((size_t)(ms * K));
+            std::vector<double>& Xs = pool.back();
+            std::vector<double> Ds;              // VALR budgets of the stacked columns
+            std::vector<int64_t> uscale;         // U-side scale index per stacked column
             int64_t c0 = 0;
             for (int32_t b : col_lr[s]) {
                 const int32_t k = V->rank[b];
-                std::memcpy(src[xs].own.data() + c0 * ms, V->X[b], sizeof(double) * (size_t)(ms * k));
+                std::memcpy(Xs.data() + c0 * ms, V->X[b], sizeof(double) * (size_t)(ms * k));
+                std::vector<double> d;
+                if (factor_dt == HM_VALR_AUTO)
+                    d = deltas_for(V->sigma[b], k, eps * norm2(V->sigma[b], k) / (1.0 + 2.0 * k));
+                urun[b] = add_factor(V->W[b], L.size(L.blk_tau[b]), k, V->sigma[b], 1, d);
+                Ds.insert(Ds.end(), d.begin(), d.end());
+                for (int32_t j = 0; j < k; ++j) uscale.push_back(run_scale(urun[b], j));
                 c0 += k;
             }
-            src[xs].A = src[xs].own.data();
-            // row scale of the stacked owner: X's range scale times the U-side
-            // column scale (sigma_j and W's range scale) of each block
-            int32_t rs = -1;
-            std::vector<int32_t> us;
-            for (int32_t b : col_lr[s]) {
-                usrc[b] = add_source(V->W[b], L.size(L.blk_tau[b]), V->rank[b], factor_dt, V->sigma[b], 1);
-                us.push_back(src[usrc[b]].scale_off);
+            std::vector<Run> xr = add_factor(Xs.data(), ms, K, nullptr, 1, Ds);
+            for (const Run& r : xr) {
+                // row scale: X's range scale times the U-side column scale
+                // (sigma_j and W's range scale) of the same column
+                std::vector<int64_t> a, bb;
+                for (int32_t j = 0; j < r.k; ++j) {
+                    a.push_back(src[r.src].scale_off >= 0 ? src[r.src].scale_off + j : -1);
+                    bb.push_back(uscale[(size_t)(r.c0 + j)]);
+                }
+                begin_owner(pa, r.k, 0, tb_off[col_lr[s][0]] + r.c0, fold_list(a, bb));
+                add_item(r.src, 0, true, (int32_t)L.node_begin[s]);
+                end_owner();
             }
-            rs = (int32_t)nscales;
-            nscales += K;
-            int64_t r0 = 0;
-            for (size_t i = 0; i < col_lr[s].size(); ++i) {
-                const int32_t k = V->rank[col_lr[s][i]];
-                folds.push_back(Fold{rs + r0, src[xs].scale_off >= 0 ? src[xs].scale_off + r0 : -1, us[i], k});
-                r0 += k;
-            }
-            begin_owner(pa, (int32_t)K, 0, tb_off[col_lr[s][0]], rs);
-            add_item(xs, 0, true, (int32_t)L.node_begin[s]);
-            end_owner();
         }
         const int32_t pb = new_stage("h_rows");
         for (int32_t rho : leaves) {
@@ -394,7 +506,8 @@ struct Builder {
             for (int32_t t : anc) {
                 const int64_t r0 = L.node_begin[rho] - L.node_begin[t];
                 for (int32_t b : row_blocks[t])
-                    if (L.blk_adm[b] && V->rank[b] > 0) add_item(usrc[b], r0, false, tb_off[b], true);
+                    if (L.blk_adm[b] && V->rank[b] > 0)
+                        for (const Run& r : urun[b]) add_item(r.src, r0, false, tb_off[b] + r.c0, true);
             }
             add_dense_items(rho, anc, dsrc);
             end_owner();
@@ -409,11 +522,13 @@ struct Builder {
             return check(false, "UH needs row/col ranks, bases and couplings");
         const int32_t N = (int32_t)L.node_begin.size();
         const int64_t nb = (int64_t)L.blk_tau.size();
-        std::vector<int32_t> s_off(N, -1), t_off(N, -1), wsrc(N, -1), dsrc(nb, -1);
+        std::vector<int32_t> s_off(N, -1), t_off(N, -1), dsrc(nb, -1);
+        std::vector<std::vector<Run>> wrun(N);
         for (int32_t v = 0; v < N; ++v) {
             const int32_t kr = V->row_rank[v], kc = V->col_rank[v];
             if (kr < 0 || kc < 0 || kr > L.size(v) || kc > L.size(v)) return check(false, "basis rank out of range");
             if ((kr > 0 && !V->row_basis[v]) || (kc > 0 && !V->col_basis[v])) return check(false, "missing basis");
+            if (!need_sv(V->row_sv, v, kr) || !need_sv(V->col_sv, v, kc)) return false;
             if (kc > 0) { s_off[v] = (int32_t)ws; ws += kc; }
             if (kr > 0) { t_off[v] = (int32_t)ws; ws += kr; }
         }
@@ -426,18 +541,22 @@ struct Builder {
         for (int32_t v = 0; v < N; ++v) {
             const int32_t kc = V->col_rank[v];
             if (kc == 0) continue;
-            int32_t xs = add_source(V->col_basis[v], L.size(v), kc, factor_dt, nullptr, 1);
-            begin_owner(pf, kc, 0, s_off[v], src[xs].scale_off);
-            add_item(xs, 0, true, (int32_t)L.node_begin[v]);
-            end_owner();
+            for (const Run& r : basis_factor(V->col_basis[v], L.size(v), kc, V->col_sv, v)) {
+                begin_owner(pf, r.k, 0, s_off[v] + r.c0, src[r.src].scale_off);
+                add_item(r.src, 0, true, (int32_t)L.node_begin[v]);
+                end_owner();
+            }
         }
         for (int32_t v = 0; v < N; ++v)
-            if (V->row_rank[v] > 0) wsrc[v] = add_source(V->row_basis[v], L.size(v), V->row_rank[v], factor_dt, nullptr, 1);
+            if (V->row_rank[v] > 0) wrun[v] = basis_factor(V->row_basis[v], L.size(v), V->row_rank[v], V->row_sv, v);
         const int32_t pc = new_stage("uh_coup");
         for (int32_t t = 0; t < N; ++t) {
             const int32_t kr = V->row_rank[t];
             if (kr == 0) continue;
-            begin_owner(pc, kr, 0, t_off[t], src[wsrc[t]].scale_off);
+            // t_t is produced times the column scales of W_t (its only consumer)
+            std::vector<int64_t> a, none(kr, -1);
+            for (int32_t j = 0; j < kr; ++j) a.push_back(run_scale(wrun[t], j));
+            begin_owner(pc, kr, 0, t_off[t], fold_list(a, none));
             for (int32_t b : row_blocks[t]) {
                 if (!L.blk_adm[b]) continue;
                 const int32_t s = L.blk_sigma[b];
@@ -453,7 +572,8 @@ struct Builder {
             begin_owner(pr, (int32_t)L.size(rho), 1, (int32_t)L.node_begin[rho], -1);
             const std::vector<int32_t> anc = ancestors_root_first(rho);
             for (int32_t t : anc)
-                if (wsrc[t] >= 0) add_item(wsrc[t], L.node_begin[rho] - L.node_begin[t], false, t_off[t], true);
+                for (const Run& r : wrun[t])
+                    add_item(r.src, L.node_begin[rho] - L.node_begin[t], false, t_off[t] + r.c0, true);
             add_dense_items(rho, anc, dsrc);
             end_owner();
         }
@@ -475,6 +595,7 @@ struct Builder {
             if (L.leaf(v) && (kr > L.size(v) || kc > L.size(v))) return check(false, "leaf rank exceeds cluster size");
             if (L.leaf(v) && ((kr > 0 && !V->row_basis[v]) || (kc > 0 && !V->col_basis[v])))
                 return check(false, "missing leaf basis");
+            if (L.leaf(v) && (!need_sv(V->row_sv, v, kr) || !need_sv(V->col_sv, v, kc))) return false;
             const int32_t p = L.node_parent[v];
             if (p >= 0) {
                 if (kr > 0 && V->row_rank[p] > 0 && !V->row_transfer[v]) return check(false, "missing row transfer");
@@ -487,10 +608,11 @@ struct Builder {
         for (int32_t g : leaves) {
             const int32_t kc = V->col_rank[g];
             if (kc == 0) continue;
-            int32_t xs = add_source(V->col_basis[g], L.size(g), kc, factor_dt, nullptr, 1);
-            begin_owner(pl, kc, 0, s_off[g], src[xs].scale_off);
-            add_item(xs, 0, true, (int32_t)L.node_begin[g]);
-            end_owner();
+            for (const Run& r : basis_factor(V->col_basis[g], L.size(g), kc, V->col_sv, g)) {
+                begin_owner(pl, r.k, 0, s_off[g] + r.c0, src[r.src].scale_off);
+                add_item(r.src, 0, true, (int32_t)L.node_begin[g]);
+                end_owner();
+            }
         }
         std::vector<std::vector<int32_t>> by_level(L.depth + 1);
         for (int32_t v = 0; v < N; ++v) by_level[L.node_level[v]].push_back(v);
@@ -513,10 +635,10 @@ struct Builder {
                 end_owner();
             }
         }
-        std::vector<int32_t> lsrc(N, -1);
+        std::vector<std::vector<Run>> lrun(N);
         for (int32_t rho : leaves)
             if (V->row_rank[rho] > 0)
-                lsrc[rho] = add_source(V->row_basis[rho], L.size(rho), V->row_rank[rho], factor_dt, nullptr, 1);
+                lrun[rho] = basis_factor(V->row_basis[rho], L.size(rho), V->row_rank[rho], V->row_sv, rho);
         for (int32_t lv = 0; lv <= L.depth; ++lv) {
             bool any = false;
             for (int32_t v : by_level[lv]) any |= V->row_rank[v] > 0;
@@ -526,7 +648,13 @@ struct Builder {
                 const int32_t kr = V->row_rank[t];
                 if (kr == 0) continue;
                 // a leaf's coefficients feed only its own basis: fold its column scales
-                begin_owner(pd, kr, 0, t_off[t], lsrc[t] >= 0 ? src[lsrc[t]].scale_off : -1);
+                int32_t rs = -1;
+                if (L.leaf(t)) {
+                    std::vector<int64_t> a, none(kr, -1);
+                    for (int32_t j = 0; j < kr; ++j) a.push_back(run_scale(lrun[t], j));
+                    rs = fold_list(a, none);
+                }
+                begin_owner(pd, kr, 0, t_off[t], rs);
                 const int32_t p = L.node_parent[t];
                 if (p >= 0 && V->row_rank[p] > 0) {
                     int32_t es = add_source(V->row_transfer[t], kr, V->row_rank[p], coup_dt, nullptr, 3);
@@ -547,8 +675,7 @@ struct Builder {
         const int32_t pr = new_stage("h2_rows");
         for (int32_t rho : leaves) {
             begin_owner(pr, (int32_t)L.size(rho), 1, (int32_t)L.node_begin[rho], -1);
-            const int32_t kr = V->row_rank[rho];
-            if (kr > 0) add_item(lsrc[rho], 0, false, t_off[rho], true);
+            for (const Run& r : lrun[rho]) add_item(r.src, 0, false, t_off[rho] + r.c0, true);
             add_dense_items(rho, ancestors_root_first(rho), dsrc);
             end_owner();
         }
@@ -581,11 +708,9 @@ struct Builder {
                         double a = std::fabs(col[i]);
                         if (a > mx) mx = a;
                     }
-                    double cj = 1.0;
-                    if (range_scaled(S.dtype) && mx > 0.0) {
-                        cj = (double)(float)(mx / fmax);
-                        if (cj < 1.1754943508222875e-38) cj = 1.1754943508222875e-38;   // 2^-126
-                    }
+                    (void)mx;
+                    (void)fmax;
+                    const double cj = column_scale(col, m, S.dtype);
                     c[(size_t)j] = cj;
                     for (int64_t i = 0; i < m; ++i)
                         codes[(size_t)(i + j * m)] = round_to(S.dtype, cj == 1.0 ? col[i] : col[i] / cj);
@@ -629,6 +754,8 @@ struct Builder {
             for (int64_t j = 0; j < f.k; ++j)
                 scales[(size_t)(f.dst + j)] = (f.a >= 0 ? scales[(size_t)(f.a + j)] : 1.0) *
                                               (f.b >= 0 ? scales[(size_t)(f.b + j)] : 1.0);
+        for (const auto& f : efolds)
+            scales[(size_t)f[0]] = (f[1] >= 0 ? scales[(size_t)f[1]] : 1.0) * (f[2] >= 0 ? scales[(size_t)f[2]] : 1.0);
         for (const Source& S : src) {
             int64_t bytes = 0;
             for (const Use& u : S.uses)
@@ -756,19 +883,30 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
         return HM_EINVAL;
     }
     for (int32_t dt : {p->dense_dtype, p->diag_dtype, p->factor_dtype, p->coupling_dtype})
-        if (dt < HM_F64 || dt > HM_FP8E4M3) {
+        if (dt < HM_F64 || dt > HM_VALR_AUTO) {
             set_error("hm_upload: unsupported dtype");
             return HM_EINVAL;
         }
+    const bool valr = p->dense_dtype == HM_VALR_AUTO || p->diag_dtype == HM_VALR_AUTO ||
+                      p->factor_dtype == HM_VALR_AUTO || p->coupling_dtype == HM_VALR_AUTO;
+    if (valr && !(p->eps > 0.0 && std::isfinite(p->eps))) {
+        set_error("hm_upload: VALR_AUTO needs eps > 0");
+        return HM_EINVAL;
+    }
     if (p->accum < HM_ACC_AUTO || p->accum > HM_ACC_F64) {
         set_error("hm_upload: bad accumulation mode");
         return HM_EINVAL;
     }
     Builder B(L, format, v, opt);
-    B.dense_dt = p->dense_dtype;
-    B.diag_dt = p->diag_dtype;
+    // VALR_AUTO for dense, diagonal and coupling/transfer matrices means
+    // direct compression in the cheapest format with unit roundoff <= eps
+    // (the diagonal near-field blocks stay FP64)
+    auto direct = [&](int32_t dt) { return dt == HM_VALR_AUTO ? direct_for_eps(p->eps) : dt; };
+    B.dense_dt = direct(p->dense_dtype);
+    B.diag_dt = p->diag_dtype == HM_VALR_AUTO ? HM_F64 : p->diag_dtype;
     B.factor_dt = p->factor_dtype;
-    B.coup_dt = p->coupling_dtype;
+    B.coup_dt = direct(p->coupling_dtype);
+    B.eps = p->eps;
     B.ws = L.n;   // x in cluster order comes first
     B.index_blocks();
     bool ok = false;
@@ -792,8 +930,7 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
         set_error("hm_upload: " + B.err);
         return HM_EINVAL;
     }
-    bool all64 = p->dense_dtype == HM_F64 && p->diag_dtype == HM_F64 && p->factor_dtype == HM_F64 &&
-                 p->coupling_dtype == HM_F64;
+    bool all64 = B.dense_dt == HM_F64 && B.diag_dt == HM_F64 && B.factor_dt == HM_F64 && B.coup_dt == HM_F64;
     if (p->accum == HM_ACC_F64)
         out.acc64 = 1;
     else if (p->accum == HM_ACC_F32)
@@ -909,6 +1046,12 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
         }
     }
     s.accum = out.acc64 ? HM_ACC_F64 : HM_ACC_F32;
+    for (const Source& S : B.src) s.entries_per_dtype[S.dtype] += S.m * S.k;
+    s.nlaunch = 1;   // gather
+    for (auto& st : out.stages) s.nlaunch += (st.t1 > st.t0) + !st.reduce.empty();
+    s.algorithmic_bytes = (double)(s.bytes_dense + s.bytes_factors + s.bytes_coupling + s.bytes_transfer +
+                                   s.bytes_scales + s.bytes_meta) +
+                          24.0 * L.n + 16.0 * (out.ws_elems - L.n);
     std::string why;
     if (!validate(out, L.n, why)) {
         set_error("hm_upload: internal plan check failed (" + why + ")");
@@ -918,3 +1061,23 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
 }
 
 }  // namespace hm
+
+extern "C" hm_status hm_plan_stats(const hm_layout* layout, int32_t format, const hm_values* values,
+                                   const hm_precision* prec, hm_stats* out) {
+    if (!layout || !values || !prec || !out) {
+        hm::set_error("hm_plan_stats: null argument");
+        return HM_EINVAL;
+    }
+    hm::Packed P;
+    hm::PackOptions opt;
+    if (const char* e = std::getenv("HM_TASK_BYTES")) opt.task_bytes = std::max(1024L, std::atol(e));
+    hm_status st;
+    try {
+        st = hm::pack(layout->L, format, values, prec, opt, P);
+    } catch (const std::bad_alloc&) {
+        hm::set_error("hm_plan_stats: out of host memory while packing");
+        return HM_ENOMEM;
+    }
+    if (st == HM_OK) *out = P.stats;
+    return st;
+}

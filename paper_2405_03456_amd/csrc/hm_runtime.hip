@@ -559,11 +559,11 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         }
     }
     m->stats = P.stats;
-    m->stats.nlaunch = nlaunch;
-    int64_t coef = P.ws_elems - n;
-    m->stats.algorithmic_bytes = (double)(m->stats.bytes_dense + m->stats.bytes_factors + m->stats.bytes_coupling +
-                                          m->stats.bytes_transfer + m->stats.bytes_scales + m->stats.bytes_meta) +
-                                 24.0 * n + 16.0 * coef;
+    if (nlaunch != P.stats.nlaunch) {
+        hm_matrix_free(m);
+        hm::set_error("hm_upload: launch count mismatch");
+        return HM_ELAYOUT;
+    }
     *out = m;
     return HM_OK;
 }

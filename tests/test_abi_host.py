@@ -74,3 +74,55 @@ def test_storage_rounding_matches_oracle(name, fmt):
     mid = 0.5 * (grid + quant.round_fmt(up * (1 + 2 ** -(quant.MANT[fmt])), fmt))
     v = np.concatenate([v, grid, mid, np.nextafter(mid, 0), [0.0, -0.0, 1e-320, 5e-324, 1e300, -1e300]])
     assert np.array_equal(hm.round_host(name, v), quant.round_fmt(v, fmt))
+
+
+def _valr_case(eps):
+    from conftest import cached
+    from synth import KERNEL_LAPLACE, compress_h, to_h2, to_uh
+
+    def build():
+        p = sphere_points(2048, 1001)
+        st = trees.build_structure(p)
+        h = compress_h(p, KERNEL_LAPLACE, st, eps, method="svd")
+        return p, st, {"h": h, "uh": to_uh(h, st), "h2": to_h2(h, st)}
+    return cached(("valr-host", eps), build)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("eps", [1e-4, 1e-6, 1e-8])
+def test_valr_choices_match_oracle(eps):
+    """hm_plan_stats (host dry run of hm_upload): the stored entries per
+    format that the library's VALR picks equal the oracle's, for every
+    format.  Both decide in float64 from the same rounding definition, so
+    the counts agree exactly."""
+    from oracle import stored
+    p, st, vals = _valr_case(eps)
+    lay = hm.Layout(p)
+    for fmt in ("h", "uh", "h2"):
+        counts = np.zeros(6, dtype=np.int64)
+        stored.stored_values(st, fmt, vals[fmt], dense="valr", diag="valr", factor="valr", eps=eps,
+                             counts=counts)
+        s = hm.plan_stats(lay, fmt, vals[fmt], eps=eps, dense="valr", diag="valr", factor="valr")
+        assert s["entries_per_dtype"] == [int(c) for c in counts[:5]], fmt
+        assert sum(s["bytes_per_dtype"]) == s["bytes_dense"] + s["bytes_factors"] + \
+            s["bytes_coupling"] + s["bytes_transfer"]
+        assert s["accum"] == (_lib.HM_ACC_F64 if eps < 1e-7 else _lib.HM_ACC_F32)
+        # uniform policies: every entry in the one dtype (diagonal blocks aside)
+        u = hm.plan_stats(lay, fmt, vals[fmt], eps=eps, dense="f32", diag="f32", factor="f32")
+        assert u["entries_per_dtype"][1] == sum(u["entries_per_dtype"])
+        assert sum(u["entries_per_dtype"]) == sum(s["entries_per_dtype"])
+
+
+def test_valr_errors():
+    import copy
+    p, st, vals = _valr_case(1e-6)
+    lay = hm.Layout(p)
+    with pytest.raises(hm.HMError) as ex:                 # VALR needs a target accuracy
+        hm.plan_stats(lay, "h", vals["h"], eps=0.0, factor="valr")
+    assert ex.value.status == _lib.HM_EINVAL
+    uh = copy.copy(vals["uh"])
+    uh.row_sv = None                                      # and the basis weights
+    with pytest.raises(hm.HMError) as ex:
+        hm.plan_stats(lay, "uh", uh, eps=1e-6, factor="valr")
+    assert "row_sv" in str(ex.value)
+    hm.plan_stats(lay, "uh", uh, eps=1e-6, factor="f32")  # not needed otherwise

@@ -68,7 +68,13 @@ POLICIES = {
     "f16": dict(dense="f32", diag="f64", factor="f16", coupling="f16", eps=1e-6),
     "fp8": dict(dense="f32", diag="f64", factor="fp8", coupling="fp8", eps=1e-6),
     "f32acc64": dict(dense="f32", factor="f32", eps=1e-8),
+    # VALR (Sec. 4.2): per-column formats of factors/bases, direct dense and
+    # coupling formats at eps, FP64 diagonal near field
+    "valr4": dict(dense="valr", diag="valr", factor="valr", eps=1e-4),
+    "valr6": dict(dense="valr", diag="valr", factor="valr", eps=1e-6),
+    "valr8": dict(dense="valr", diag="valr", factor="valr", eps=1e-8),
 }
+ACC64 = ("f64", "f32acc64", "valr8")
 
 
 @pytest.mark.parametrize("fmt", ["h", "uh", "h2"])
@@ -80,10 +86,10 @@ def test_parity_n2048(fmt, pol):
     print(f"case fmt={fmt} policy={pol} n={n}", flush=True)
     x, y = gaussian_vector(n, 2001), gaussian_vector(n, 3001)
     sv = stored.stored_values(st, fmt, vals[fmt], dense=pp["dense"], diag=pp.get("diag"),
-                              factor=pp["factor"], coupling=pp.get("coupling"))
+                              factor=pp["factor"], coupling=pp.get("coupling"), eps=pp["eps"])
     ref = stored.product(st, fmt, sv, -0.5, x, y)
     out = run_gpu(lay, fmt, vals[fmt], x, y, -0.5, **pp)
-    tol = TOL64 if pol == "f64" or pol == "f32acc64" else TOL32
+    tol = TOL64 if pol in ACC64 else TOL32
     err = rel(out, ref, y)
     print(f"  rel err {err:.3e} (tol {tol:g})", flush=True)
     assert err <= tol
