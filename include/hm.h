@@ -206,6 +206,28 @@ hm_status hm_plan_stats(const hm_layout* layout, int32_t format, const hm_values
 hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double* y, uint32_t flags,
                  hm_stream_t stream);
 
+/* Many right-hand sides (the paper's product applied to every column of a
+ * block of vectors, eq. 4 per column): for i < nmat,
+ *     Y_i := alpha * M_i * X_i + Y_i,
+ * X_i, Y_i device arrays of n_i x nrhs[i] values, column-major with leading
+ * dimensions ldx[i], ldy[i] >= n_i, in float64 (vec_dtype HM_F64) or
+ * float32 (HM_F32).  mats, X, ldx, nrhs, Y, ldy are host arrays of nmat
+ * entries; the vectors are caller-owned and X_i must not overlap Y_i.
+ * nrhs[i] in [0, HM_MAX_NRHS]; 0 skips the entry.  One matrix may appear
+ * only once per call.  flags: HM_CLUSTER_ORDER as for hm_mvm.
+ * A single float64 column runs the hm_mvm kernels; wider blocks run the
+ * matrix-core path (16x16x4 MFMA, float32 products and accumulation, or
+ * float64 throughout for float64 data and for matrices that accumulate in
+ * float64).  Each matrix keeps a workspace sized for the widest block seen;
+ * growing it synchronises the device and allocates, so the first call at a
+ * new width must not be inside a graph capture.  Enqueued on `stream`;
+ * calls on one matrix must not overlap in time.
+ * Errors: HM_EINVAL (arguments), HM_ENOMEM (workspace), HM_EDEVICE. */
+#define HM_MAX_NRHS 1024
+hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double alpha, const void* const* X,
+                       const int64_t* ldx, const int32_t* nrhs, void* const* Y, const int64_t* ldy,
+                       int32_t vec_dtype, uint32_t flags, hm_stream_t stream);
+
 /* A product captured into a HIP graph: the kernels of one hm_mvm call with
  * fixed (alpha, x, y, flags) recorded once and replayed with one launch.
  * Replays read x and update y in place exactly like hm_mvm; results are

@@ -180,3 +180,14 @@ def product(st, fmt: str, values, alpha, x, y):
     return mvm.h2_mvm(st, values.dense, values.row_rank, values.col_rank, values.row_leaf_basis,
                       values.row_transfer, values.col_leaf_basis, values.col_transfer, values.coupling,
                       alpha, x, y)
+
+
+def product_many(st, fmt: str, values, alpha, X, Y):
+    """Many right-hand sides: column j of the result is the single-vector
+    product (eq. 4) applied to column j of X and Y."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    out = np.empty_like(Y)
+    for j in range(X.shape[1]):
+        out[:, j] = product(st, fmt, values, alpha, X[:, j], Y[:, j])
+    return out

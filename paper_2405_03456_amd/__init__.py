@@ -193,6 +193,10 @@ class Matrix:
         flags = (HM_CLUSTER_ORDER if cluster_order else 0) | (_lib.HM_TIMING if timing else 0)
         _lib.check(_lib.lib().hm_mvm(self._h, float(alpha), xp, yp, flags, _stream_ptr(stream)))
 
+    def mvm_many(self, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None):
+        """Y += alpha * M * X for an n x r block (column-major device tensors)."""
+        mvm_batch([self], [X], [Y], alpha, cluster_order, stream)
+
     def graph(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None) -> "Graph":
         """Capture one product (fixed x, y, alpha) into a replayable HIP graph."""
         return Graph(self, x, y, alpha, cluster_order, stream)
@@ -215,6 +219,47 @@ class Matrix:
 
     def __del__(self):
         self.free()
+
+
+def _block_arg(t, n, name):
+    """(device pointer, leading dimension, columns, vec dtype) of a vector
+    block: a 1-D tensor of length n, or an n x r column-major tensor."""
+    import torch
+    if not t.is_cuda or t.dtype not in (torch.float64, torch.float32):
+        raise ValueError(f"{name} must be a float64 or float32 device tensor")
+    vdt = HM_F64 if t.dtype == torch.float64 else HM_F32
+    if t.dim() == 1:
+        if t.numel() != n or t.stride(0) != 1:
+            raise ValueError(f"{name}: contiguous vector of length n expected")
+        return t.data_ptr(), n, 1, vdt
+    if t.dim() != 2 or t.shape[0] != n or (t.shape[1] > 1 and t.stride(0) != 1):
+        raise ValueError(f"{name} must be n x r and column-major (e.g. x.T.contiguous().T)")
+    ld = t.stride(1) if t.shape[1] > 1 else n
+    return t.data_ptr(), max(ld, n), t.shape[1], vdt
+
+
+def mvm_batch(mats, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None):
+    """Y[i] += alpha * mats[i] * X[i] for every i (hm_mvm_batch).  X[i], Y[i]:
+    device tensors of n_i x r_i values (column-major) or vectors of length
+    n_i, all float64 or all float32."""
+    k = len(mats)
+    if len(X) != k or len(Y) != k:
+        raise ValueError("mats, X and Y must have the same length")
+    hs = (ctypes.c_void_p * k)()
+    xs, ys = (ctypes.c_void_p * k)(), (ctypes.c_void_p * k)()
+    ldx, ldy = (ctypes.c_int64 * k)(), (ctypes.c_int64 * k)()
+    nr = (ctypes.c_int32 * k)()
+    vdt = None
+    for i, (M, x, y) in enumerate(zip(mats, X, Y)):
+        px, lx, rx, dx = _block_arg(x, M.layout.n, "X")
+        py, ly, ry, dy = _block_arg(y, M.layout.n, "Y")
+        if rx != ry or dx != dy or (vdt is not None and dx != vdt):
+            raise ValueError("X and Y blocks must agree in width and all share one dtype")
+        vdt = dx
+        hs[i], xs[i], ys[i], ldx[i], ldy[i], nr[i] = M.handle.value, px, py, lx, ly, rx
+    flags = HM_CLUSTER_ORDER if cluster_order else 0
+    _lib.check(_lib.lib().hm_mvm_batch(hs, k, float(alpha), xs, ldx, nr, ys, ldy,
+                                       HM_F64 if vdt is None else vdt, flags, _stream_ptr(stream)))
 
 
 class Graph:

@@ -73,6 +73,8 @@ SIGNATURES = {
     "hm_matrix_stats": (c_int32, [c_void_p, P(Stats)]),
     "hm_plan_stats": (c_int32, [c_void_p, c_int32, P(Values), P(Precision), P(Stats)]),
     "hm_mvm": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p]),
+    "hm_mvm_batch": (c_int32, [P(c_void_p), c_int32, c_double, P(c_void_p), P(c_int64), P(c_int32),
+                               P(c_void_p), P(c_int64), c_int32, c_uint32, c_void_p]),
     "hm_graph_create": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p, P(c_void_p)]),
     "hm_graph_launch": (c_int32, [c_void_p, c_void_p]),
     "hm_graph_free": (None, [c_void_p]),

@@ -1,0 +1,465 @@
+// Many right-hand sides: Y += alpha * M * X for R columns at once.
+//
+// The plan is the one of the single-vector product (owners, items, tasks,
+// stages); only the inner operation changes.  With R columns a task is the
+// dense contraction C[nrows x R] = A[nrows x K] * B[K x R], where A is the
+// task's stored slab and B holds the inputs of its K columns (times their
+// column scales).  It runs on the matrix cores with the 16x16x4 MFMA
+// (float32, or float64 when the matrix accumulates in float64):
+//
+//   * lane l = 16*kq + rl loads the 16-byte tile row `rl` of tile kb + kq,
+//     so one wave load brings in 4 tiles of 16 rows (1 KiB);
+//   * element c of that tile row is the A operand A[rl][kq] of MFMA #c, the
+//     matching input value W[col(kb + kq, c)][j0 + rl] the B operand, so the
+//     V MFMAs of a load step cover all 4*V columns of the 4 tiles;
+//   * each wave owns up to 64 rows (4 row groups) and 16*NRB right-hand
+//     sides, and keeps 4*NRB accumulator tiles in registers.
+//
+// Vectors live in entry-major workspaces (value j of entry i at i*R + j), so
+// the B operands of 16 lanes are 16 consecutive values.  The input X is
+// gathered into cluster order and the output accumulated into a cluster-
+// order buffer; both are transposed through LDS to and from the caller's
+// column-major X and Y.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <new>
+#include <string>
+#include <type_traits>
+
+#include "hm_device.h"
+
+namespace hm {
+namespace mr {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int DT> struct Bytes;
+template <> struct Bytes<HM_F64> { static constexpr int v = 8; };
+template <> struct Bytes<HM_F32> { static constexpr int v = 4; };
+template <> struct Bytes<HM_BF16> { static constexpr int v = 2; };
+template <> struct Bytes<HM_F16> { static constexpr int v = 2; };
+template <> struct Bytes<HM_FP8E4M3> { static constexpr int v = 1; };
+
+__device__ __forceinline__ uint32_t word(const uint4& q, int i) {
+    return i == 0 ? q.x : i == 1 ? q.y : i == 2 ? q.z : q.w;
+}
+
+// element c (compile-time after unrolling) of a tile row, widened to T
+template <int DT, typename T>
+__device__ __forceinline__ T elem(const uint4& q, int c) {
+    if constexpr (DT == HM_F64) {
+        return (T)(c == 0 ? __hiloint2double((int)q.y, (int)q.x) : __hiloint2double((int)q.w, (int)q.z));
+    } else if constexpr (DT == HM_F32) {
+        return (T)__uint_as_float(word(q, c));
+    } else if constexpr (DT == HM_BF16) {
+        const uint32_t w = word(q, c >> 1);
+        return (T)__uint_as_float((c & 1) ? (w & 0xffff0000u) : (w << 16));
+    } else if constexpr (DT == HM_F16) {
+        const uint32_t w = word(q, c >> 1);
+        return (T)dev::f16_to_f32((uint16_t)((c & 1) ? (w >> 16) : (w & 0xffffu)));
+    } else {
+        return (T)dev::fp8_to_f32((uint8_t)(word(q, c >> 2) >> (8 * (c & 3))));
+    }
+}
+
+// A[i][k] comes from lane i + 16k, B[k][j] from lane j + 16k.  Result
+// element v of lane l = 16q + j is C[row(q, v)][j]: the float32 form holds
+// four consecutive rows per lane, the float64 form every fourth row.
+template <bool ACC64> struct Mfma;
+template <> struct Mfma<false> {
+    using T = float;
+    using V = f32x4;
+    __device__ static V step(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int q, int v) { return 4 * q + v; }
+};
+template <> struct Mfma<true> {
+    using T = double;
+    using V = f64x4;
+    __device__ static V step(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int q, int v) { return q + 4 * v; }
+};
+
+struct ItemPos {
+    int it, k0, k1, vec, sc;
+};
+
+template <int V>
+__device__ __forceinline__ ItemPos item_pos(const DItem* __restrict__ items, int it) {
+    const DItem d = items[it];
+    return ItemPos{it, d.tile0, d.tile0 + (d.ncols + V - 1) / V, d.vec_off, d.scale_off};
+}
+
+struct Outs {
+    double* wsm;        // coefficient outputs (mode 0), entry-major
+    float* wsm32;
+    double* ym;         // y outputs (modes 1, 2) in cluster order, entry-major
+    double* partm;      // partial sums of split owners
+    const double* scales;
+    int R;
+};
+
+__device__ __forceinline__ void put(const DTask& tk, const Outs& o, int row, int j, double v) {
+    if (tk.rscale_off >= 0) v *= o.scales[tk.rscale_off + row];
+    if (tk.ntasks > 1) {
+        o.partm[((int64_t)tk.part_off + (int64_t)tk.local * tk.nrows + row) * o.R + j] = v;
+    } else if (tk.mode == 0) {
+        const int64_t i = (int64_t)(tk.out_off + row) * o.R + j;
+        o.wsm[i] = v;
+        o.wsm32[i] = (float)v;
+    } else {
+        o.ym[(int64_t)(tk.out_off + row) * o.R + j] += v;
+    }
+}
+
+// Rows [r0, r0 + 16*nrg) of one task against right-hand sides [j0, j0 + 16*NRB).
+template <int DT, bool ACC64, int NRB>
+__device__ __forceinline__ void task_rows(const DTask& tk, int r0, int nrg, const DItem* __restrict__ items,
+                                          const uint8_t* __restrict__ data, const double* __restrict__ wsm,
+                                          const float* __restrict__ wsm32, int j0, int lane, const Outs& o) {
+    using M = Mfma<ACC64>;
+    using T = typename M::T;
+    constexpr int V = 16 / Bytes<DT>::v;
+    const int rl = lane & 15, kq = lane >> 4;
+    const int nrows = tk.nrows;
+    const int64_t rt = (int64_t)nrows * 16;
+    const uint8_t* base = data + tk.stream;
+    int rows[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) rows[g] = min(r0 + g * 16 + rl, nrows - 1);
+    typename M::V acc[4][NRB];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int b = 0; b < NRB; ++b) acc[g][b] = typename M::V{0, 0, 0, 0};
+    ItemPos st = item_pos<V>(items, tk.item_start);
+    const int R = o.R;
+    for (int kb = tk.k0; kb < tk.k1; kb += 4) {
+        const int tt = kb + kq;
+        const bool valid = tt < tk.k1;
+        const int tc = valid ? tt : tk.k1 - 1;    // lanes past the end re-read the last tile
+        while (tc >= st.k1) st = item_pos<V>(items, st.it + 1);
+        uint4 q[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            if (g < nrg) q[g] = *reinterpret_cast<const uint4*>(base + (int64_t)tc * rt + rows[g] * 16);
+        const int cb = (tc - st.k0) * V;
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            const int64_t wi = (int64_t)(st.vec + cb + c) * R + j0 + rl;
+            T sc = (T)1;
+            if (st.sc >= 0) sc = (T)o.scales[st.sc + cb + c];
+            if (!valid) sc = (T)0;
+            T bv[NRB];
+#pragma unroll
+            for (int b = 0; b < NRB; ++b) bv[b] = (ACC64 ? (T)wsm[wi + 16 * b] : (T)wsm32[wi + 16 * b]) * sc;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                if (g < nrg) {
+                    const T a = elem<DT, T>(q[g], c);
+#pragma unroll
+                    for (int b = 0; b < NRB; ++b) acc[g][b] = M::step(a, bv[b], acc[g][b]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        if (g >= nrg) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = r0 + g * 16 + M::row(kq, i);
+            if (row < nrows)
+#pragma unroll
+                for (int b = 0; b < NRB; ++b) put(tk, o, row, j0 + 16 * b + rl, (double)acc[g][b][i]);
+        }
+    }
+}
+
+// One wavefront per (task, block of 16*NRB right-hand sides); the blocks of
+// one task are adjacent waves, so the task's slab is read from HBM about once.
+template <bool ACC64, int NRB>
+__global__ __launch_bounds__(256) void k_tasks(const DTask* __restrict__ tasks, int ntasks, int nblk,
+                                               const DItem* __restrict__ items, const uint8_t* __restrict__ data,
+                                               const double* __restrict__ scales, double* wsm, float* wsm32,
+                                               double* __restrict__ ym, double* __restrict__ partm, int R) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * 4 + wave;
+    if (w >= ntasks * nblk) return;
+    const int t = w / nblk;
+    const int j0 = (w - t * nblk) * 16 * NRB;
+    const DTask tk = tasks[t];
+    const Outs o{wsm, wsm32, ym, partm, scales, R};
+    const int dt = tk.k0 < tk.k1 ? (int)items[tk.item_start].dtype : -1;
+    for (int r0 = 0; r0 < tk.nrows; r0 += 64) {
+        const int nrg = min(4, (tk.nrows - r0 + 15) / 16);
+        switch (dt) {
+            case HM_F64: task_rows<HM_F64, true, NRB>(tk, r0, nrg, items, data, wsm, wsm32, j0, lane, o); break;
+            case HM_F32: task_rows<HM_F32, ACC64, NRB>(tk, r0, nrg, items, data, wsm, wsm32, j0, lane, o); break;
+            case HM_BF16: task_rows<HM_BF16, ACC64, NRB>(tk, r0, nrg, items, data, wsm, wsm32, j0, lane, o); break;
+            case HM_F16: task_rows<HM_F16, ACC64, NRB>(tk, r0, nrg, items, data, wsm, wsm32, j0, lane, o); break;
+            case HM_FP8E4M3:
+                task_rows<HM_FP8E4M3, ACC64, NRB>(tk, r0, nrg, items, data, wsm, wsm32, j0, lane, o);
+                break;
+            default: {
+                // a task without columns contributes zero
+                for (int idx = lane; idx < 64 * 16 * NRB; idx += 64) {
+                    const int row = r0 + idx / (16 * NRB);
+                    if (row < tk.nrows) put(tk, o, row, j0 + idx % (16 * NRB), 0.0);
+                }
+            }
+        }
+    }
+}
+
+// Sum the partial results of split owners in task order, one wave per owner.
+__global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list, int nlist,
+                                                const DOwner* __restrict__ owners, const double* __restrict__ partm,
+                                                double* wsm, float* wsm32, double* __restrict__ ym, int R) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= nlist) return;
+    const DOwner ow = owners[list[i]];
+    const int64_t span = (int64_t)ow.nrows * R;
+    for (int64_t idx = lane; idx < span; idx += 64) {
+        const double* p = partm + (int64_t)ow.part_off * R + idx;
+        double v = 0.0;
+        for (int l = 0; l < ow.ntasks; ++l) v += p[(int64_t)l * span];
+        const int64_t e = (int64_t)ow.out_off * R + idx;
+        if (ow.mode == 0) {
+            wsm[e] = v;
+            wsm32[e] = (float)v;
+        } else {
+            ym[e] += v;
+        }
+    }
+}
+
+// X (column-major, ldx) -> wsm / wsm32 in cluster order, entry-major; the
+// padding columns j >= nrhs get zeros, and ym is cleared.  64 x 64 tiles
+// transposed through LDS.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_gather(const XT* __restrict__ X, int64_t ldx, int nrhs,
+                                                const int64_t* __restrict__ perm, int64_t n, int R,
+                                                double* __restrict__ wsm, float* __restrict__ wsm32,
+                                                double* __restrict__ ym) {
+    __shared__ double tile[64][65];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 64;
+    const int64_t i = i0 + tx;
+    const int64_t src = i < n ? (perm ? perm[i] : i) : 0;
+    for (int jj = ty; jj < 64; jj += 4) {
+        const int j = j0 + jj;
+        tile[jj][tx] = (i < n && j < nrhs) ? (double)X[src + (int64_t)j * ldx] : 0.0;
+    }
+    __syncthreads();
+    for (int ii = ty; ii < 64; ii += 4) {
+        const int64_t r = i0 + ii;
+        const int j = j0 + tx;
+        if (r < n && j < R) {
+            const double v = tile[tx][ii];
+            wsm[r * R + j] = v;
+            wsm32[r * R + j] = (float)v;
+            ym[r * R + j] = 0.0;
+        }
+    }
+}
+
+// Y[perm[i], j] += alpha * ym[i * R + j]  (column-major Y, ldy), via LDS.
+template <typename YT>
+__global__ __launch_bounds__(256) void k_scatter(YT* __restrict__ Y, int64_t ldy, int nrhs,
+                                                 const int64_t* __restrict__ perm, int64_t n, int R,
+                                                 const double* __restrict__ ym, double alpha) {
+    __shared__ double tile[64][65];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 64;
+    for (int ii = ty; ii < 64; ii += 4) {
+        const int64_t r = i0 + ii;
+        const int j = j0 + tx;
+        tile[ii][tx] = (r < n && j < R) ? ym[r * R + j] : 0.0;
+    }
+    __syncthreads();
+    const int64_t i = i0 + tx;
+    if (i < n) {
+        const int64_t dst = perm ? perm[i] : i;
+        for (int jj = ty; jj < 64; jj += 4) {
+            const int j = j0 + jj;
+            if (j < nrhs) {
+                YT* p = Y + dst + (int64_t)j * ldy;
+                *p = (YT)((double)*p + alpha * tile[tx][jj]);
+            }
+        }
+    }
+}
+
+using TaskKernel = void (*)(const DTask*, int, int, const DItem*, const uint8_t*, const double*, double*, float*,
+                            double*, double*, int);
+
+// [acc64][log2 NRB]
+static const TaskKernel kTasks[2][3] = {{&k_tasks<false, 1>, &k_tasks<false, 2>, &k_tasks<false, 4>},
+                                        {&k_tasks<true, 1>, &k_tasks<true, 2>, &k_tasks<true, 4>}};
+
+}  // namespace mr
+
+// Grow the matrix's many-RHS workspace to R values per entry.
+static hm_status ensure_mr(hm_matrix* m, int R) {
+    if (m->mr_cap >= R) return HM_OK;
+    if (m->mr_arena) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail("hm_mvm_batch: synchronize before regrowing the workspace", e);
+        (void)hipFree(m->mr_arena);
+        m->mr_arena = nullptr;
+        m->mr_cap = 0;
+    }
+    const size_t ent = (size_t)(m->ws_elems + TILE_PAD);
+    const size_t o_wsm = 0;
+    const size_t o_wsm32 = align256(o_wsm + ent * R * sizeof(double));
+    const size_t o_ym = align256(o_wsm32 + ent * R * sizeof(float));
+    const size_t o_part = align256(o_ym + (size_t)m->n * R * sizeof(double));
+    const size_t total = align256(o_part + (size_t)std::max<int64_t>(m->part_elems, 1) * R * sizeof(double));
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, total);
+    if (e != hipSuccess) {
+        set_error("hm_mvm_batch: hipMalloc of " + std::to_string(total) + " bytes of workspace failed");
+        return HM_ENOMEM;
+    }
+    // every workspace entry starts finite (padding columns of last tiles read them)
+    e = hipMemset(p, 0, total);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail("hm_mvm_batch: hipMemset", e);
+    }
+    uint8_t* b = (uint8_t*)p;
+    m->mr_arena = p;
+    m->mr_cap = R;
+    m->wsm = (double*)(b + o_wsm);
+    m->wsm32 = (float*)(b + o_wsm32);
+    m->ym = (double*)(b + o_ym);
+    m->partm = (double*)(b + o_part);
+    return HM_OK;
+}
+
+// Width of the padded right-hand-side block: 16, 32, 64 or a multiple of 64.
+static int padded_width(int nrhs) {
+    if (nrhs <= 16) return 16;
+    if (nrhs <= 32) return 32;
+    return (nrhs + 63) / 64 * 64;
+}
+
+static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx, int nrhs, void* Y, int64_t ldy,
+                          int32_t vdt, uint32_t flags, hipStream_t stream) {
+    const int R = padded_width(nrhs);
+    hm_status st = ensure_mr(m, R);
+    if (st != HM_OK) return st;
+    const int nrb = std::min(R, 64) / 16;          // 1, 2 or 4 blocks of 16 per wave
+    const int lg = nrb == 1 ? 0 : nrb == 2 ? 1 : 2;
+    const int nblk = R / (16 * nrb);
+    const int64_t n = m->n;
+    const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : m->perm;
+    dim3 tgrid((unsigned)((n + 63) / 64), (unsigned)((R + 63) / 64));
+    if (vdt == HM_F64)
+        hipLaunchKernelGGL(mr::k_gather<double>, tgrid, dim3(256), 0, stream, (const double*)X, ldx, nrhs, perm, n, R,
+                           m->wsm, m->wsm32, m->ym);
+    else
+        hipLaunchKernelGGL(mr::k_gather<float>, tgrid, dim3(256), 0, stream, (const float*)X, ldx, nrhs, perm, n, R,
+                           m->wsm, m->wsm32, m->ym);
+    const hipStream_t main_stream = stream;
+    if (m->aux) {
+        (void)hipEventRecord(m->ev_fork, main_stream);
+        (void)hipStreamWaitEvent(m->aux, m->ev_fork, 0);
+    }
+    bool joined = m->aux == nullptr;
+    for (auto& ph : m->phases) {
+        hipStream_t s = ph.aux ? m->aux : main_stream;
+        if (!joined && !ph.aux && ph.ntasks == 0 && &ph == &m->phases.back()) {
+            (void)hipEventRecord(m->ev_join, m->aux);
+            (void)hipStreamWaitEvent(main_stream, m->ev_join, 0);
+            joined = true;
+        }
+        if (ph.ntasks > 0) {
+            const int64_t waves = (int64_t)ph.ntasks * nblk;
+            hipLaunchKernelGGL(mr::kTasks[m->acc64 ? 1 : 0][lg], dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
+                               m->tasks + ph.t0, ph.ntasks, nblk, m->items, m->data, m->scales, m->wsm, m->wsm32,
+                               m->ym, m->partm, R);
+        }
+        if (ph.nreduce > 0)
+            hipLaunchKernelGGL(mr::k_reduce, dim3((unsigned)((ph.nreduce + 3) / 4)), dim3(256), 0, s, ph.reduce,
+                               ph.nreduce, m->owners, m->partm, m->wsm, m->wsm32, m->ym, R);
+    }
+    if (!joined) {
+        (void)hipEventRecord(m->ev_join, m->aux);
+        (void)hipStreamWaitEvent(main_stream, m->ev_join, 0);
+    }
+    if (vdt == HM_F64)
+        hipLaunchKernelGGL(mr::k_scatter<double>, tgrid, dim3(256), 0, main_stream, (double*)Y, ldy, nrhs, perm, n, R,
+                           m->ym, alpha);
+    else
+        hipLaunchKernelGGL(mr::k_scatter<float>, tgrid, dim3(256), 0, main_stream, (float*)Y, ldy, nrhs, perm, n, R,
+                           m->ym, alpha);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail("hm_mvm_batch: kernel launch", e);
+    return HM_OK;
+}
+
+}  // namespace hm
+
+extern "C" hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double alpha, const void* const* X,
+                                  const int64_t* ldx, const int32_t* nrhs, void* const* Y, const int64_t* ldy,
+                                  int32_t vec_dtype, uint32_t flags, hm_stream_t stream) {
+    if (nmat < 0 || (nmat > 0 && (!mats || !X || !ldx || !nrhs || !Y || !ldy))) {
+        hm::set_error("hm_mvm_batch: null argument");
+        return HM_EINVAL;
+    }
+    if (vec_dtype != HM_F64 && vec_dtype != HM_F32) {
+        hm::set_error("hm_mvm_batch: vec_dtype must be HM_F64 or HM_F32");
+        return HM_EINVAL;
+    }
+    if (flags & ~(uint32_t)HM_CLUSTER_ORDER) {
+        hm::set_error("hm_mvm_batch: unsupported flags");
+        return HM_EINVAL;
+    }
+    int dev = -1;
+    if (nmat > 0 && hipGetDevice(&dev) != hipSuccess) {
+        hm::set_error("hm_mvm_batch: no current device");
+        return HM_EDEVICE;
+    }
+    for (int32_t i = 0; i < nmat; ++i) {
+        const hm_matrix* m = mats[i];
+        if (!m || nrhs[i] < 0 || nrhs[i] > HM_MAX_NRHS) {
+            hm::set_error("hm_mvm_batch: null matrix or nrhs out of [0, HM_MAX_NRHS] at index " + std::to_string(i));
+            return HM_EINVAL;
+        }
+        if (nrhs[i] == 0) continue;
+        if (!X[i] || !Y[i] || X[i] == Y[i] || ldx[i] < m->n || ldy[i] < m->n) {
+            hm::set_error("hm_mvm_batch: bad X/Y or leading dimension at index " + std::to_string(i));
+            return HM_EINVAL;
+        }
+        if (m->device != dev) {
+            hm::set_error("hm_mvm_batch: matrix " + std::to_string(i) + " lives on another device");
+            return HM_EINVAL;
+        }
+        for (int32_t k = 0; k < i; ++k)
+            if (mats[k] == m && nrhs[k] > 0) {
+                hm::set_error("hm_mvm_batch: a matrix appears twice (its workspace is shared)");
+                return HM_EINVAL;
+            }
+    }
+    for (int32_t i = 0; i < nmat; ++i) {
+        if (nrhs[i] == 0) continue;
+        hm_status st;
+        if (nrhs[i] == 1 && vec_dtype == HM_F64)
+            st = hm_mvm(mats[i], alpha, (const double*)X[i], (double*)Y[i], flags, stream);
+        else
+            st = hm::mvm_many(mats[i], alpha, X[i], ldx[i], nrhs[i], Y[i], ldy[i], vec_dtype, flags,
+                              (hipStream_t)stream);
+        if (st != HM_OK) return st;
+    }
+    return HM_OK;
+}

@@ -1,0 +1,149 @@
+// Device-side definitions shared by the single- and many-right-hand-side
+// engines: storage decoders, the uploaded matrix object and its stages.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hm_pack.h"
+
+namespace hm {
+namespace dev {
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float f16_to_f32(uint16_t b) {
+    _Float16 h;
+    __builtin_memcpy(&h, &b, 2);
+    return (float)h;
+}
+
+// OCP FP8 E4M3: sign | 4-bit exponent (bias 7) | 3-bit mantissa, no infinities.
+__device__ __forceinline__ float fp8_to_f32(uint8_t b) {
+    const uint32_t e = (b >> 3) & 15u, m = b & 7u;
+    float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
+    return (b & 0x80u) ? -mag : mag;
+}
+
+// A 16-byte tile row holds V = 16 / element-size consecutive columns of one
+// slab row.  decode<DT> widens the V stored values (float32 for the
+// narrow formats, float64 for FP64).
+template <int DT> struct Tile;
+template <> struct Tile<HM_F64> {
+    static constexpr int V = 2;
+    using R = double;
+    __device__ static void decode(const uint4& q, R* o) {
+        o[0] = __hiloint2double((int)q.y, (int)q.x);
+        o[1] = __hiloint2double((int)q.w, (int)q.z);
+    }
+};
+template <> struct Tile<HM_F32> {
+    static constexpr int V = 4;
+    using R = float;
+    __device__ static void decode(const uint4& q, R* o) {
+        o[0] = __uint_as_float(q.x);
+        o[1] = __uint_as_float(q.y);
+        o[2] = __uint_as_float(q.z);
+        o[3] = __uint_as_float(q.w);
+    }
+};
+template <> struct Tile<HM_BF16> {
+    static constexpr int V = 8;
+    using R = float;
+    __device__ static void decode(const uint4& q, R* o) {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = __uint_as_float(w[i] << 16);
+            o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        }
+    }
+};
+template <> struct Tile<HM_F16> {
+    static constexpr int V = 8;
+    using R = float;
+    __device__ static void decode(const uint4& q, R* o) {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = f16_to_f32((uint16_t)(w[i] & 0xffffu));
+            o[2 * i + 1] = f16_to_f32((uint16_t)(w[i] >> 16));
+        }
+    }
+};
+template <> struct Tile<HM_FP8E4M3> {
+    static constexpr int V = 16;
+    using R = float;
+    __device__ static void decode(const uint4& q, R* o) {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) o[4 * i + b] = fp8_to_f32((uint8_t)(w[i] >> (8 * b)));
+    }
+};
+
+}  // namespace dev
+
+struct DevStage {
+    bool aux;
+    int64_t t0;
+    int32_t ntasks, nreduce, nowners;
+    const int32_t* reduce;
+    int32_t dtype_mask;
+    int64_t data_bytes;
+    double alg_bytes;
+    std::string name;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;   // HM_TIMING event pairs
+};
+
+}  // namespace hm
+
+struct hm_matrix {
+    const hm_layout* layout = nullptr;
+    int32_t format = 0;
+    int32_t acc64 = 1;
+    int64_t n = 0;
+    int device = 0;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    int64_t* perm = nullptr;
+    uint8_t* data = nullptr;
+    double* scales = nullptr;
+    double* ws = nullptr;
+    float* ws32 = nullptr;
+    double* part = nullptr;
+    const hm::DOwner* owners = nullptr;
+    const hm::DItem* items = nullptr;
+    const hm::DTask* tasks = nullptr;
+    std::vector<hm::DevStage> phases;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+    // second stream for the independent dense stage, with fork/join events
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hm_stats stats{};
+    int64_t ws_elems = 0;      // x in cluster order + coefficient vectors
+    int64_t part_elems = 0;    // partial sums of split owners
+    // many-right-hand-side workspace (grown on demand): R values per entry
+    // of ws / ws32 / part, entry-major (value j of entry i at i * R + j)
+    void* mr_arena = nullptr;
+    int32_t mr_cap = 0;
+    double* wsm = nullptr;
+    float* wsm32 = nullptr;
+    double* ym = nullptr;      // y contributions in cluster order
+    double* partm = nullptr;
+};
+
+namespace hm {
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+inline hm_status hip_fail(const char* what, hipError_t e) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return HM_EDEVICE;
+}
+
+}  // namespace hm

@@ -21,7 +21,7 @@
 #include <string>
 #include <vector>
 
-#include "hm_pack.h"
+#include "hm_device.h"
 
 namespace hm {
 
@@ -30,78 +30,6 @@ void set_error(const std::string& msg) { g_err = msg; }
 
 namespace dev {
 
-__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-__device__ __forceinline__ float f16_to_f32(uint16_t b) {
-    _Float16 h;
-    __builtin_memcpy(&h, &b, 2);
-    return (float)h;
-}
-
-// OCP FP8 E4M3: sign | 4-bit exponent (bias 7) | 3-bit mantissa, no infinities.
-__device__ __forceinline__ float fp8_to_f32(uint8_t b) {
-    const uint32_t e = (b >> 3) & 15u, m = b & 7u;
-    float mag = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
-    return (b & 0x80u) ? -mag : mag;
-}
-
-// A 16-byte tile row holds V = 16 / element-size consecutive columns of one
-// slab row.  decode<DT> widens the V stored values (float32 for the
-// narrow formats, float64 for FP64).
-template <int DT> struct Tile;
-template <> struct Tile<HM_F64> {
-    static constexpr int V = 2;
-    using R = double;
-    __device__ static void decode(const uint4& q, R* o) {
-        o[0] = __hiloint2double((int)q.y, (int)q.x);
-        o[1] = __hiloint2double((int)q.w, (int)q.z);
-    }
-};
-template <> struct Tile<HM_F32> {
-    static constexpr int V = 4;
-    using R = float;
-    __device__ static void decode(const uint4& q, R* o) {
-        o[0] = __uint_as_float(q.x);
-        o[1] = __uint_as_float(q.y);
-        o[2] = __uint_as_float(q.z);
-        o[3] = __uint_as_float(q.w);
-    }
-};
-template <> struct Tile<HM_BF16> {
-    static constexpr int V = 8;
-    using R = float;
-    __device__ static void decode(const uint4& q, R* o) {
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            o[2 * i] = __uint_as_float(w[i] << 16);
-            o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
-        }
-    }
-};
-template <> struct Tile<HM_F16> {
-    static constexpr int V = 8;
-    using R = float;
-    __device__ static void decode(const uint4& q, R* o) {
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            o[2 * i] = f16_to_f32((uint16_t)(w[i] & 0xffffu));
-            o[2 * i + 1] = f16_to_f32((uint16_t)(w[i] >> 16));
-        }
-    }
-};
-template <> struct Tile<HM_FP8E4M3> {
-    static constexpr int V = 16;
-    using R = float;
-    __device__ static void decode(const uint4& q, R* o) {
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) o[4 * i + b] = fp8_to_f32((uint8_t)(w[i] >> (8 * b)));
-    }
-};
 
 // Accumulate one tile row.  WIDE: float64 accumulator with float64 inputs
 // w; otherwise float32 accumulator with the float32 mirror of the inputs.
@@ -381,55 +309,13 @@ static const std::array<TaskKernel, 32> kTasks[2] = {task_kernels<false>(std::ma
 
 }  // namespace dev
 
-struct DevStage {
-    bool aux;
-    int64_t t0;
-    int32_t ntasks, nreduce, nowners;
-    const int32_t* reduce;
-    int32_t dtype_mask;
-    int64_t data_bytes;
-    double alg_bytes;
-    std::string name;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;   // HM_TIMING event pairs
-};
 
 }  // namespace hm
 
-struct hm_matrix {
-    const hm_layout* layout = nullptr;
-    int32_t format = 0;
-    int32_t acc64 = 1;
-    int64_t n = 0;
-    int device = 0;
-    void* arena = nullptr;
-    size_t arena_bytes = 0;
-    int64_t* perm = nullptr;
-    uint8_t* data = nullptr;
-    double* scales = nullptr;
-    double* ws = nullptr;
-    float* ws32 = nullptr;
-    double* part = nullptr;
-    const hm::DOwner* owners = nullptr;
-    const hm::DItem* items = nullptr;
-    const hm::DTask* tasks = nullptr;
-    std::vector<hm::DevStage> phases;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
-    // second stream for the independent dense stage, with fork/join events
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hm_stats stats{};
-};
 
-namespace {
 
-size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
-
-hm_status hip_fail(const char* what, hipError_t e) {
-    hm::set_error(std::string(what) + ": " + hipGetErrorString(e));
-    return HM_EDEVICE;
-}
-
-}  // namespace
+using hm::align256;
+using hm::hip_fail;
 
 extern "C" const char* hm_last_error(void) { return hm::g_err.c_str(); }
 extern "C" const char* hm_version(void) { return "hm 0.1 gfx950"; }
@@ -559,6 +445,8 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         }
     }
     m->stats = P.stats;
+    m->ws_elems = P.ws_elems;
+    m->part_elems = P.part_elems;
     if (nlaunch != P.stats.nlaunch) {
         hm_matrix_free(m);
         hm::set_error("hm_upload: launch count mismatch");
@@ -580,6 +468,7 @@ extern "C" void hm_matrix_free(hm_matrix* m) {
     if (m->ev_join) (void)hipEventDestroy(m->ev_join);
     if (m->aux) (void)hipStreamDestroy(m->aux);
     if (m->arena) (void)hipFree(m->arena);
+    if (m->mr_arena) (void)hipFree(m->mr_arena);
     delete m;
 }
 

@@ -1,0 +1,144 @@
+"""GPU parity of the many-right-hand-side path (hm_mvm_batch) against the
+oracle, column by column, on the same stored matrix.
+
+Tolerances (relative L2 of each column's increment):
+  * float64 data and float64 accumulation (float64 MFMA): 1e-10;
+  * float32 accumulation (float32 MFMA on the stored values): 1e-6;
+  * float32 vectors: the oracle gets X rounded to float32; 1e-6.
+Widths cover one 16-wide block, a ragged block, several 64-wide blocks and
+a ragged tail; the leading dimensions differ from n."""
+import numpy as np
+import pytest
+
+from conftest import cached
+from oracle import stored, trees
+from synth import KERNEL_LAPLACE, compress_h, gaussian_matrix, sphere_points, to_h2, to_uh
+
+pytestmark = pytest.mark.gpu
+
+POLICIES = {
+    "f64": (dict(dense="f64", factor="f64", eps=1e-8), 1e-10),
+    "f32": (dict(dense="f32", factor="f32", eps=1e-6), 1e-6),
+    "bf16": (dict(dense="f32", diag="f64", factor="bf16", coupling="f32", eps=1e-6), 1e-6),
+    "fp8": (dict(dense="f32", diag="f64", factor="fp8", coupling="fp8", eps=1e-6), 1e-6),
+    "valr6": (dict(dense="valr", diag="valr", factor="valr", eps=1e-6), 1e-6),
+    "valr8": (dict(dense="valr", diag="valr", factor="valr", eps=1e-8), 1e-10),
+}
+
+
+def case(n=2048, seed=1001):
+    def build():
+        import paper_2405_03456_amd as hm
+        p = sphere_points(n, seed)
+        st = trees.build_structure(p)
+        lay = hm.Layout(p)
+        h = compress_h(p, KERNEL_LAPLACE, st, 1e-8, method="svd")
+        return st, lay, {"h": h, "uh": to_uh(h, st), "h2": to_h2(h, st)}
+    return cached(("batch", n, seed), build)
+
+
+def colerr(out, ref, y0):
+    d = np.linalg.norm(out - ref, axis=0)
+    s = np.maximum(np.linalg.norm(ref - y0, axis=0), 1e-300)
+    return (d / s).max()
+
+
+def padded(torch, A, ld, dtype):
+    """A column-major device copy of A with leading dimension ld >= n."""
+    n, r = A.shape
+    buf = torch.zeros((r, ld), dtype=dtype, device="cuda")
+    buf[:, :n] = torch.from_numpy(np.ascontiguousarray(A.T)).to(dtype)
+    return buf.T[:n, :]
+
+
+@pytest.mark.parametrize("fmt", ["h", "uh", "h2"])
+@pytest.mark.parametrize("pol", list(POLICIES))
+@pytest.mark.parametrize("r", [5, 16, 33, 130])
+def test_batch_parity(fmt, pol, r):
+    import torch
+    import paper_2405_03456_amd as hm
+    st, lay, vals = case()
+    pp, tol = POLICIES[pol]
+    n = st.n
+    print(f"case batch fmt={fmt} policy={pol} r={r}", flush=True)
+    X, Y = gaussian_matrix(n, r, 2000 + r), gaussian_matrix(n, r, 3000 + r)
+    sv = stored.stored_values(st, fmt, vals[fmt], dense=pp["dense"], diag=pp.get("diag"),
+                              factor=pp["factor"], coupling=pp.get("coupling"), eps=pp["eps"])
+    ref = stored.product_many(st, fmt, sv, -0.5, X, Y)
+    M = hm.Matrix(lay, fmt, vals[fmt], **pp)
+    Xd, Yd = padded(torch, X, n + 7, torch.float64), padded(torch, Y, n + 3, torch.float64)
+    M.mvm_many(Xd, Yd, alpha=-0.5)
+    torch.cuda.synchronize()
+    err = colerr(Yd.cpu().numpy(), ref, Y)
+    print(f"  worst column rel err {err:.3e} (tol {tol:g})", flush=True)
+    M.free()
+    assert err <= tol
+
+
+@pytest.mark.parametrize("fmt", ["h", "uh", "h2"])
+def test_batch_f32_vectors_and_cluster_order(fmt):
+    import torch
+    import paper_2405_03456_amd as hm
+    st, lay, vals = case()
+    n, r = st.n, 24
+    pp = POLICIES["f32"][0]
+    X = gaussian_matrix(n, r, 7).astype(np.float32).astype(np.float64)
+    Y = gaussian_matrix(n, r, 8).astype(np.float32).astype(np.float64)
+    sv = stored.stored_values(st, fmt, vals[fmt], dense="f32", factor="f32", eps=1e-6)
+    ref = stored.product_many(st, fmt, sv, 1.0, X, Y)
+    M = hm.Matrix(lay, fmt, vals[fmt], **pp)
+    Xd, Yd = padded(torch, X, n, torch.float32), padded(torch, Y, n, torch.float32)
+    M.mvm_many(Xd, Yd)
+    # cluster order: the same product on permuted vectors
+    Xc, Yc = padded(torch, X[st.perm], n, torch.float64), padded(torch, Y[st.perm], n, torch.float64)
+    M.mvm_many(Xc, Yc, cluster_order=True)
+    torch.cuda.synchronize()
+    assert colerr(Yd.double().cpu().numpy(), ref, Y) <= 1e-6
+    assert colerr(Yc.cpu().numpy(), ref[st.perm], Y[st.perm]) <= 1e-6
+    M.free()
+
+
+def test_batch_several_matrices_one_call():
+    """Three matrices of different formats and widths in one hm_mvm_batch,
+    including a width-1 float64 entry (the single-vector kernels) and an
+    empty one; each result equals its own single-matrix call bitwise."""
+    import torch
+    import paper_2405_03456_amd as hm
+    st, lay, vals = case()
+    n = st.n
+    pp = POLICIES["valr6"][0]
+    Ms = [hm.Matrix(lay, f, vals[f], **pp) for f in ("h", "uh", "h2", "h")]
+    widths = [1, 40, 17, 0]
+    Xs = [padded(torch, gaussian_matrix(n, max(r, 1), 40 + i), n, torch.float64)[:, :r] for i, r in enumerate(widths)]
+    Ys = [padded(torch, gaussian_matrix(n, max(r, 1), 50 + i), n, torch.float64)[:, :r] for i, r in enumerate(widths)]
+    Y0 = [y.clone() for y in Ys]
+    hm.mvm_batch(Ms, Xs, Ys, alpha=0.75)
+    for M, x, y in zip(Ms[:3], Xs[:3], Y0[:3]):
+        if x.shape[1] == 1:
+            yy = y[:, 0].contiguous()
+            M.mvm(x[:, 0].contiguous(), yy, alpha=0.75)
+            y[:, 0] = yy
+        else:
+            M.mvm_many(x, y, alpha=0.75)
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert torch.equal(Ys[i], Y0[i]), i
+    for M in Ms:
+        M.free()
+
+
+def test_batch_errors():
+    import torch
+    import paper_2405_03456_amd as hm
+    st, lay, vals = case()
+    n = st.n
+    M = hm.Matrix(lay, "h", vals["h"], dense="f32", factor="f32", eps=1e-6)
+    X = torch.zeros((n, 4), dtype=torch.float64, device="cuda")   # row-major: rejected by the binding
+    with pytest.raises(ValueError):
+        M.mvm_many(X, X.clone())
+    Xc = padded(torch, np.zeros((n, 4)), n, torch.float64)
+    with pytest.raises(hm.HMError):                                 # the same matrix twice
+        hm.mvm_batch([M, M], [Xc, Xc.clone()], [Xc.clone(), Xc.clone()])
+    with pytest.raises(hm.HMError):                                 # X == Y
+        hm.mvm_batch([M], [Xc], [Xc])
+    M.free()

@@ -247,3 +247,18 @@ def test_planted_mistake_is_caught():
     bad = mvm.h_mvm(st, h.dense, W, h.sigma, h.X, 1.0, x, y)
     yd = dense.dense_product(KERNEL_LAPLACE, p, 1.0, x, y)
     assert rel(bad, yd, yd) > 1e-6
+
+
+@pytest.mark.parametrize("fmt", ["h", "uh", "h2"])
+def test_product_many_closed_forms(fmt):
+    """Many right-hand sides (one product per column): identity kernel gives
+    Y + alpha X, constant kernel Y + alpha (column sums - X)."""
+    from oracle import stored
+    from synth import gaussian_matrix
+    for kernel, n in ((KERNEL_IDENTITY, 700), (KERNEL_CONST, 900)):
+        p, st, h = setup(n, kernel, 1e-10 if kernel == KERNEL_IDENTITY else 1e-12)
+        vals = {"h": h, "uh": to_uh(h, st), "h2": to_h2(h, st)}[fmt]
+        X, Y = gaussian_matrix(n, 5, 11), gaussian_matrix(n, 5, 12)
+        out = stored.product_many(st, fmt, vals, -0.5, X, Y)
+        ref = Y - 0.5 * (X if kernel == KERNEL_IDENTITY else X.sum(axis=0)[None, :] - X)
+        assert np.abs(out - ref).max() < 1e-11 * np.abs(ref).max()
