@@ -200,6 +200,98 @@ def cpu_baseline(fmt, st, vals, x, budget_s, gpu_results, points, eps):
     return dt, reps, cores, errs
 
 
+MFMA_PEAK_TFS = {True: 78.6, False: 157.3}     # float64 / float32 dense matrix-core peaks
+
+MANY_POLICIES = {
+    "f64": dict(dense="f64", factor="f64", coupling="f64"),
+    "f32": dict(dense="f32", factor="f32", coupling="f32"),
+    "bf16": dict(dense="bf16", factor="bf16", coupling="bf16"),
+}
+
+
+def many_rhs(args, hm, torch, lay, fmt, vals, eps, n, points, st, desc):
+    """Blocks of r right-hand sides through hm_mvm_batch (graph-replayed),
+    per storage policy; per-kernel MFMA roofline from event-timed launches."""
+    from synth import gaussian_matrix
+    widths = [int(v) for v in args.nrhs.split(",")]
+    pols = args.policies.split(",")
+    rows = []
+    base_ms = None
+    Xall = gaussian_matrix(n, max(widths), 2004)
+    for pname in pols:
+        M = hm.Matrix(lay, fmt, vals, eps=eps, **MANY_POLICIES[pname])
+        ref = None
+        if not args.no_cpu:
+            from oracle import stored as ostored
+            from oracle import trees as otrees
+            ost = otrees.build_structure(points)
+            sv = ostored.stored_values(ost, fmt, vals, eps=eps, **MANY_POLICIES[pname])
+            ref = ostored.product(ost, fmt, sv, 1.0, Xall[:, 0], np.zeros(n))
+            del sv
+        s = M.stats()
+        entries = sum(s["entries_per_dtype"])
+        stored_b = s["bytes_dense"] + s["bytes_factors"] + s["bytes_coupling"] + s["bytes_transfer"]
+        acc64 = s["accum"] == hm.HM_ACC_F64
+        for r in widths:
+            X = torch.from_numpy(np.ascontiguousarray(Xall[:, :r].T)).cuda().T
+            Y = torch.zeros((r, n), dtype=torch.float64, device="cuda").T
+            tuned = None
+            if r == 1:
+                X, Y = X[:, 0].contiguous(), Y[:, 0].contiguous()
+            elif not args.no_tune:
+                tuned = M.tune(r, reps=3)
+            g = hm.BatchGraph([M], [X], [Y])
+            for _ in range(args.warmup):
+                g.launch()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                g.launch()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            g.free()
+            M.timing()
+            for _ in range(max(3, args.steps // 5)):
+                hm.mvm_batch([M], [X], [Y], timing=True)
+            torch.cuda.synchronize()
+            ph = [p for p in M.timing() if p["launches"] > 0]
+            dom = max(ph, key=lambda p: p["ms_total"] / p["launches"])
+            us = dom["ms_total"] * 1e3 / dom["launches"]
+            flops = 2.0 * dom["data_entries"] * r
+            gbs_dom = dom["data_bytes"] / (us * 1e-6) / 1e9
+            alg = stored_b + s["bytes_scales"] + s["bytes_meta"] + 24.0 * n * r
+            row = {"policy": pname, "nrhs": r, "ms_per_step": round(ms, 4), "tuned": tuned,
+                   "columns_per_s": round(r * 1e3 / ms, 1), "GBs": round(alg / (ms * 1e-3) / 1e9, 1),
+                   "TFLOPs": round(2.0 * entries * r / (ms * 1e-3) / 1e12, 2),
+                   "dominant": {"phase": dom["name"], "avg_launch_us": round(us, 2),
+                                "data_GBs": round(gbs_dom, 1),
+                                "TFLOPs": round(flops / (us * 1e-6) / 1e12, 2),
+                                "mfma_peak_TFLOPs": None if r == 1 else MFMA_PEAK_TFS[acc64 or pname == "f64"]}}
+            if pname == "f64" and r == 1:
+                base_ms = ms
+            if base_ms is not None:
+                row["speedup_vs_f64_single_per_column"] = round(base_ms * r / ms, 2)
+            # accuracy of the first column against the oracle on the same stored values
+            if ref is not None:
+                got = (Y if r == 1 else Y[:, 0]).cpu().numpy() / (args.warmup + args.steps + max(3, args.steps // 5))
+                row["rel_err_col0_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            row["phases"] = [{"name": p["name"], "ntasks": p["ntasks"],
+                              "us": round(p["ms_total"] * 1e3 / p["launches"], 1),
+                              "TFLOPs": round(2.0 * p["data_entries"] * r / (p["ms_total"] * 1e-3 / p["launches"])
+                                              / 1e12, 2)} for p in ph]
+            log(f"[bench] {json.dumps(row)}")
+            rows.append(row)
+            del X, Y
+        M.free()
+    best = max(rows, key=lambda r: r["columns_per_s"])
+    out = {"metric": "H-MVM many-RHS matvec columns/s (hm_mvm_batch)", "value": best["columns_per_s"],
+           "unit": "columns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": best["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic (seeded sphere points, Laplace kernel, ACA-compressed)",
+           "config": {"workload": desc, "format": fmt, "n": n, "eps": eps}, "runs": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +304,10 @@ def main():
                     help="after timing, run a plain 1 GiB device copy (known traffic) to scale PMC counters")
     ap.add_argument("--copies-bytes", type=float, default=2.0e9,
                     help="upload copies until the rotated set exceeds this many bytes")
+    ap.add_argument("--nrhs", default=None,
+                    help="comma-separated block widths: run the many-right-hand-side path instead")
+    ap.add_argument("--policies", default="f32,bf16", help="storage policies of the --nrhs runs")
+    ap.add_argument("--no-tune", action="store_true", help="--nrhs runs: keep the default plan parameters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
@@ -231,6 +327,9 @@ def main():
     st = structure_from_layout(lay)
     vals = make_values(fmt, points, st, eps)
     log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f}s (n={n}, fmt={fmt}, blocks={st.nblocks})")
+    if args.nrhs:
+        many_rhs(args, hm, torch, lay, fmt, vals, eps, n, points, st, desc)
+        return
     x_np = gaussian_vector(n, xseed)
     x = torch.from_numpy(x_np).cuda()
 

@@ -214,7 +214,7 @@ hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double* y, uint32_
  * float32 (HM_F32).  mats, X, ldx, nrhs, Y, ldy are host arrays of nmat
  * entries; the vectors are caller-owned and X_i must not overlap Y_i.
  * nrhs[i] in [0, HM_MAX_NRHS]; 0 skips the entry.  One matrix may appear
- * only once per call.  flags: HM_CLUSTER_ORDER as for hm_mvm.
+ * only once per call.  flags: HM_CLUSTER_ORDER and HM_TIMING as for hm_mvm.
  * A single float64 column runs the hm_mvm kernels; wider blocks run the
  * matrix-core path (16x16x4 MFMA, float32 products and accumulation, or
  * float64 throughout for float64 data and for matrices that accumulate in
@@ -228,6 +228,25 @@ hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double alpha, const
                        const int64_t* ldx, const int32_t* nrhs, void* const* Y, const int64_t* ldy,
                        int32_t vec_dtype, uint32_t flags, hm_stream_t stream);
 
+/* Autotuner of the many-right-hand-side path.  The engine's two free
+ * parameters are the column-chunk size of a task (bytes of stored data per
+ * 64-row group: 64 KiB ... 1 MiB) and the number of 16-wide right-hand-side
+ * blocks one wave carries (1 or 2).  hm_tune_batch times every candidate
+ * with `reps` products of an nrhs-wide zero block (allocated and freed
+ * here), keeps the fastest for this matrix and reports it.  It allocates,
+ * synchronises and rebuilds the plan: call it outside graph capture, before
+ * creating graphs of the matrix.  Results of later products may differ from
+ * earlier ones in rounding (a different summation order), within the
+ * accumulation tolerance. */
+typedef struct {
+    int64_t target_bytes;   /* chosen column-chunk size */
+    int32_t nrb;            /* chosen 16-wide blocks per wave */
+    double ms;              /* its mean time per product */
+    int32_t ncandidates;    /* candidates timed */
+} hm_tune_result;
+hm_status hm_tune_batch(hm_matrix* m, int32_t nrhs, int32_t vec_dtype, int32_t reps, hm_stream_t stream,
+                        hm_tune_result* out);
+
 /* A product captured into a HIP graph: the kernels of one hm_mvm call with
  * fixed (alpha, x, y, flags) recorded once and replayed with one launch.
  * Replays read x and update y in place exactly like hm_mvm; results are
@@ -236,16 +255,25 @@ hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double alpha, const
 typedef struct hm_graph hm_graph;
 hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x, double* y, uint32_t flags,
                           hm_stream_t stream, hm_graph** out);
+/* The same for one hm_mvm_batch call (fixed matrices, blocks and alpha).
+ * The matrices' many-RHS workspaces are sized before the capture, so the
+ * recorded work allocates nothing and holds no memset nodes. */
+hm_status hm_graph_create_batch(hm_matrix* const* mats, int32_t nmat, double alpha, const void* const* X,
+                                const int64_t* ldx, const int32_t* nrhs, void* const* Y, const int64_t* ldy,
+                                int32_t vec_dtype, uint32_t flags, hm_stream_t stream, hm_graph** out);
 hm_status hm_graph_launch(hm_graph* g, hm_stream_t stream);
 void hm_graph_free(hm_graph* g);
 
-/* Per-phase kernel timing.  Every hm_mvm call made with HM_TIMING records a
+/* Per-phase kernel timing.  Every hm_mvm (or hm_mvm_batch) call made with HM_TIMING records a
  * HIP event pair on its stream around each phase's main kernel; this call
  * waits for the recorded events, returns the accumulated times and clears
- * them.  out[i] for i < min(cap, number of phases); *nphase = number of
- * phases.  Names are owned by the matrix.  algorithmic_bytes is what the
- * phase kernel must move per launch: its stored matrix data, the scales and
- * distinct input elements it reads, and the outputs it writes. */
+ * them.  The phases of the single-vector plan come first, then those of
+ * the many-right-hand-side plan (empty until hm_mvm_batch has run a block
+ * wider than one float64 column).  out[i] for i < min(cap, number of
+ * phases); *nphase = number of phases.  Names are owned by the matrix.
+ * algorithmic_bytes is what a single-vector phase kernel must move per
+ * launch: its stored matrix data, the scales and distinct input elements it
+ * reads, and the outputs it writes. */
 typedef struct {
     const char* name;
     double ms_total;
@@ -253,6 +281,11 @@ typedef struct {
     double algorithmic_bytes;
     int32_t ntasks;
     int32_t nowners;
+    int64_t data_bytes;      /* stored matrix bytes its tasks stream per launch */
+    int64_t data_entries;    /* stored matrix entries streamed (tile padding included) */
+    int32_t nrhs;            /* padded block width of the timed launches (1 = single vector);
+                                launches of different widths are not mixed: timing
+                                an hm_mvm_batch call discards pending hm_mvm timings */
 } hm_phase_timing;
 
 hm_status hm_timing_read(hm_matrix* m, hm_phase_timing* out, int32_t cap, int32_t* nphase);

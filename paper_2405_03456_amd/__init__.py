@@ -193,9 +193,16 @@ class Matrix:
         flags = (HM_CLUSTER_ORDER if cluster_order else 0) | (_lib.HM_TIMING if timing else 0)
         _lib.check(_lib.lib().hm_mvm(self._h, float(alpha), xp, yp, flags, _stream_ptr(stream)))
 
-    def mvm_many(self, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None):
+    def mvm_many(self, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None, timing: bool = False):
         """Y += alpha * M * X for an n x r block (column-major device tensors)."""
-        mvm_batch([self], [X], [Y], alpha, cluster_order, stream)
+        mvm_batch([self], [X], [Y], alpha, cluster_order, stream, timing)
+
+    def tune(self, nrhs: int, vec_dtype: str = "f64", reps: int = 3, stream=None) -> dict:
+        """Pick the many-RHS plan parameters for blocks of `nrhs` columns (hm_tune_batch)."""
+        r = _lib.TuneResult()
+        _lib.check(_lib.lib().hm_tune_batch(self._h, int(nrhs), DTYPES[vec_dtype], int(reps),
+                                            _stream_ptr(stream), ctypes.byref(r)))
+        return dict(target_bytes=r.target_bytes, nrb=r.nrb, ms=r.ms, ncandidates=r.ncandidates)
 
     def graph(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None) -> "Graph":
         """Capture one product (fixed x, y, alpha) into a replayable HIP graph."""
@@ -208,7 +215,8 @@ class Matrix:
         n = ctypes.c_int32()
         _lib.check(_lib.lib().hm_timing_read(self._h, arr, cap, ctypes.byref(n)))
         return [dict(name=arr[i].name.decode(), ms_total=arr[i].ms_total, launches=arr[i].launches,
-                     algorithmic_bytes=arr[i].algorithmic_bytes, ntasks=arr[i].ntasks, nowners=arr[i].nowners)
+                     algorithmic_bytes=arr[i].algorithmic_bytes, ntasks=arr[i].ntasks, nowners=arr[i].nowners,
+                     data_bytes=arr[i].data_bytes, data_entries=arr[i].data_entries, nrhs=arr[i].nrhs)
                 for i in range(min(n.value, cap))]
 
     def free(self):
@@ -238,10 +246,7 @@ def _block_arg(t, n, name):
     return t.data_ptr(), max(ld, n), t.shape[1], vdt
 
 
-def mvm_batch(mats, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None):
-    """Y[i] += alpha * mats[i] * X[i] for every i (hm_mvm_batch).  X[i], Y[i]:
-    device tensors of n_i x r_i values (column-major) or vectors of length
-    n_i, all float64 or all float32."""
+def _marshal_batch(mats, X, Y):
     k = len(mats)
     if len(X) != k or len(Y) != k:
         raise ValueError("mats, X and Y must have the same length")
@@ -257,9 +262,42 @@ def mvm_batch(mats, X, Y, alpha: float = 1.0, cluster_order: bool = False, strea
             raise ValueError("X and Y blocks must agree in width and all share one dtype")
         vdt = dx
         hs[i], xs[i], ys[i], ldx[i], ldy[i], nr[i] = M.handle.value, px, py, lx, ly, rx
-    flags = HM_CLUSTER_ORDER if cluster_order else 0
-    _lib.check(_lib.lib().hm_mvm_batch(hs, k, float(alpha), xs, ldx, nr, ys, ldy,
-                                       HM_F64 if vdt is None else vdt, flags, _stream_ptr(stream)))
+    return k, hs, xs, ldx, nr, ys, ldy, HM_F64 if vdt is None else vdt
+
+
+def mvm_batch(mats, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None, timing: bool = False):
+    """Y[i] += alpha * mats[i] * X[i] for every i (hm_mvm_batch).  X[i], Y[i]:
+    device tensors of n_i x r_i values (column-major) or vectors of length
+    n_i, all float64 or all float32."""
+    k, hs, xs, ldx, nr, ys, ldy, vdt = _marshal_batch(mats, X, Y)
+    flags = (HM_CLUSTER_ORDER if cluster_order else 0) | (_lib.HM_TIMING if timing else 0)
+    _lib.check(_lib.lib().hm_mvm_batch(hs, k, float(alpha), xs, ldx, nr, ys, ldy, vdt, flags,
+                                       _stream_ptr(stream)))
+
+
+class BatchGraph:
+    """hm_graph_create_batch: one captured hm_mvm_batch call, replayed with launch()."""
+
+    def __init__(self, mats, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None):
+        self._keep = (list(mats), list(X), list(Y))
+        k, hs, xs, ldx, nr, ys, ldy, vdt = _marshal_batch(mats, X, Y)
+        h = ctypes.c_void_p()
+        flags = HM_CLUSTER_ORDER if cluster_order else 0
+        _lib.check(_lib.lib().hm_graph_create_batch(hs, k, float(alpha), xs, ldx, nr, ys, ldy, vdt, flags,
+                                                    _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _lib.check(_lib.lib().hm_graph_launch(self._h, _stream_ptr(stream)))
+
+    def free(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None and _lib._lib is not None:
+            _lib._lib.hm_graph_free(h)
+        self._h = None
+
+    def __del__(self):
+        self.free()
 
 
 class Graph:

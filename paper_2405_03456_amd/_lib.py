@@ -58,7 +58,12 @@ class Stats(ctypes.Structure):
 
 class PhaseTiming(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("ms_total", c_double), ("launches", c_int64),
-                ("algorithmic_bytes", c_double), ("ntasks", c_int32), ("nowners", c_int32)]
+                ("algorithmic_bytes", c_double), ("ntasks", c_int32), ("nowners", c_int32),
+                ("data_bytes", c_int64), ("data_entries", c_int64), ("nrhs", c_int32)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("target_bytes", c_int64), ("nrb", c_int32), ("ms", c_double), ("ncandidates", c_int32)]
 
 
 HM_TIMING = 2
@@ -76,6 +81,9 @@ SIGNATURES = {
     "hm_mvm_batch": (c_int32, [P(c_void_p), c_int32, c_double, P(c_void_p), P(c_int64), P(c_int32),
                                P(c_void_p), P(c_int64), c_int32, c_uint32, c_void_p]),
     "hm_graph_create": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p, P(c_void_p)]),
+    "hm_tune_batch": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, P(TuneResult)]),
+    "hm_graph_create_batch": (c_int32, [P(c_void_p), c_int32, c_double, P(c_void_p), P(c_int64), P(c_int32),
+                                        P(c_void_p), P(c_int64), c_int32, c_uint32, c_void_p, P(c_void_p)]),
     "hm_graph_launch": (c_int32, [c_void_p, c_void_p]),
     "hm_graph_free": (None, [c_void_p]),
     "hm_timing_read": (c_int32, [c_void_p, P(PhaseTiming), c_int32, P(c_int32)]),

@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstring>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -116,18 +117,25 @@ __device__ __forceinline__ void put(const DTask& tk, const Outs& o, int row, int
     }
 }
 
-// Rows [r0, r0 + 16*nrg) of one task against right-hand sides [j0, j0 + 16*NRB).
+// One task: rows [r0, r0 + 64) (r0 = DTask::pad) against right-hand sides
+// [j0, j0 + 16*NRB).  The wave walks 4 tiles per step; the item bookkeeping
+// of those tiles is uniform (scalar loads), so only the tile data and the
+// input values are vector loads, and the next step's loads are in flight
+// while the current step's MFMAs run.
 template <int DT, bool ACC64, int NRB>
-__device__ __forceinline__ void task_rows(const DTask& tk, int r0, int nrg, const DItem* __restrict__ items,
+__device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restrict__ items,
                                           const uint8_t* __restrict__ data, const double* __restrict__ wsm,
                                           const float* __restrict__ wsm32, int j0, int lane, const Outs& o) {
     using M = Mfma<ACC64>;
     using T = typename M::T;
     constexpr int V = 16 / Bytes<DT>::v;
     const int rl = lane & 15, kq = lane >> 4;
-    const int nrows = tk.nrows;
+    const int nrows = tk.nrows, r0 = tk.pad;
+    const int nrg = min(4, (nrows - r0 + 15) / 16);
     const int64_t rt = (int64_t)nrows * 16;
     const uint8_t* base = data + tk.stream;
+    const int k0 = tk.k0, k1 = tk.k1;
+    const int R = o.R;
     int rows[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) rows[g] = min(r0 + g * 16 + rl, nrows - 1);
@@ -136,37 +144,90 @@ __device__ __forceinline__ void task_rows(const DTask& tk, int r0, int nrg, cons
     for (int g = 0; g < 4; ++g)
 #pragma unroll
         for (int b = 0; b < NRB; ++b) acc[g][b] = typename M::V{0, 0, 0, 0};
-    ItemPos st = item_pos<V>(items, tk.item_start);
-    const int R = o.R;
-    for (int kb = tk.k0; kb < tk.k1; kb += 4) {
-        const int tt = kb + kq;
-        const bool valid = tt < tk.k1;
-        const int tc = valid ? tt : tk.k1 - 1;    // lanes past the end re-read the last tile
-        while (tc >= st.k1) st = item_pos<V>(items, st.it + 1);
+
+    struct Buf {
         uint4 q[4];
+        T b[V][NRB];
+    };
+    ItemPos cur = item_pos<V>(items, tk.item_start);
+    auto load = [&](Buf& f, int kb) {
+        // uniform: the item of each of the 4 tiles of this step
+        int vec[4], sc[4], t0[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = min(kb + u, k1 - 1);
+            while (t >= cur.k1) cur = item_pos<V>(items, cur.it + 1);
+            vec[u] = cur.vec;
+            sc[u] = cur.sc;
+            t0[u] = cur.k0;
+        }
+        const int tt = kb + kq;
+        const bool valid = tt < k1;
+        const int tc = valid ? tt : k1 - 1;
+        const int myvec = kq == 0 ? vec[0] : kq == 1 ? vec[1] : kq == 2 ? vec[2] : vec[3];
+        const int mysc = kq == 0 ? sc[0] : kq == 1 ? sc[1] : kq == 2 ? sc[2] : sc[3];
+        const int myt0 = kq == 0 ? t0[0] : kq == 1 ? t0[1] : kq == 2 ? t0[2] : t0[3];
 #pragma unroll
         for (int g = 0; g < 4; ++g)
-            if (g < nrg) q[g] = *reinterpret_cast<const uint4*>(base + (int64_t)tc * rt + rows[g] * 16);
-        const int cb = (tc - st.k0) * V;
+            if (g < nrg) f.q[g] = *reinterpret_cast<const uint4*>(base + (int64_t)tc * rt + rows[g] * 16);
+        const int cb = (tc - myt0) * V;
 #pragma unroll
         for (int c = 0; c < V; ++c) {
-            const int64_t wi = (int64_t)(st.vec + cb + c) * R + j0 + rl;
-            T sc = (T)1;
-            if (st.sc >= 0) sc = (T)o.scales[st.sc + cb + c];
-            if (!valid) sc = (T)0;
-            T bv[NRB];
+            const int64_t wi = (int64_t)(myvec + cb + c) * R + j0 + rl;
+            T s = (T)1;
+            if (mysc >= 0) s = (T)o.scales[mysc + cb + c];
+            if (!valid) s = (T)0;
 #pragma unroll
-            for (int b = 0; b < NRB; ++b) bv[b] = (ACC64 ? (T)wsm[wi + 16 * b] : (T)wsm32[wi + 16 * b]) * sc;
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                if (g < nrg) {
-                    const T a = elem<DT, T>(q[g], c);
-#pragma unroll
-                    for (int b = 0; b < NRB; ++b) acc[g][b] = M::step(a, bv[b], acc[g][b]);
-                }
-            }
+            for (int b = 0; b < NRB; ++b) f.b[c][b] = (ACC64 ? (T)wsm[wi + 16 * b] : (T)wsm32[wi + 16 * b]) * s;
         }
+    };
+    auto compute = [&](const Buf& f) {
+#pragma unroll
+        for (int c = 0; c < V; ++c)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                if (g < nrg) {
+                    const T a = elem<DT, T>(f.q[g], c);
+#pragma unroll
+                    for (int b = 0; b < NRB; ++b) acc[g][b] = M::step(a, f.b[c][b], acc[g][b]);
+                }
+    };
+    // float32 accumulators are moved into float64 sums every kFlush tiles,
+    // so a float32 accumulation chain never spans more than kFlush tiles
+    constexpr int kFlush = 32;
+    double sum[ACC64 ? 1 : 4][ACC64 ? 1 : NRB][ACC64 ? 1 : 4];
+    if constexpr (!ACC64) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int b = 0; b < NRB; ++b)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sum[g][b][i] = 0.0;
     }
+    auto flush = [&]() {
+        if constexpr (!ACC64) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int b = 0; b < NRB; ++b) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) sum[g][b][i] += (double)acc[g][b][i];
+                    acc[g][b] = typename M::V{0, 0, 0, 0};
+                }
+        }
+    };
+    Buf fa, fb;
+    load(fa, k0);
+    for (int kb = k0; kb < k1; kb += 8) {
+        load(fb, kb + 4);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(fa);
+        if (kb + 8 < k1) load(fa, kb + 8);
+        __builtin_amdgcn_sched_barrier(0);
+        if (kb + 4 < k1) compute(fb);
+        if (!ACC64 && ((kb - k0 + 8) % kFlush) == 0) flush();
+    }
+    flush();
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         if (g >= nrg) continue;
@@ -175,14 +236,22 @@ __device__ __forceinline__ void task_rows(const DTask& tk, int r0, int nrg, cons
             const int row = r0 + g * 16 + M::row(kq, i);
             if (row < nrows)
 #pragma unroll
-                for (int b = 0; b < NRB; ++b) put(tk, o, row, j0 + 16 * b + rl, (double)acc[g][b][i]);
+                for (int b = 0; b < NRB; ++b) {
+                    double v;
+                    if constexpr (ACC64)
+                        v = acc[g][b][i];
+                    else
+                        v = sum[g][b][i];
+                    put(tk, o, row, j0 + 16 * b + rl, v);
+                }
         }
     }
 }
 
 // One wavefront per (task, block of 16*NRB right-hand sides); the blocks of
-// one task are adjacent waves, so the task's slab is read from HBM about once.
-template <bool ACC64, int NRB>
+// one task are adjacent waves of one workgroup, so the task's slab is read
+// from HBM about once.
+template <bool ACC64, int NRB, int MASK>
 __global__ __launch_bounds__(256) void k_tasks(const DTask* __restrict__ tasks, int ntasks, int nblk,
                                                const DItem* __restrict__ items, const uint8_t* __restrict__ data,
                                                const double* __restrict__ scales, double* wsm, float* wsm32,
@@ -196,22 +265,35 @@ __global__ __launch_bounds__(256) void k_tasks(const DTask* __restrict__ tasks, 
     const DTask tk = tasks[t];
     const Outs o{wsm, wsm32, ym, partm, scales, R};
     const int dt = tk.k0 < tk.k1 ? (int)items[tk.item_start].dtype : -1;
-    for (int r0 = 0; r0 < tk.nrows; r0 += 64) {
-        const int nrg = min(4, (tk.nrows - r0 + 15) / 16);
-        switch (dt) {
-            case HM_F64: task_rows<HM_F64, true, NRB>(tk, r0, nrg, items, data, wsm, wsm32, j0, lane, o); break;
-            case HM_F32: task_rows<HM_F32, ACC64, NRB>(tk, r0, nrg, items, data, wsm, wsm32, j0, lane, o); break;
-            case HM_BF16: task_rows<HM_BF16, ACC64, NRB>(tk, r0, nrg, items, data, wsm, wsm32, j0, lane, o); break;
-            case HM_F16: task_rows<HM_F16, ACC64, NRB>(tk, r0, nrg, items, data, wsm, wsm32, j0, lane, o); break;
-            case HM_FP8E4M3:
-                task_rows<HM_FP8E4M3, ACC64, NRB>(tk, r0, nrg, items, data, wsm, wsm32, j0, lane, o);
-                break;
-            default: {
-                // a task without columns contributes zero
-                for (int idx = lane; idx < 64 * 16 * NRB; idx += 64) {
-                    const int row = r0 + idx / (16 * NRB);
-                    if (row < tk.nrows) put(tk, o, row, j0 + idx % (16 * NRB), 0.0);
-                }
+    // MASK: the dtypes that may occur in the launched stage (one bit per
+    // dtype); the other cases are not compiled, which keeps the register
+    // budget of single-dtype stages low
+    switch (dt) {
+        case HM_F64:
+            if constexpr ((MASK & (1 << HM_F64)) != 0)
+                task_rows<HM_F64, true, NRB>(tk, items, data, wsm, wsm32, j0, lane, o);
+            break;
+        case HM_F32:
+            if constexpr ((MASK & (1 << HM_F32)) != 0)
+                task_rows<HM_F32, ACC64, NRB>(tk, items, data, wsm, wsm32, j0, lane, o);
+            break;
+        case HM_BF16:
+            if constexpr ((MASK & (1 << HM_BF16)) != 0)
+                task_rows<HM_BF16, ACC64, NRB>(tk, items, data, wsm, wsm32, j0, lane, o);
+            break;
+        case HM_F16:
+            if constexpr ((MASK & (1 << HM_F16)) != 0)
+                task_rows<HM_F16, ACC64, NRB>(tk, items, data, wsm, wsm32, j0, lane, o);
+            break;
+        case HM_FP8E4M3:
+            if constexpr ((MASK & (1 << HM_FP8E4M3)) != 0)
+                task_rows<HM_FP8E4M3, ACC64, NRB>(tk, items, data, wsm, wsm32, j0, lane, o);
+            break;
+        default: {
+            // a task without columns contributes zero
+            for (int idx = lane; idx < 64 * 16 * NRB; idx += 64) {
+                const int row = tk.pad + idx / (16 * NRB);
+                if (row < tk.nrows) put(tk, o, row, j0 + idx % (16 * NRB), 0.0);
             }
         }
     }
@@ -302,14 +384,115 @@ __global__ __launch_bounds__(256) void k_scatter(YT* __restrict__ Y, int64_t ldy
 using TaskKernel = void (*)(const DTask*, int, int, const DItem*, const uint8_t*, const double*, double*, float*,
                             double*, double*, int);
 
-// [acc64][log2 NRB]
-static const TaskKernel kTasks[2][3] = {{&k_tasks<false, 1>, &k_tasks<false, 2>, &k_tasks<false, 4>},
-                                        {&k_tasks<true, 1>, &k_tasks<true, 2>, &k_tasks<true, 4>}};
+// [acc64][NRB - 1][dtype of a single-dtype stage, or 5 = several]
+#define HM_MR_ROW(A, N)                                                                                  \
+    {                                                                                                   \
+        &k_tasks<A, N, 1 << HM_F64>, &k_tasks<A, N, 1 << HM_F32>, &k_tasks<A, N, 1 << HM_BF16>,         \
+            &k_tasks<A, N, 1 << HM_F16>, &k_tasks<A, N, 1 << HM_FP8E4M3>, &k_tasks<A, N, 31>              \
+    }
+static const TaskKernel kTasks[2][2][6] = {{HM_MR_ROW(false, 1), HM_MR_ROW(false, 2)},
+                                           {HM_MR_ROW(true, 1), HM_MR_ROW(true, 2)}};
+#undef HM_MR_ROW
+
+// kernel variant for a stage with dtype set `mask`
+static int variant(int mask) {
+    for (int d = 0; d < 5; ++d)
+        if (mask == (1 << d)) return d;
+    return 5;
+}
 
 }  // namespace mr
 
+// Column-chunk size of the many-RHS plan (bytes per 64-row group) unless
+// the tuner picked another one.
+static constexpr int64_t kDefaultMrTarget = 256 * 1024;
+
+// Build (or rebuild for another chunk size) the matrix's many-RHS plan and
+// copy its tables to the device.
+static hm_status ensure_mr_plan(hm_matrix* m, int64_t target) {
+    if (m->mr_meta && m->mr_target == target) return HM_OK;
+    MrPlan P;
+    try {
+        build_mr_plan(m->h_owners, m->h_items, m->h_tasks, m->h_stages, target, P);
+    } catch (const std::bad_alloc&) {
+        set_error("hm_mvm_batch: out of host memory");
+        return HM_ENOMEM;
+    }
+    size_t off = 0;
+    const size_t o_tasks = off;
+    off = align256(off + P.tasks.size() * sizeof(DTask));
+    const size_t o_owners = off;
+    off = align256(off + P.owners.size() * sizeof(DOwner));
+    std::vector<size_t> o_red;
+    for (auto& st : P.stages) {
+        o_red.push_back(off);
+        off = align256(off + st.reduce.size() * sizeof(int32_t));
+    }
+    std::vector<uint8_t> host(std::max<size_t>(off, 256), 0);
+    std::memcpy(host.data() + o_tasks, P.tasks.data(), P.tasks.size() * sizeof(DTask));
+    std::memcpy(host.data() + o_owners, P.owners.data(), P.owners.size() * sizeof(DOwner));
+    for (size_t i = 0; i < P.stages.size(); ++i)
+        std::memcpy(host.data() + o_red[i], P.stages[i].reduce.data(), P.stages[i].reduce.size() * sizeof(int32_t));
+    hipError_t e = hipSuccess;
+    if (m->mr_meta) {
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail("hm_mvm_batch: synchronize before replacing the plan", e);
+        (void)hipFree(m->mr_meta);
+        m->mr_meta = nullptr;
+    }
+    void* d = nullptr;
+    e = hipMalloc(&d, host.size());
+    if (e != hipSuccess) {
+        set_error("hm_mvm_batch: hipMalloc of the many-RHS plan failed");
+        return HM_ENOMEM;
+    }
+    e = hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail("hm_mvm_batch: plan copy", e);
+    }
+    for (auto& ph : m->mr_phases)
+        for (auto& ev : ph.pending) m->event_pool.push_back(ev);
+    m->mr_phases.clear();
+    uint8_t* b = (uint8_t*)d;
+    for (size_t i = 0; i < P.stages.size(); ++i) {
+        const Stage& st = P.stages[i];
+        DevStage ds;
+        ds.aux = st.aux;
+        ds.t0 = st.t0;
+        ds.ntasks = (int32_t)(st.t1 - st.t0);
+        ds.reduce = (const int32_t*)(b + o_red[i]);
+        ds.nreduce = (int32_t)st.reduce.size();
+        ds.nowners = 0;
+        ds.dtype_mask = 0;
+        for (int64_t k = st.t0; k < st.t1; ++k) {
+            const DTask& t = P.tasks[k];
+            if (t.c0 < t.c1) ds.dtype_mask |= 1 << m->h_items[t.item_start].dtype;
+        }
+        ds.data_bytes = st.data_bytes;
+        ds.data_entries = st.data_entries;
+        ds.alg_bytes = (double)st.data_bytes;
+        ds.name = st.name;
+        m->mr_phases.push_back(ds);
+    }
+    m->mr_meta = d;
+    m->mr_tasks = (const DTask*)(b + o_tasks);
+    m->mr_owners = (const DOwner*)(b + o_owners);
+    if (P.part_elems > m->mr_part_elems && m->mr_arena) {
+        // the partial-sum workspace no longer fits: regrow it on next use
+        (void)hipFree(m->mr_arena);
+        m->mr_arena = nullptr;
+        m->mr_cap = 0;
+    }
+    m->mr_part_elems = std::max(m->mr_part_elems, P.part_elems);
+    m->mr_target = target;
+    return HM_OK;
+}
+
 // Grow the matrix's many-RHS workspace to R values per entry.
 static hm_status ensure_mr(hm_matrix* m, int R) {
+    hm_status st = ensure_mr_plan(m, m->mr_target ? m->mr_target : kDefaultMrTarget);
+    if (st != HM_OK) return st;
     if (m->mr_cap >= R) return HM_OK;
     if (m->mr_arena) {
         hipError_t e = hipDeviceSynchronize();
@@ -323,7 +506,7 @@ static hm_status ensure_mr(hm_matrix* m, int R) {
     const size_t o_wsm32 = align256(o_wsm + ent * R * sizeof(double));
     const size_t o_ym = align256(o_wsm32 + ent * R * sizeof(float));
     const size_t o_part = align256(o_ym + (size_t)m->n * R * sizeof(double));
-    const size_t total = align256(o_part + (size_t)std::max<int64_t>(m->part_elems, 1) * R * sizeof(double));
+    const size_t total = align256(o_part + (size_t)std::max<int64_t>(m->mr_part_elems, 1) * R * sizeof(double));
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, total);
     if (e != hipSuccess) {
@@ -346,23 +529,19 @@ static hm_status ensure_mr(hm_matrix* m, int R) {
     return HM_OK;
 }
 
-// Width of the padded right-hand-side block: 16, 32, 64 or a multiple of 64.
-static int padded_width(int nrhs) {
-    if (nrhs <= 16) return 16;
-    if (nrhs <= 32) return 32;
-    return (nrhs + 63) / 64 * 64;
-}
+// Width of the padded right-hand-side block: 16 or a multiple of 32.
+static int padded_width(int nrhs) { return nrhs <= 16 ? 16 : (nrhs + 31) / 32 * 32; }
 
 static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx, int nrhs, void* Y, int64_t ldy,
                           int32_t vdt, uint32_t flags, hipStream_t stream) {
     const int R = padded_width(nrhs);
     hm_status st = ensure_mr(m, R);
     if (st != HM_OK) return st;
-    const int nrb = std::min(R, 64) / 16;          // 1, 2 or 4 blocks of 16 per wave
-    const int lg = nrb == 1 ? 0 : nrb == 2 ? 1 : 2;
+    const int nrb = (R >= 32 && m->mr_nrb == 2) ? 2 : 1;   // blocks of 16 right-hand sides per wave
     const int nblk = R / (16 * nrb);
     const int64_t n = m->n;
     const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : m->perm;
+    const bool timing = (flags & HM_TIMING) != 0;
     dim3 tgrid((unsigned)((n + 63) / 64), (unsigned)((R + 63) / 64));
     if (vdt == HM_F64)
         hipLaunchKernelGGL(mr::k_gather<double>, tgrid, dim3(256), 0, stream, (const double*)X, ldx, nrhs, perm, n, R,
@@ -376,22 +555,29 @@ static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx
         (void)hipStreamWaitEvent(m->aux, m->ev_fork, 0);
     }
     bool joined = m->aux == nullptr;
-    for (auto& ph : m->phases) {
+    for (auto& ph : m->mr_phases) {
         hipStream_t s = ph.aux ? m->aux : main_stream;
-        if (!joined && !ph.aux && ph.ntasks == 0 && &ph == &m->phases.back()) {
+        if (!joined && !ph.aux && ph.ntasks == 0 && &ph == &m->mr_phases.back()) {
             (void)hipEventRecord(m->ev_join, m->aux);
             (void)hipStreamWaitEvent(main_stream, m->ev_join, 0);
             joined = true;
         }
         if (ph.ntasks > 0) {
             const int64_t waves = (int64_t)ph.ntasks * nblk;
-            hipLaunchKernelGGL(mr::kTasks[m->acc64 ? 1 : 0][lg], dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
-                               m->tasks + ph.t0, ph.ntasks, nblk, m->items, m->data, m->scales, m->wsm, m->wsm32,
-                               m->ym, m->partm, R);
+            std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+            if (timing && !timing_begin(m, ph, R, s, ev)) {
+                set_error("hm_mvm_batch: timing events failed");
+                return HM_EDEVICE;
+            }
+            hipLaunchKernelGGL(mr::kTasks[m->acc64 ? 1 : 0][nrb - 1][mr::variant(ph.dtype_mask)],
+                               dim3((unsigned)((waves + 3) / 4)), dim3(256), 0,
+                               s, m->mr_tasks + ph.t0, ph.ntasks, nblk, m->items, m->data, m->scales, m->wsm,
+                               m->wsm32, m->ym, m->partm, R);
+            if (timing) timing_end(ph, s, ev);
         }
         if (ph.nreduce > 0)
             hipLaunchKernelGGL(mr::k_reduce, dim3((unsigned)((ph.nreduce + 3) / 4)), dim3(256), 0, s, ph.reduce,
-                               ph.nreduce, m->owners, m->partm, m->wsm, m->wsm32, m->ym, R);
+                               ph.nreduce, m->mr_owners, m->partm, m->wsm, m->wsm32, m->ym, R);
     }
     if (!joined) {
         (void)hipEventRecord(m->ev_join, m->aux);
@@ -408,6 +594,48 @@ static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx
     return HM_OK;
 }
 
+// Time one candidate (chunk size, blocks per wave) of the many-RHS plan.
+static hm_status time_candidate(hm_matrix* m, int64_t target, int nrb, int nrhs, int32_t vdt, const void* X,
+                                void* Y, int reps, hipStream_t s, double* ms) {
+    m->mr_nrb = nrb;
+    hm_status st = ensure_mr_plan(m, target);
+    if (st == HM_OK) st = mvm_many(m, 1.0, X, m->n, nrhs, Y, m->n, vdt, 0, s);   // warm-up
+    if (st != HM_OK) return st;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    for (int r = 0; r < reps && e == hipSuccess && st == HM_OK; ++r)
+        st = mvm_many(m, 1.0, X, m->n, nrhs, Y, m->n, vdt, 0, s);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (st != HM_OK) return st;
+    if (e != hipSuccess) return hip_fail("hm_tune_batch: timing", e);
+    *ms = (double)t / reps;
+    return HM_OK;
+}
+
+hm_status batch_prepare(hm_matrix* const* mats, int32_t nmat, const int32_t* nrhs, int32_t vec_dtype) {
+    if (nmat < 0 || (nmat > 0 && (!mats || !nrhs))) {
+        set_error("hm_graph_create_batch: null argument");
+        return HM_EINVAL;
+    }
+    for (int32_t i = 0; i < nmat; ++i) {
+        if (!mats[i] || nrhs[i] < 0 || nrhs[i] > HM_MAX_NRHS) {
+            set_error("hm_graph_create_batch: null matrix or nrhs out of range");
+            return HM_EINVAL;
+        }
+        if (nrhs[i] == 0 || (nrhs[i] == 1 && vec_dtype == HM_F64)) continue;
+        hm_status st = ensure_mr(mats[i], padded_width(nrhs[i]));
+        if (st != HM_OK) return st;
+    }
+    return HM_OK;
+}
+
 }  // namespace hm
 
 extern "C" hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double alpha, const void* const* X,
@@ -421,7 +649,7 @@ extern "C" hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double a
         hm::set_error("hm_mvm_batch: vec_dtype must be HM_F64 or HM_F32");
         return HM_EINVAL;
     }
-    if (flags & ~(uint32_t)HM_CLUSTER_ORDER) {
+    if (flags & ~(uint32_t)(HM_CLUSTER_ORDER | HM_TIMING)) {
         hm::set_error("hm_mvm_batch: unsupported flags");
         return HM_EINVAL;
     }
@@ -461,5 +689,54 @@ extern "C" hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double a
                               (hipStream_t)stream);
         if (st != HM_OK) return st;
     }
+    return HM_OK;
+}
+
+extern "C" hm_status hm_tune_batch(hm_matrix* m, int32_t nrhs, int32_t vec_dtype, int32_t reps, hm_stream_t stream,
+                                   hm_tune_result* out) {
+    if (!m || nrhs < 2 || nrhs > HM_MAX_NRHS || (vec_dtype != HM_F64 && vec_dtype != HM_F32) || reps < 1) {
+        hm::set_error("hm_tune_batch: bad argument (nrhs in [2, HM_MAX_NRHS], vec_dtype F64/F32, reps >= 1)");
+        return HM_EINVAL;
+    }
+    const size_t esz = vec_dtype == HM_F64 ? 8 : 4;
+    const size_t bytes = (size_t)m->n * nrhs * esz;
+    void* X = nullptr;
+    void* Y = nullptr;
+    if (hipMalloc(&X, bytes) != hipSuccess || hipMalloc(&Y, bytes) != hipSuccess) {
+        if (X) (void)hipFree(X);
+        hm::set_error("hm_tune_batch: hipMalloc of the trial blocks failed");
+        return HM_ENOMEM;
+    }
+    hipError_t e = hipMemset(X, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(Y, 0, bytes);
+    if (e != hipSuccess) {
+        (void)hipFree(X);
+        (void)hipFree(Y);
+        return hm::hip_fail("hm_tune_batch: hipMemset", e);
+    }
+    static const int64_t targets[] = {64 * 1024, 128 * 1024, 256 * 1024, 512 * 1024, 1024 * 1024};
+    const int R = hm::padded_width(nrhs);
+    hm_tune_result best{0, 1, 0.0, 0};
+    hm_status st = HM_OK;
+    for (int nrb = 1; nrb <= (R >= 32 ? 2 : 1) && st == HM_OK; ++nrb)
+        for (int64_t t : targets) {
+            double ms = 0.0;
+            st = hm::time_candidate(m, t, nrb, nrhs, vec_dtype, X, Y, reps, (hipStream_t)stream, &ms);
+            if (st != HM_OK) break;
+            ++best.ncandidates;
+            if (best.target_bytes == 0 || ms < best.ms) {
+                best.target_bytes = t;
+                best.nrb = nrb;
+                best.ms = ms;
+            }
+        }
+    (void)hipDeviceSynchronize();
+    (void)hipFree(X);
+    (void)hipFree(Y);
+    if (st != HM_OK) return st;
+    m->mr_nrb = best.nrb;
+    st = hm::ensure_mr_plan(m, best.target_bytes);
+    if (st != HM_OK) return st;
+    if (out) *out = best;
     return HM_OK;
 }

@@ -95,9 +95,11 @@ struct DevStage {
     const int32_t* reduce;
     int32_t dtype_mask;
     int64_t data_bytes;
+    int64_t data_entries;
     double alg_bytes;
     std::string name;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;   // HM_TIMING event pairs
+    int32_t timed_nrhs = 1;                                    // block width of the pending pairs
 };
 
 }  // namespace hm
@@ -127,6 +129,19 @@ struct hm_matrix {
     hm_stats stats{};
     int64_t ws_elems = 0;      // x in cluster order + coefficient vectors
     int64_t part_elems = 0;    // partial sums of split owners
+    // host copy of the plan tables (the many-RHS plan is derived from them)
+    std::vector<hm::DOwner> h_owners;
+    std::vector<hm::DItem> h_items;
+    std::vector<hm::DTask> h_tasks;
+    std::vector<hm::Stage> h_stages;
+    // many-RHS plan on the device (built on first use, rebuilt by the tuner)
+    void* mr_meta = nullptr;
+    const hm::DTask* mr_tasks = nullptr;
+    const hm::DOwner* mr_owners = nullptr;
+    std::vector<hm::DevStage> mr_phases;
+    int64_t mr_part_elems = 0;
+    int64_t mr_target = 0;
+    int32_t mr_nrb = 1;        // right-hand-side blocks of 16 per wave (1 or 2)
     // many-right-hand-side workspace (grown on demand): R values per entry
     // of ws / ws32 / part, entry-major (value j of entry i at i * R + j)
     void* mr_arena = nullptr;
@@ -139,7 +154,33 @@ struct hm_matrix {
 
 namespace hm {
 
+// Size the many-RHS workspaces of a batch (see hm_mvm_batch) ahead of a call.
+hm_status batch_prepare(hm_matrix* const* mats, int32_t nmat, const int32_t* nrhs, int32_t vec_dtype);
+
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// HM_TIMING: record the start event of one phase launch of block width
+// `width` on `s` (pending pairs of another width are dropped first).
+inline bool timing_begin(hm_matrix* m, DevStage& ph, int32_t width, hipStream_t s,
+                         std::pair<hipEvent_t, hipEvent_t>& ev) {
+    if (ph.timed_nrhs != width) {
+        for (auto& e : ph.pending) m->event_pool.push_back(e);
+        ph.pending.clear();
+        ph.timed_nrhs = width;
+    }
+    if (m->event_pool.empty()) {
+        if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) return false;
+    } else {
+        ev = m->event_pool.back();
+        m->event_pool.pop_back();
+    }
+    return hipEventRecord(ev.first, s) == hipSuccess;
+}
+
+inline void timing_end(DevStage& ph, hipStream_t s, const std::pair<hipEvent_t, hipEvent_t>& ev) {
+    (void)hipEventRecord(ev.second, s);
+    ph.pending.push_back(ev);
+}
 
 inline hm_status hip_fail(const char* what, hipError_t e) {
     set_error(std::string(what) + ": " + hipGetErrorString(e));

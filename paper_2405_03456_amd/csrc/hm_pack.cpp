@@ -1005,6 +1005,7 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
                     const int V = tile_cols(item.dtype);
                     const int32_t jb = c - item.col0, je = std::min(item.ncols, t.c1 - item.col0);
                     st.data_bytes += (int64_t)((je + V - 1) / V - jb / V) * ow.nrows * 16;
+                    st.data_entries += (int64_t)((je + V - 1) / V - jb / V) * ow.nrows * V;
                     st.dtype_mask |= 1 << item.dtype;
                     c = item.col0 + je;
                 }
@@ -1058,6 +1059,95 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
         return HM_ELAYOUT;
     }
     return HM_OK;
+}
+
+void build_mr_plan(const std::vector<DOwner>& owners, const std::vector<DItem>& items,
+                   const std::vector<DTask>& tasks, const std::vector<Stage>& stages, int64_t target_bytes,
+                   MrPlan& out) {
+    out = MrPlan{};
+    out.target_bytes = target_bytes;
+    out.owners = owners;
+    struct Chunk {
+        DTask t;         // owner fields, c0/c1, item_start, k0/k1, stream
+        int32_t stage;
+    };
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> nchunk(owners.size(), 0), last_stage(owners.size(), -1);
+    const int32_t nst = (int32_t)stages.size();
+    for (int32_t si = 0; si < nst; ++si) {
+        const Stage& st = stages[si];
+        int64_t acc = 0;
+        for (int64_t k = st.t0; k < st.t1; ++k) {
+            const DTask& t = tasks[k];
+            const DOwner& ow = owners[t.owner];
+            const int32_t dt = t.c0 < t.c1 ? items[t.item_start].dtype : -1;
+            const int64_t bytes = (int64_t)(t.k1 - t.k0) * std::min(ow.nrows, 64) * 16;
+            bool merge = false;
+            if (!chunks.empty()) {
+                const Chunk& c = chunks.back();
+                const int32_t cdt = c.t.c0 < c.t.c1 ? items[c.t.item_start].dtype : -1;
+                merge = c.stage == si && c.t.owner == t.owner && c.t.c1 == t.c0 && cdt == dt && dt >= 0 &&
+                        c.t.k1 == t.k0 && acc + bytes <= target_bytes;
+            }
+            if (merge) {
+                chunks.back().t.c1 = t.c1;
+                chunks.back().t.k1 = t.k1;
+                acc += bytes;
+            } else {
+                chunks.push_back(Chunk{t, si});
+                chunks.back().t.local = nchunk[t.owner]++;
+                acc = bytes;
+            }
+            last_stage[t.owner] = std::max(last_stage[t.owner], si);
+        }
+    }
+    for (size_t o = 0; o < owners.size(); ++o) {
+        DOwner& ow = out.owners[o];
+        ow.ntasks = std::max(nchunk[o], 1);
+        ow.part_off = 0;
+        if (ow.ntasks > 1) {
+            ow.part_off = (int32_t)out.part_elems;
+            out.part_elems += (int64_t)ow.ntasks * ow.nrows;
+        }
+    }
+    // stages: the task stages of the plan (its final reduce-only stage is rebuilt)
+    for (int32_t si = 0; si < nst; ++si) {
+        const Stage& src = stages[si];
+        if (src.t0 == src.t1 && !src.reduce.empty() && si == nst - 1) break;
+        Stage st;
+        st.name = src.name;
+        st.aux = src.aux;
+        st.t0 = (int64_t)out.tasks.size();
+        for (const Chunk& c : chunks) {
+            if (c.stage != si) continue;
+            const DOwner& ow = out.owners[c.t.owner];
+            for (int32_t r0 = 0; r0 < ow.nrows; r0 += 64) {
+                DTask t = c.t;
+                t.ntasks = ow.ntasks;
+                t.part_off = ow.part_off;
+                t.pad = r0;
+                out.tasks.push_back(t);
+                st.data_bytes += (int64_t)(t.k1 - t.k0) * std::min(64, ow.nrows - r0) * 16;
+                if (t.c0 < t.c1)
+                    st.data_entries += (int64_t)(t.k1 - t.k0) * std::min(64, ow.nrows - r0) *
+                                       tile_cols(items[t.item_start].dtype);
+            }
+        }
+        st.t1 = (int64_t)out.tasks.size();
+        out.stages.push_back(std::move(st));
+    }
+    Stage fin;
+    fin.name = "y_reduce";
+    fin.t0 = fin.t1 = (int64_t)out.tasks.size();
+    for (int32_t o = 0; o < (int32_t)owners.size(); ++o) {
+        const DOwner& ow = out.owners[o];
+        if (ow.ntasks < 2) continue;
+        if (ow.mode == 0)
+            out.stages[last_stage[o]].reduce.push_back(o);
+        else
+            fin.reduce.push_back(o);
+    }
+    if (!fin.reduce.empty()) out.stages.push_back(std::move(fin));
 }
 
 }  // namespace hm

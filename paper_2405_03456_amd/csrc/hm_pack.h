@@ -28,4 +28,23 @@ struct Packed {
 hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_precision* p,
                const PackOptions& opt, Packed& out);
 
+// Task table of the many-right-hand-side engine, derived from a packed plan.
+// Consecutive tasks of one owner in one stage (same dtype, adjacent
+// columns) are merged into column chunks of about `target_bytes` per 64-row
+// group, and every chunk is split into row groups of at most 64 rows
+// (DTask::pad = first row).  Owners split over several chunks get partial
+// sums (ntasks / part_off of `owners`); coefficient owners are reduced after
+// their stage, y owners in a final reduce stage.
+struct MrPlan {
+    std::vector<DTask> tasks;
+    std::vector<DOwner> owners;
+    std::vector<Stage> stages;
+    int64_t part_elems = 0;
+    int64_t target_bytes = 0;
+};
+
+void build_mr_plan(const std::vector<DOwner>& owners, const std::vector<DItem>& items,
+                   const std::vector<DTask>& tasks, const std::vector<Stage>& stages, int64_t target_bytes,
+                   MrPlan& out);
+
 }  // namespace hm

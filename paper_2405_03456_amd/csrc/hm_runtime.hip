@@ -428,6 +428,7 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         d.nowners = 0;
         d.dtype_mask = st.dtype_mask;
         d.data_bytes = st.data_bytes;
+        d.data_entries = st.data_entries;
         d.alg_bytes = st.alg_bytes;
         d.name = st.name;
         nlaunch += (d.ntasks > 0) + (d.nreduce > 0);
@@ -445,6 +446,10 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         }
     }
     m->stats = P.stats;
+    m->h_owners = P.owners;
+    m->h_items = P.items;
+    m->h_tasks = P.tasks;
+    m->h_stages = P.stages;
     m->ws_elems = P.ws_elems;
     m->part_elems = P.part_elems;
     if (nlaunch != P.stats.nlaunch) {
@@ -469,6 +474,12 @@ extern "C" void hm_matrix_free(hm_matrix* m) {
     if (m->aux) (void)hipStreamDestroy(m->aux);
     if (m->arena) (void)hipFree(m->arena);
     if (m->mr_arena) (void)hipFree(m->mr_arena);
+    if (m->mr_meta) (void)hipFree(m->mr_meta);
+    for (auto& ph : m->mr_phases)
+        for (auto& e : ph.pending) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
     delete m;
 }
 
@@ -517,25 +528,14 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
         if (ph.ntasks > 0) {
             dim3 grid((unsigned)((ph.ntasks + 3) / 4));
             std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-            if (timing) {
-                if (m->event_pool.empty()) {
-                    if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
-                        hm::set_error("hm_mvm: hipEventCreate failed");
-                        return HM_EDEVICE;
-                    }
-                } else {
-                    ev = m->event_pool.back();
-                    m->event_pool.pop_back();
-                }
-                (void)hipEventRecord(ev.first, stream);
+            if (timing && !hm::timing_begin(m, ph, 1, stream, ev)) {
+                hm::set_error("hm_mvm: timing events failed");
+                return HM_EDEVICE;
             }
             hipLaunchKernelGGL(hm::dev::kTasks[m->acc64 ? 1 : 0][ph.dtype_mask & 31], grid, dim3(256), 0, stream,
                                m->tasks + ph.t0, ph.ntasks, m->owners, m->items, m->data, m->scales, m->ws, m->ws32,
                                m->ws, m->ws32, m->part, y, perm, alpha);
-            if (timing) {
-                (void)hipEventRecord(ev.second, stream);
-                ph.pending.push_back(ev);
-            }
+            if (timing) hm::timing_end(ph, stream, ev);
         }
         if (ph.nreduce > 0) {
             dim3 grid((unsigned)((ph.nreduce + 3) / 4));
@@ -558,7 +558,8 @@ extern "C" hm_status hm_timing_read(hm_matrix* m, hm_phase_timing* out, int32_t 
         return HM_EINVAL;
     }
     int32_t i = 0;
-    for (auto& ph : m->phases) {
+    for (auto* list : {&m->phases, &m->mr_phases})
+    for (auto& ph : *list) {
         double ms = 0.0;
         int64_t cnt = 0;
         for (auto& e : ph.pending) {
@@ -578,6 +579,9 @@ extern "C" hm_status hm_timing_read(hm_matrix* m, hm_phase_timing* out, int32_t 
             out[i].algorithmic_bytes = ph.alg_bytes;
             out[i].ntasks = ph.ntasks;
             out[i].nowners = ph.nowners;
+            out[i].data_bytes = ph.data_bytes;
+            out[i].data_entries = ph.data_entries;
+            out[i].nrhs = ph.timed_nrhs;
         }
         ++i;
     }
@@ -590,17 +594,14 @@ struct hm_graph {
     hipGraphExec_t exec = nullptr;
 };
 
-extern "C" hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x, double* y, uint32_t flags,
-                                     hm_stream_t stream_, hm_graph** out) {
-    if (!m || !x || !y || !out || (flags & HM_TIMING)) {
-        hm::set_error("hm_graph_create: null argument or HM_TIMING requested");
-        return HM_EINVAL;
-    }
+// Record whatever `enqueue` puts on a private capturing stream (ordered after
+// the work already queued on `stream_`) into an instantiated graph.
+template <typename F>
+static hm_status capture_graph(const char* who, hm_stream_t stream_, hm_graph** out, F&& enqueue) {
     *out = nullptr;
     hipStream_t cap = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (e != hipSuccess) return hip_fail("hm_graph_create: hipStreamCreate", e);
-    // order the capture after work already queued on the caller's stream
+    if (e != hipSuccess) return hip_fail(who, e);
     hipEvent_t dep = nullptr;
     e = hipEventCreateWithFlags(&dep, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(dep, (hipStream_t)stream_);
@@ -610,7 +611,7 @@ extern "C" hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x
     hm_status st = HM_OK;
     if (e == hipSuccess && g) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess && g) {
-        st = hm_mvm(m, alpha, x, y, flags, (hm_stream_t)cap);
+        st = enqueue((hm_stream_t)cap);
         hipError_t e2 = hipStreamEndCapture(cap, &g->graph);
         if (st == HM_OK && e2 != hipSuccess) e = e2;
     }
@@ -625,13 +626,40 @@ extern "C" hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x
         }
         if (st != HM_OK) return st;
         if (!g) {
-            hm::set_error("hm_graph_create: out of host memory");
+            hm::set_error(std::string(who) + ": out of host memory");
             return HM_ENOMEM;
         }
-        return hip_fail("hm_graph_create", e);
+        return hip_fail(who, e);
     }
     *out = g;
     return HM_OK;
+}
+
+extern "C" hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x, double* y, uint32_t flags,
+                                     hm_stream_t stream_, hm_graph** out) {
+    if (!m || !x || !y || !out || (flags & HM_TIMING)) {
+        hm::set_error("hm_graph_create: null argument or HM_TIMING requested");
+        return HM_EINVAL;
+    }
+    return capture_graph("hm_graph_create", stream_, out, [&](hm_stream_t s) {
+        return hm_mvm(m, alpha, x, y, flags, s);
+    });
+}
+
+extern "C" hm_status hm_graph_create_batch(hm_matrix* const* mats, int32_t nmat, double alpha,
+                                           const void* const* X, const int64_t* ldx, const int32_t* nrhs,
+                                           void* const* Y, const int64_t* ldy, int32_t vec_dtype, uint32_t flags,
+                                           hm_stream_t stream_, hm_graph** out) {
+    if (!out || (flags & HM_TIMING)) {
+        hm::set_error("hm_graph_create_batch: null argument or HM_TIMING requested");
+        return HM_EINVAL;
+    }
+    // workspaces are sized (allocated) before the capture starts
+    hm_status st = hm::batch_prepare(mats, nmat, nrhs, vec_dtype);
+    if (st != HM_OK) return st;
+    return capture_graph("hm_graph_create_batch", stream_, out, [&](hm_stream_t s) {
+        return hm_mvm_batch(mats, nmat, alpha, X, ldx, nrhs, Y, ldy, vec_dtype, flags, s);
+    });
 }
 
 extern "C" hm_status hm_graph_launch(hm_graph* g, hm_stream_t stream) {

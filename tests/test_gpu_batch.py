@@ -142,3 +142,60 @@ def test_batch_errors():
     with pytest.raises(hm.HMError):                                 # X == Y
         hm.mvm_batch([M], [Xc], [Xc])
     M.free()
+
+
+def test_batch_graph_replays_and_timing():
+    """A captured hm_mvm_batch replays bitwise like the eager call, with
+    unrelated torch work and synchronisations between replays; HM_TIMING
+    reports per-phase times at the block width."""
+    import torch
+    import paper_2405_03456_amd as hm
+    st, lay, vals = case()
+    n = st.n
+    Ms = [hm.Matrix(lay, f, vals[f], dense="f32", diag="f64", factor="bf16", coupling="f32", eps=1e-6)
+          for f in ("uh", "h2")]
+    Xs = [padded(torch, gaussian_matrix(n, r, 60 + r), n, torch.float64) for r in (20, 70)]
+    Ye = [torch.zeros_like(x) for x in Xs]
+    hm.mvm_batch(Ms, Xs, Ye, alpha=1.5)
+    Yg = [torch.zeros_like(x) for x in Xs]
+    g = hm.BatchGraph(Ms, Xs, Yg, alpha=1.5)
+    for rep in range(3):
+        for y in Yg:
+            y.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()      # unrelated work between replays
+        g.launch()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for a, b in zip(Yg, Ye):
+            assert torch.equal(a, b), rep
+    g.free()
+    Ms[0].mvm_many(Xs[0], Ye[0], timing=True)
+    ph = Ms[0].timing()
+    assert all(p["nrhs"] == 32 for p in ph if p["launches"] > 0)
+    assert sum(p["launches"] for p in ph) > 0 and all(p["ms_total"] >= 0 for p in ph)
+    for M in Ms:
+        M.free()
+
+
+@pytest.mark.parametrize("fmt", ["h", "h2"])
+def test_tuner_keeps_parity(fmt):
+    """hm_tune_batch times every plan candidate and keeps the fastest; the
+    product stays within the accumulation tolerance of the oracle."""
+    import torch
+    import paper_2405_03456_amd as hm
+    st, lay, vals = case()
+    n, r = st.n, 40
+    pp, tol = POLICIES["bf16"]
+    M = hm.Matrix(lay, fmt, vals[fmt], **pp)
+    res = M.tune(r, reps=2)
+    assert res["ncandidates"] == 10 and res["nrb"] in (1, 2) and res["ms"] > 0
+    assert 64 * 1024 <= res["target_bytes"] <= 1024 * 1024
+    X, Y = gaussian_matrix(n, r, 91), gaussian_matrix(n, r, 92)
+    sv = stored.stored_values(st, fmt, vals[fmt], dense=pp["dense"], diag=pp.get("diag"),
+                              factor=pp["factor"], coupling=pp.get("coupling"), eps=pp["eps"])
+    ref = stored.product_many(st, fmt, sv, 1.0, X, Y)
+    Xd, Yd = padded(torch, X, n, torch.float64), padded(torch, Y, n, torch.float64)
+    M.mvm_many(Xd, Yd)
+    torch.cuda.synchronize()
+    assert colerr(Yd.cpu().numpy(), ref, Y) <= tol
+    M.free()
