@@ -28,6 +28,7 @@
 #include <new>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "hm_device.h"
 
@@ -248,20 +249,14 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
     }
 }
 
-// One wavefront per (task, block of 16*NRB right-hand sides); the blocks of
-// one task are adjacent waves of one workgroup, so the task's slab is read
-// from HBM about once.
+// Wave w of a task list: task w / nblk against right-hand-side block w % nblk.
 template <bool ACC64, int NRB, int MASK>
-__global__ __launch_bounds__(256) void k_tasks(const DTask* __restrict__ tasks, int ntasks, int nblk,
-                                               const DItem* __restrict__ items, const uint8_t* __restrict__ data,
-                                               const double* __restrict__ scales, double* wsm, float* wsm32,
-                                               double* __restrict__ ym, double* __restrict__ partm, int R) {
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * 4 + wave;
-    if (w >= ntasks * nblk) return;
-    const int t = w / nblk;
-    const int j0 = (w - t * nblk) * 16 * NRB;
+__device__ __forceinline__ void task_wave(const DTask* __restrict__ tasks, int64_t w, int nblk,
+                                          const DItem* __restrict__ items, const uint8_t* __restrict__ data,
+                                          const double* __restrict__ scales, double* wsm, float* wsm32,
+                                          double* __restrict__ ym, double* __restrict__ partm, int R, int lane) {
+    const int64_t t = w / nblk;
+    const int j0 = (int)(w - t * nblk) * 16 * NRB;
     const DTask tk = tasks[t];
     const Outs o{wsm, wsm32, ym, partm, scales, R};
     const int dt = tk.k0 < tk.k1 ? (int)items[tk.item_start].dtype : -1;
@@ -299,14 +294,57 @@ __global__ __launch_bounds__(256) void k_tasks(const DTask* __restrict__ tasks, 
     }
 }
 
+// One wavefront per (task, block of 16*NRB right-hand sides); the blocks of
+// one task are adjacent waves of one workgroup, so the task's slab is read
+// from HBM about once.
+template <bool ACC64, int NRB, int MASK>
+__global__ __launch_bounds__(256) void k_tasks(const DTask* __restrict__ tasks, int ntasks, int nblk,
+                                               const DItem* __restrict__ items, const uint8_t* __restrict__ data,
+                                               const double* __restrict__ scales, double* wsm, float* wsm32,
+                                               double* __restrict__ ym, double* __restrict__ partm, int R) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave;
+    if (w >= (int64_t)ntasks * nblk) return;
+    task_wave<ACC64, NRB, MASK>(tasks, w, nblk, items, data, scales, wsm, wsm32, ym, partm, R, threadIdx.x & 63);
+}
+
+// Several matrices in one launch: the stage tasks of up to kMaxJobs
+// matrices, passed by value; wave w belongs to the last job whose first
+// wave is <= w.
+constexpr int kMaxJobs = 24;
+struct Job {
+    const DTask* tasks;
+    const DItem* items;
+    const uint8_t* data;
+    const double* scales;
+    double* wsm;
+    float* wsm32;
+    double* ym;
+    double* partm;
+    int64_t wave0;
+    int32_t nblk, R;
+};
+struct Jobs {
+    int32_t njobs;
+    int64_t total;
+    Job j[kMaxJobs];
+};
+
+template <bool ACC64, int NRB, int MASK>
+__global__ __launch_bounds__(256) void k_tasks_multi(const Jobs J) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave;
+    if (w >= J.total) return;
+    int ji = 0;
+    while (ji + 1 < J.njobs && w >= J.j[ji + 1].wave0) ++ji;
+    const Job& jb = J.j[ji];
+    task_wave<ACC64, NRB, MASK>(jb.tasks, w - jb.wave0, jb.nblk, jb.items, jb.data, jb.scales, jb.wsm, jb.wsm32,
+                                jb.ym, jb.partm, jb.R, threadIdx.x & 63);
+}
+
 // Sum the partial results of split owners in task order, one wave per owner.
-__global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list, int nlist,
-                                                const DOwner* __restrict__ owners, const double* __restrict__ partm,
-                                                double* wsm, float* wsm32, double* __restrict__ ym, int R) {
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= nlist) return;
-    const DOwner ow = owners[list[i]];
+__device__ __forceinline__ void reduce_owner(const DOwner& ow, const double* __restrict__ partm, double* wsm,
+                                             float* wsm32, double* __restrict__ ym, int R, int lane) {
     const int64_t span = (int64_t)ow.nrows * R;
     for (int64_t idx = lane; idx < span; idx += 64) {
         const double* p = partm + (int64_t)ow.part_off * R + idx;
@@ -320,6 +358,39 @@ __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list
             ym[e] += v;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list, int nlist,
+                                                const DOwner* __restrict__ owners, const double* __restrict__ partm,
+                                                double* wsm, float* wsm32, double* __restrict__ ym, int R) {
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= nlist) return;
+    reduce_owner(owners[list[i]], partm, wsm, wsm32, ym, R, threadIdx.x & 63);
+}
+
+struct RJob {
+    const int32_t* list;
+    const DOwner* owners;
+    const double* partm;
+    double* wsm;
+    float* wsm32;
+    double* ym;
+    int64_t wave0;
+    int32_t R;
+};
+struct RJobs {
+    int32_t njobs;
+    int64_t total;
+    RJob j[kMaxJobs];
+};
+
+__global__ __launch_bounds__(256) void k_reduce_multi(const RJobs J) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= J.total) return;
+    int ji = 0;
+    while (ji + 1 < J.njobs && i >= J.j[ji + 1].wave0) ++ji;
+    const RJob& jb = J.j[ji];
+    reduce_owner(jb.owners[jb.list[i - jb.wave0]], jb.partm, jb.wsm, jb.wsm32, jb.ym, jb.R, threadIdx.x & 63);
 }
 
 // X (column-major, ldx) -> wsm / wsm32 in cluster order, entry-major; the
@@ -392,6 +463,17 @@ using TaskKernel = void (*)(const DTask*, int, int, const DItem*, const uint8_t*
     }
 static const TaskKernel kTasks[2][2][6] = {{HM_MR_ROW(false, 1), HM_MR_ROW(false, 2)},
                                            {HM_MR_ROW(true, 1), HM_MR_ROW(true, 2)}};
+#undef HM_MR_ROW
+
+using MultiKernel = void (*)(const Jobs);
+#define HM_MR_ROW(A, N)                                                                                  \
+    {                                                                                                   \
+        &k_tasks_multi<A, N, 1 << HM_F64>, &k_tasks_multi<A, N, 1 << HM_F32>,                           \
+            &k_tasks_multi<A, N, 1 << HM_BF16>, &k_tasks_multi<A, N, 1 << HM_F16>,                      \
+            &k_tasks_multi<A, N, 1 << HM_FP8E4M3>, &k_tasks_multi<A, N, 31>                               \
+    }
+static const MultiKernel kMulti[2][2][6] = {{HM_MR_ROW(false, 1), HM_MR_ROW(false, 2)},
+                                            {HM_MR_ROW(true, 1), HM_MR_ROW(true, 2)}};
 #undef HM_MR_ROW
 
 // kernel variant for a stage with dtype set `mask`
@@ -594,6 +676,111 @@ static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx
     return HM_OK;
 }
 
+// Several matrices at once: the stages of all of them are merged level by
+// level (the dense stage, which only reads x, joins level 0), so each level
+// is one launch per (accumulation, blocks-per-wave) class instead of one per
+// matrix and stage.
+struct Entry {
+    hm_matrix* m;
+    double alpha;
+    const void* X;
+    int64_t ldx;
+    int nrhs;
+    void* Y;
+    int64_t ldy;
+    int R, nrb, nblk;
+    std::vector<int> level;   // per many-RHS stage; -1 = the final reduce
+};
+
+static hm_status mvm_many_multi(std::vector<Entry>& E, int32_t vdt, uint32_t flags, hipStream_t s) {
+    int maxL = -1;
+    for (auto& e : E) {
+        e.R = padded_width(e.nrhs);
+        hm_status st = ensure_mr(e.m, e.R);
+        if (st != HM_OK) return st;
+        e.nrb = (e.R >= 32 && e.m->mr_nrb == 2) ? 2 : 1;
+        e.nblk = e.R / (16 * e.nrb);
+        e.level.clear();
+        int next = 0;
+        const auto& ph = e.m->mr_phases;
+        for (size_t i = 0; i < ph.size(); ++i) {
+            const bool fin = i + 1 == ph.size() && ph[i].ntasks == 0 && !ph[i].aux;
+            e.level.push_back(fin ? -1 : ph[i].aux ? 0 : next++);
+        }
+        maxL = std::max(maxL, next - 1);
+    }
+    for (auto& e : E) {
+        const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : e.m->perm;
+        dim3 tgrid((unsigned)((e.m->n + 63) / 64), (unsigned)((e.R + 63) / 64));
+        if (vdt == HM_F64)
+            hipLaunchKernelGGL(mr::k_gather<double>, tgrid, dim3(256), 0, s, (const double*)e.X, e.ldx, e.nrhs, perm,
+                               e.m->n, e.R, e.m->wsm, e.m->wsm32, e.m->ym);
+        else
+            hipLaunchKernelGGL(mr::k_gather<float>, tgrid, dim3(256), 0, s, (const float*)e.X, e.ldx, e.nrhs, perm,
+                               e.m->n, e.R, e.m->wsm, e.m->wsm32, e.m->ym);
+    }
+    auto launch_reduces = [&](int L) {
+        mr::RJobs J{};
+        auto flush = [&]() {
+            if (J.njobs > 0 && J.total > 0)
+                hipLaunchKernelGGL(mr::k_reduce_multi, dim3((unsigned)((J.total + 3) / 4)), dim3(256), 0, s, J);
+            J = mr::RJobs{};
+        };
+        for (auto& e : E)
+            for (size_t i = 0; i < e.m->mr_phases.size(); ++i) {
+                const DevStage& ph = e.m->mr_phases[i];
+                if (e.level[i] != L || ph.nreduce == 0) continue;
+                if (J.njobs == mr::kMaxJobs) flush();
+                J.j[J.njobs++] = mr::RJob{ph.reduce, e.m->mr_owners, e.m->partm, e.m->wsm, e.m->wsm32, e.m->ym,
+                                          J.total, e.R};
+                J.total += ph.nreduce;
+            }
+        flush();
+    };
+    for (int L = 0; L <= maxL; ++L) {
+        for (int acc = 0; acc < 2; ++acc)
+            for (int nrb = 1; nrb <= 2; ++nrb) {
+                mr::Jobs J{};
+                int mask = 0;
+                auto flush = [&]() {
+                    if (J.njobs > 0 && J.total > 0)
+                        hipLaunchKernelGGL(mr::kMulti[acc][nrb - 1][mr::variant(mask)],
+                                           dim3((unsigned)((J.total + 3) / 4)), dim3(256), 0, s, J);
+                    J = mr::Jobs{};
+                    mask = 0;
+                };
+                for (auto& e : E) {
+                    if ((e.m->acc64 ? 1 : 0) != acc || e.nrb != nrb) continue;
+                    for (size_t i = 0; i < e.m->mr_phases.size(); ++i) {
+                        const DevStage& ph = e.m->mr_phases[i];
+                        if (e.level[i] != L || ph.ntasks == 0) continue;
+                        if (J.njobs == mr::kMaxJobs) flush();
+                        J.j[J.njobs++] = mr::Job{e.m->mr_tasks + ph.t0, e.m->items, e.m->data, e.m->scales, e.m->wsm,
+                                                 e.m->wsm32, e.m->ym, e.m->partm, J.total, e.nblk, e.R};
+                        J.total += (int64_t)ph.ntasks * e.nblk;
+                        mask |= ph.dtype_mask;
+                    }
+                }
+                flush();
+            }
+        launch_reduces(L);
+    }
+    launch_reduces(-1);
+    for (auto& e : E) {
+        const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : e.m->perm;
+        dim3 tgrid((unsigned)((e.m->n + 63) / 64), (unsigned)((e.R + 63) / 64));
+        if (vdt == HM_F64)
+            hipLaunchKernelGGL(mr::k_scatter<double>, tgrid, dim3(256), 0, s, (double*)e.Y, e.ldy, e.nrhs, perm,
+                               e.m->n, e.R, e.m->ym, e.alpha);
+        else
+            hipLaunchKernelGGL(mr::k_scatter<float>, tgrid, dim3(256), 0, s, (float*)e.Y, e.ldy, e.nrhs, perm,
+                               e.m->n, e.R, e.m->ym, e.alpha);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail("hm_mvm_batch: kernel launch", e);
+    return HM_OK;
+}
+
 // Time one candidate (chunk size, blocks per wave) of the many-RHS plan.
 static hm_status time_candidate(hm_matrix* m, int64_t target, int nrb, int nrhs, int32_t vdt, const void* X,
                                 void* Y, int reps, hipStream_t s, double* ms) {
@@ -679,17 +866,42 @@ extern "C" hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double a
                 return HM_EINVAL;
             }
     }
+    // single float64 columns: the single-vector kernels
+    int nmany = 0;
     for (int32_t i = 0; i < nmat; ++i) {
         if (nrhs[i] == 0) continue;
-        hm_status st;
-        if (nrhs[i] == 1 && vec_dtype == HM_F64)
-            st = hm_mvm(mats[i], alpha, (const double*)X[i], (double*)Y[i], flags, stream);
-        else
-            st = hm::mvm_many(mats[i], alpha, X[i], ldx[i], nrhs[i], Y[i], ldy[i], vec_dtype, flags,
-                              (hipStream_t)stream);
-        if (st != HM_OK) return st;
+        if (nrhs[i] == 1 && vec_dtype == HM_F64) {
+            hm_status st = hm_mvm(mats[i], alpha, (const double*)X[i], (double*)Y[i], flags, stream);
+            if (st != HM_OK) return st;
+        } else {
+            ++nmany;
+        }
     }
-    return HM_OK;
+    if (nmany == 1 || (flags & HM_TIMING)) {
+        // one block (or per-phase timing): the per-matrix launch sequence
+        for (int32_t i = 0; i < nmat; ++i) {
+            if (nrhs[i] == 0 || (nrhs[i] == 1 && vec_dtype == HM_F64)) continue;
+            hm_status st = hm::mvm_many(mats[i], alpha, X[i], ldx[i], nrhs[i], Y[i], ldy[i], vec_dtype, flags,
+                                        (hipStream_t)stream);
+            if (st != HM_OK) return st;
+        }
+        return HM_OK;
+    }
+    if (nmany == 0) return HM_OK;
+    std::vector<hm::Entry> E;
+    for (int32_t i = 0; i < nmat; ++i) {
+        if (nrhs[i] == 0 || (nrhs[i] == 1 && vec_dtype == HM_F64)) continue;
+        hm::Entry e;
+        e.m = mats[i];
+        e.alpha = alpha;
+        e.X = X[i];
+        e.ldx = ldx[i];
+        e.nrhs = nrhs[i];
+        e.Y = Y[i];
+        e.ldy = ldy[i];
+        E.push_back(std::move(e));
+    }
+    return hm::mvm_many_multi(E, vec_dtype, flags, (hipStream_t)stream);
 }
 
 extern "C" hm_status hm_tune_batch(hm_matrix* m, int32_t nrhs, int32_t vec_dtype, int32_t reps, hm_stream_t stream,

@@ -199,3 +199,33 @@ def test_tuner_keeps_parity(fmt):
     torch.cuda.synchronize()
     assert colerr(Yd.cpu().numpy(), ref, Y) <= tol
     M.free()
+
+
+def test_batch_many_matrices_merged_launches():
+    """26 matrices (more than one launch's job table) of mixed formats,
+    storage and widths in one call: each result equals its own call bitwise."""
+    import torch
+    import paper_2405_03456_amd as hm
+    n = 300
+    p = sphere_points(n, 77)
+    st = trees.build_structure(p)
+    lay = hm.Layout(p)
+    h = compress_h(p, KERNEL_LAPLACE, st, 1e-8, method="svd")
+    vals = {"h": h, "uh": to_uh(h, st), "h2": to_h2(h, st)}
+    pols = [POLICIES[k][0] for k in ("f64", "f32", "bf16", "valr6")]
+    Ms, Xs, Ys = [], [], []
+    for i in range(26):
+        fmt = ("h", "uh", "h2")[i % 3]
+        Ms.append(hm.Matrix(lay, fmt, vals[fmt], **pols[i % 4]))
+        r = 2 + (7 * i) % 39
+        Xs.append(padded(torch, gaussian_matrix(n, r, 500 + i), n, torch.float64))
+        Ys.append(padded(torch, gaussian_matrix(n, r, 600 + i), n, torch.float64))
+    Y0 = [y.clone() for y in Ys]
+    hm.mvm_batch(Ms, Xs, Ys, alpha=-1.25)
+    for M, x, y in zip(Ms, Xs, Y0):
+        M.mvm_many(x, y, alpha=-1.25)
+    torch.cuda.synchronize()
+    for i in range(26):
+        assert torch.equal(Ys[i], Y0[i]), i
+    for M in Ms:
+        M.free()
