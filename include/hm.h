@@ -290,6 +290,75 @@ typedef struct {
 
 hm_status hm_timing_read(hm_matrix* m, hm_phase_timing* out, int32_t cap, int32_t* nphase);
 
+/* --------------------------------------------------------------- serving */
+
+/* A request loop over resident matrices (continuous batching).  A server
+ * owns one scheduler thread, two HIP streams, a device arena of mem_budget
+ * bytes for request blocks and a pinned host staging arena of the same
+ * size.  Requests wait in FIFO order; the scheduler repeatedly forms a
+ * launch group from the queued requests whose matrix is not in flight,
+ * concatenating the columns of requests for the same matrix into one block,
+ * as long as slots (max_slots requests in flight) and arena memory allow
+ * (memory admission).  A group is copied in, multiplied with the
+ * many-right-hand-side engine (hm_mvm_batch's merged launches) and copied
+ * out on one stream while the next group forms and runs on the other, so
+ * requests that arrive while others run join the next launch.
+ *
+ * Every product runs the same per-column arithmetic whatever the group:
+ * a request's result is bitwise the same alone and in any mix (alpha is
+ * applied on the host after the device product with alpha = 1).
+ *
+ * Matrices stay owned by the caller and must outlive the server.  fake = 1
+ * runs the scheduler without a device (dry runs and tests): products are not
+ * computed and results are zero, a group "runs" for fake_us microseconds. */
+typedef struct {
+    int64_t mem_budget;     /* device bytes for request blocks (and pinned host staging) */
+    int32_t max_slots;      /* requests in flight at most (> 0) */
+    int32_t max_queue;      /* queued requests at most; submit returns HM_EBUSY beyond */
+    int32_t max_cols;       /* columns per matrix and launch group at most (a wider request runs alone) */
+    int32_t fake;           /* 1 = no device work (see above) */
+    int32_t fake_us;        /* duration of a fake launch group */
+} hm_serve_opts;
+
+typedef struct {
+    double queue_ms;        /* submit -> admitted into a launch group */
+    double run_ms;          /* admitted -> results copied out */
+    double latency_ms;      /* submit -> done */
+    int64_t group_id;       /* launch group that ran it */
+    int32_t group_requests; /* requests in that group */
+    int32_t group_cols;     /* columns of its matrix in that group */
+} hm_req_stats;
+
+typedef struct {
+    int64_t submitted, completed, groups;
+    int64_t peak_arena_bytes;   /* device arena high-water mark */
+    int32_t peak_inflight;      /* requests in flight at most */
+    int32_t max_group_requests; /* largest launch group */
+} hm_serve_stats;
+
+typedef struct hm_server hm_server;
+hm_status hm_serve_create(const hm_serve_opts* opts, hm_server** out);
+/* Register a resident matrix (its many-RHS workspace is sized for max_cols
+ * here); *matrix_id identifies it in hm_serve_submit. */
+hm_status hm_serve_register(hm_server* s, hm_matrix* m, int32_t* matrix_id);
+/* Register a placeholder of n rows for a fake server (no matrix). */
+hm_status hm_serve_register_shape(hm_server* s, int64_t n, int32_t* matrix_id);
+/* Y_host := alpha * M * X_host.  X_host, Y_host: host float64 arrays of
+ * n x nrhs values, column-major (leading dimension n), caller-owned and
+ * valid until hm_serve_poll reports the ticket done; nrhs in
+ * [1, HM_MAX_NRHS].  Non-blocking; HM_EBUSY when max_queue requests wait,
+ * HM_ENOMEM when the request could never fit mem_budget. */
+hm_status hm_serve_submit(hm_server* s, int32_t matrix_id, double alpha, const double* X_host, int32_t nrhs,
+                          double* Y_host, uint64_t* ticket);
+/* Non-blocking.  *done = 1 once Y_host holds the result (the ticket is then
+ * released and *st, if not NULL, filled); 0 while queued or running.
+ * Unknown or released tickets give HM_EINVAL; a failed product returns its
+ * error status (and releases the ticket). */
+hm_status hm_serve_poll(hm_server* s, uint64_t ticket, int32_t* done, hm_req_stats* st);
+hm_status hm_serve_stats_read(hm_server* s, hm_serve_stats* out);
+/* Waits for every submitted request, then stops the thread and frees all. */
+void hm_serve_destroy(hm_server* s);
+
 /* Host-side helper used by tests: round float64 values to `dtype` exactly as
  * hm_upload does (scale already applied); writes float64 results. */
 hm_status hm_round_host(int32_t dtype, const double* in, double* out, int64_t count);

@@ -326,6 +326,82 @@ class Graph:
         self.free()
 
 
+class Server:
+    """hm_serve_*: a request loop over resident matrices (continuous batching)."""
+
+    def __init__(self, mem_budget: int = 1 << 30, max_slots: int = 64, max_queue: int = 4096, max_cols: int = 64,
+                 fake: bool = False, fake_us: int = 0):
+        opts = _lib.ServeOpts(int(mem_budget), int(max_slots), int(max_queue), int(max_cols), 1 if fake else 0,
+                              int(fake_us))
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().hm_serve_create(ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self._pending = {}    # ticket -> (X, Y) kept alive until done
+        self._mats = []
+
+    def register(self, M: "Matrix") -> int:
+        i = ctypes.c_int32()
+        _lib.check(_lib.lib().hm_serve_register(self._h, M.handle, ctypes.byref(i)))
+        self._mats.append(M)
+        return i.value
+
+    def register_shape(self, n: int) -> int:
+        i = ctypes.c_int32()
+        _lib.check(_lib.lib().hm_serve_register_shape(self._h, int(n), ctypes.byref(i)))
+        return i.value
+
+    def submit(self, mid: int, X, alpha: float = 1.0):
+        """Queue Y := alpha * M * X for a host n x r (or length-n) float64 block;
+        returns (ticket, Y) where Y is filled once poll() reports done."""
+        X = np.asfortranarray(X, dtype=np.float64)
+        r = 1 if X.ndim == 1 else X.shape[1]
+        Y = np.zeros(X.shape, dtype=np.float64, order="F")
+        t = ctypes.c_uint64()
+        _lib.check(_lib.lib().hm_serve_submit(self._h, int(mid), float(alpha), X.ctypes.data, r, Y.ctypes.data,
+                                              ctypes.byref(t)))
+        self._pending[t.value] = (X, Y)
+        return t.value, Y
+
+    def poll(self, ticket: int):
+        """None while queued/running, else the request's stats (dict)."""
+        done = ctypes.c_int32()
+        st = _lib.ReqStats()
+        status = _lib.lib().hm_serve_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(st))
+        if status != _lib.HM_OK:
+            self._pending.pop(ticket, None)
+            _lib.check(status)
+        if not done.value:
+            return None
+        self._pending.pop(ticket, None)
+        return {k: getattr(st, k) for k, _ in _lib.ReqStats._fields_}
+
+    def wait(self, ticket: int, timeout_s: float = 120.0):
+        import time
+        t0 = time.perf_counter()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout_s} s")
+            time.sleep(20e-6)
+
+    def stats(self) -> dict:
+        s = _lib.ServeStats()
+        _lib.check(_lib.lib().hm_serve_stats_read(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _lib.ServeStats._fields_}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None and _lib._lib is not None:
+            _lib._lib.hm_serve_destroy(h)
+        self._h = None
+        self._pending = {}
+
+    def __del__(self):
+        self.close()
+
+
 def _stream_ptr(stream):
     if stream is None:
         try:

@@ -66,6 +66,21 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("target_bytes", c_int64), ("nrb", c_int32), ("ms", c_double), ("ncandidates", c_int32)]
 
 
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("mem_budget", c_int64), ("max_slots", c_int32), ("max_queue", c_int32), ("max_cols", c_int32),
+                ("fake", c_int32), ("fake_us", c_int32)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("queue_ms", c_double), ("run_ms", c_double), ("latency_ms", c_double), ("group_id", c_int64),
+                ("group_requests", c_int32), ("group_cols", c_int32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", c_int64), ("completed", c_int64), ("groups", c_int64), ("peak_arena_bytes", c_int64),
+                ("peak_inflight", c_int32), ("max_group_requests", c_int32)]
+
+
 HM_TIMING = 2
 
 # name -> (restype, argtypes); every exported symbol of include/hm.h
@@ -87,6 +102,13 @@ SIGNATURES = {
     "hm_graph_launch": (c_int32, [c_void_p, c_void_p]),
     "hm_graph_free": (None, [c_void_p]),
     "hm_timing_read": (c_int32, [c_void_p, P(PhaseTiming), c_int32, P(c_int32)]),
+    "hm_serve_create": (c_int32, [P(ServeOpts), P(c_void_p)]),
+    "hm_serve_register": (c_int32, [c_void_p, c_void_p, P(c_int32)]),
+    "hm_serve_register_shape": (c_int32, [c_void_p, c_int64, P(c_int32)]),
+    "hm_serve_submit": (c_int32, [c_void_p, c_int32, c_double, c_void_p, c_int32, c_void_p, P(ctypes.c_uint64)]),
+    "hm_serve_poll": (c_int32, [c_void_p, ctypes.c_uint64, P(c_int32), P(ReqStats)]),
+    "hm_serve_stats_read": (c_int32, [c_void_p, P(ServeStats)]),
+    "hm_serve_destroy": (None, [c_void_p]),
     "hm_round_host": (c_int32, [c_int32, P(c_double), P(c_double), c_int64]),
     "hm_last_error": (ctypes.c_char_p, []),
     "hm_version": (ctypes.c_char_p, []),

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libhm.so")
 ARCH = os.environ.get("HM_OFFLOAD_ARCH", "gfx950")
 
 HOST_SRCS = ["hm_layout.cpp", "hm_quant.cpp", "hm_pack.cpp"]
-DEVICE_SRCS = ["hm_runtime.hip", "hm_batch.hip"]
+DEVICE_SRCS = ["hm_runtime.hip", "hm_batch.hip", "hm_serve.hip"]
 HEADERS = ["hm_internal.h", "hm_plan.h", "hm_pack.h", "hm_device.h"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-ffp-contract=off"]

@@ -781,6 +781,25 @@ static hm_status mvm_many_multi(std::vector<Entry>& E, int32_t vdt, uint32_t fla
     return HM_OK;
 }
 
+hm_status mvm_blocks(const BlockCall* calls, int ncalls, hipStream_t stream) {
+    if (ncalls == 1)
+        return mvm_many(calls[0].m, calls[0].alpha, calls[0].X, calls[0].ldx, calls[0].nrhs, calls[0].Y,
+                        calls[0].ldy, HM_F64, 0, stream);
+    std::vector<Entry> E;
+    for (int i = 0; i < ncalls; ++i) {
+        Entry e;
+        e.m = calls[i].m;
+        e.alpha = calls[i].alpha;
+        e.X = calls[i].X;
+        e.ldx = calls[i].ldx;
+        e.nrhs = calls[i].nrhs;
+        e.Y = calls[i].Y;
+        e.ldy = calls[i].ldy;
+        E.push_back(std::move(e));
+    }
+    return mvm_many_multi(E, HM_F64, 0, stream);
+}
+
 // Time one candidate (chunk size, blocks per wave) of the many-RHS plan.
 static hm_status time_candidate(hm_matrix* m, int64_t target, int nrb, int nrhs, int32_t vdt, const void* X,
                                 void* Y, int reps, hipStream_t s, double* ms) {

@@ -154,6 +154,22 @@ struct hm_matrix {
 
 namespace hm {
 
+// One block of right-hand sides for mvm_blocks: Y := alpha * M * X + Y in
+// float64, column-major.
+struct BlockCall {
+    hm_matrix* m;
+    double alpha;
+    const double* X;
+    int64_t ldx;
+    int nrhs;
+    double* Y;
+    int64_t ldy;
+};
+
+// Run blocks of distinct matrices through the many-right-hand-side engine
+// (any width >= 1, including single columns), merged as in hm_mvm_batch.
+hm_status mvm_blocks(const BlockCall* calls, int ncalls, hipStream_t stream);
+
 // Size the many-RHS workspaces of a batch (see hm_mvm_batch) ahead of a call.
 hm_status batch_prepare(hm_matrix* const* mats, int32_t nmat, const int32_t* nrhs, int32_t vec_dtype);
 
