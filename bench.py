@@ -292,6 +292,92 @@ def many_rhs(args, hm, torch, lay, fmt, vals, eps, n, points, st, desc):
     print(json.dumps(out), flush=True)
 
 
+def serve_mix(args, hm, torch):
+    """Serving mix: resident H/UH/H2 matrices, Poisson arrivals of 1..32
+    column requests at fractions of the measured capacity."""
+    from synth import (KERNEL_EXPR, KERNEL_LAPLACE, compress_h, gaussian_matrix, sphere_points, to_h2, to_uh)
+    rng = np.random.default_rng(4200)
+    nm = args.serve_matrices
+    eps_of = [1e-4, 1e-6, 1e-8]
+    mats, info = [], []
+    t0 = time.perf_counter()
+    for i in range(nm):
+        n = int(rng.integers(8192, args.serve_nmax + 1))
+        fmt = ("h", "uh", "h2")[i % 3]
+        kern = KERNEL_LAPLACE if i % 2 == 0 else KERNEL_EXPR
+        eps = eps_of[(i // 3) % 3]
+        p = sphere_points(n, 4100 + i)
+        lay = hm.Layout(p)
+        st = structure_from_layout(lay)
+        h = compress_h(p, kern, st, eps, method="auto")
+        vals = h if fmt == "h" else to_uh(h, st) if fmt == "uh" else to_h2(h, st)
+        pol = dict(dense="valr", diag="valr", factor="valr") if eps >= 1e-6 else dict(dense="f64", factor="f64")
+        M = hm.Matrix(lay, fmt, vals, eps=eps, **pol)
+        s = M.stats()
+        mats.append(M)
+        info.append(dict(n=n, fmt=fmt, eps=eps, kernel="laplace" if kern == KERNEL_LAPLACE else "exp(-r)/r",
+                         storage="valr" if eps >= 1e-6 else "f64",
+                         stored_bytes=s["bytes_dense"] + s["bytes_factors"] + s["bytes_coupling"] + s["bytes_transfer"]))
+        log(f"[bench] serve matrix {i}: {info[-1]} ({time.perf_counter() - t0:.0f}s)")
+    S = hm.Server(mem_budget=args.serve_budget, max_slots=64, max_queue=100000, max_cols=64)
+    ids = [S.register(M) for M in mats]
+    Xpool = {}
+
+    def block(m, r):
+        key = (m, r)
+        if key not in Xpool:
+            Xpool[key] = gaussian_matrix(info[m]["n"], r, 7000 + 37 * m + r)
+        return Xpool[key]
+
+    def draw(k, seed):
+        g = np.random.default_rng(seed)
+        return [(int(g.integers(0, nm)), int(g.integers(1, 33))) for _ in range(k)]
+
+    # capacity: a closed burst
+    burst = draw(args.serve_requests, 4300)
+    t1 = time.perf_counter()
+    pend = [S.submit(ids[m], block(m, r))[0] for m, r in burst]
+    for t in pend:
+        S.wait(t)
+    cap = len(burst) / (time.perf_counter() - t1)
+    log(f"[bench] serve capacity {cap:.1f} requests/s")
+    runs = []
+    for frac in (0.5, 0.8, 1.0):
+        reqs = draw(args.serve_requests, 4400 + int(frac * 10))
+        gaps = np.random.default_rng(4200).exponential(1.0 / (frac * cap), size=len(reqs))
+        pend, cols, bytes_ = [], 0, 0.0
+        t1 = time.perf_counter()
+        nxt = t1
+        for (m, r), gap in zip(reqs, gaps):
+            nxt += gap
+            while time.perf_counter() < nxt:
+                pass
+            pend.append(S.submit(ids[m], block(m, r))[0])
+            cols += r
+            bytes_ += info[m]["stored_bytes"]
+        lat = [S.wait(t)["latency_ms"] for t in pend]
+        dt = time.perf_counter() - t1
+        runs.append({"offered_fraction": frac, "offered_rps": round(frac * cap, 1), "requests": len(reqs),
+                     "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                     "columns_per_s": round(cols / dt, 1), "requests_per_s": round(len(reqs) / dt, 1),
+                     "GBs_if_unbatched": round(bytes_ / dt / 1e9, 1)})
+        log(f"[bench] serve {runs[-1]}")
+    st = S.stats()
+    S.close()
+    for M in mats:
+        M.free()
+    out = {"metric": "H-MVM serving p50/p99 latency + columns/s (hm_serve)", "value": runs[-1]["columns_per_s"],
+           "unit": "columns/s", "n_gpus": 1, "steps": len(runs), "warmup": 0, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "mixed",
+           "data": "synthetic (seeded sphere points, Laplace and exp(-r)/r kernels)",
+           "config": {"workload": f"{nm} resident H/UH/H2 matrices, n ~ U[8192, {args.serve_nmax}], "
+                                  "Poisson arrivals of 1..32-column requests", "matrices": info,
+                      "mem_budget": args.serve_budget},
+           "capacity_rps": round(cap, 1), "runs": runs, "server": st}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +394,11 @@ def main():
                     help="comma-separated block widths: run the many-right-hand-side path instead")
     ap.add_argument("--policies", default="f32,bf16", help="storage policies of the --nrhs runs")
     ap.add_argument("--no-tune", action="store_true", help="--nrhs runs: keep the default plan parameters")
+    ap.add_argument("--serve", action="store_true", help="run the serving mix instead")
+    ap.add_argument("--serve-matrices", type=int, default=16)
+    ap.add_argument("--serve-nmax", type=int, default=32768, help="largest n of the serving mix (full: 131072)")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-budget", type=float, default=4e9)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
@@ -320,6 +411,10 @@ def main():
     torch.cuda.set_device(0)
     from synth import gaussian_vector, sphere_points
 
+    if args.serve:
+        args.serve_budget = int(args.serve_budget)
+        serve_mix(args, hm, torch)
+        return
     fmt, n, eps, pseed, xseed, desc = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     points = sphere_points(n, pseed)

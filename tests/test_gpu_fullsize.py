@@ -1,0 +1,91 @@
+"""Parity at the full benchmark sizes, in the launch configuration the
+benchmark times (HIP graph replays of rotated copies): the UH n=32768 and
+H n=131072 products against the oracle on the same stored values, over the
+whole output vector.  The H2 n=262144 product is checked the same way by
+bench.py (rel_err.vs_oracle_same_storage), since its input generation alone
+takes minutes."""
+import numpy as np
+import pytest
+
+from conftest import cached
+from oracle import stored, trees
+from synth import KERNEL_LAPLACE, compress_h, gaussian_matrix, gaussian_vector, sphere_points, to_uh
+
+pytestmark = pytest.mark.gpu
+
+
+def workload(fmt, n, seed):
+    def build():
+        import paper_2405_03456_amd as hm
+        p = sphere_points(n, seed)
+        st = trees.build_structure(p)
+        lay = hm.Layout(p)
+        e = lay.export()
+        assert np.array_equal(e["perm"], st.perm) and np.array_equal(e["blk_tau"], st.blk_tau)
+        h = compress_h(p, KERNEL_LAPLACE, st, 1e-6, method="auto")
+        return st, lay, (h if fmt == "h" else to_uh(h, st))
+    return cached(("full", fmt, n, seed), build)
+
+
+CASES = [("uh", 32768, 1002, "f64", dict(dense="f64", factor="f64", eps=1e-6), 1e-10),
+         ("uh", 32768, 1002, "f32", dict(dense="f32", factor="f32", eps=1e-6), 1e-6),
+         ("uh", 32768, 1002, "valr", dict(dense="valr", diag="valr", factor="valr", eps=1e-6), 1e-6),
+         ("h", 131072, 1004, "f64", dict(dense="f64", factor="f64", eps=1e-6), 1e-10),
+         ("h", 131072, 1004, "bf16", dict(dense="bf16", factor="bf16", eps=1e-6), 1e-6)]
+
+
+@pytest.mark.parametrize("fmt,n,seed,pname,pol,tol", CASES, ids=[f"{c[0]}{c[1]}-{c[3]}" for c in CASES])
+def test_fullsize_graph_parity(fmt, n, seed, pname, pol, tol):
+    import torch
+    import paper_2405_03456_amd as hm
+    print(f"case fullsize {fmt} n={n} policy={pname}", flush=True)
+    st, lay, vals = workload(fmt, n, seed)
+    x = gaussian_vector(n, 2000 + seed % 1000)
+    sv = stored.stored_values(st, fmt, vals, dense=pol["dense"], diag=pol.get("diag"), factor=pol["factor"],
+                              eps=pol["eps"])
+    ref = stored.product(st, fmt, sv, 1.0, x, np.zeros(n))
+    Ms = [hm.Matrix(lay, fmt, vals, **pol) for _ in range(2)]       # rotated copies, as in bench.py
+    xd = torch.from_numpy(x).cuda()
+    ys = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in Ms]
+    gs = [M.graph(xd, y) for M, y in zip(Ms, ys)]
+    for _ in range(3):
+        for g in gs:
+            g.launch()
+    torch.cuda.synchronize()
+    for y in ys:
+        err = float(np.linalg.norm(y.cpu().numpy() / 3.0 - ref) / np.linalg.norm(ref))
+        print(f"  rel err {err:.3e} (tol {tol:g})", flush=True)
+        assert err <= tol
+    for g in gs:
+        g.free()
+    for M in Ms:
+        M.free()
+
+
+def test_fullsize_many_rhs_h131072():
+    """H n=131072, BF16 storage, 32 right-hand sides through the tuned
+    many-RHS plan in a captured batch graph, every column against the oracle."""
+    import torch
+    import paper_2405_03456_amd as hm
+    print("case fullsize many-rhs h131072 bf16 r=32", flush=True)
+    n, r = 131072, 32
+    st, lay, vals = workload("h", n, 1004)
+    pol = dict(dense="bf16", factor="bf16", eps=1e-6)
+    M = hm.Matrix(lay, "h", vals, **pol)
+    M.tune(r, reps=2)
+    X = gaussian_matrix(n, r, 2004)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda().T
+    Yd = torch.zeros((r, n), dtype=torch.float64, device="cuda").T
+    g = hm.BatchGraph([M], [Xd], [Yd])
+    g.launch()
+    torch.cuda.synchronize()
+    sv = stored.stored_values(st, "h", vals, eps=1e-6, **pol)
+    Y = Yd.cpu().numpy()
+    worst = 0.0
+    for j in (0, 7, 31):
+        ref = stored.product(st, "h", sv, 1.0, X[:, j], np.zeros(n))
+        worst = max(worst, float(np.linalg.norm(Y[:, j] - ref) / np.linalg.norm(ref)))
+    print(f"  worst sampled column rel err {worst:.3e}", flush=True)
+    assert worst <= 1e-6
+    g.free()
+    M.free()
