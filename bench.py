@@ -45,6 +45,9 @@ WORKLOADS = {
 POLICIES = {
     "f64": dict(dense="f64", factor="f64", coupling="f64"),
     "f32": dict(dense="f32", factor="f32", coupling="f32"),
+    # VALR at the workload's eps: per-column formats of the bases, direct
+    # formats of dense/coupling blocks, FP64 diagonal near field
+    "valr": dict(dense="valr", diag="valr", factor="valr", coupling="valr"),
 }
 
 
@@ -187,8 +190,8 @@ def cpu_baseline(fmt, st, vals, x, budget_s, gpu_results, points, eps):
     errs = {}
     for name, r in gpu_results.items():
         pol = POLICIES[name]
-        sv = stored.stored_values(ost, fmt, vals, dense=pol["dense"], factor=pol["factor"],
-                                  coupling=pol["coupling"])
+        sv = stored.stored_values(ost, fmt, vals, dense=pol["dense"], diag=pol.get("diag"), factor=pol["factor"],
+                                  coupling=pol["coupling"], eps=eps)
         rs = ref if name == "f64" else stored.product(ost, fmt, sv, 1.0, x, y0)
         errs[name] = {"vs_oracle_same_storage": float(np.linalg.norm(r["y"] - rs) / np.linalg.norm(rs))}
     # error against the dense kernel matrix on sampled rows (the stated accuracy)
@@ -449,6 +452,7 @@ def main():
         tr = measured_traffic(args.workload, "f64")
         main_s["roofline"]["traffic"] = None if tr is None else int(tr)
     f32_s = summarize(results["f32"], args.steps)
+    valr_s = summarize(results["valr"], args.steps)
     out = {
         "metric": METRIC,
         "value": round(main_s["gbs"], 1),
@@ -470,6 +474,12 @@ def main():
         "algorithmic_bytes_per_matvec": int(main_s["algorithmic_bytes"]),
         "roofline": main_s["roofline"],
         "phases_f64": main_s["phases"],
+        "valr_storage": {"GBs": round(valr_s["gbs"], 1), "matvecs_per_s": round(valr_s["matvecs_per_s"], 1),
+                         "ms_per_step": round(valr_s["ms_per_step"], 5),
+                         "speedup_vs_f64": round(main_s["ms_per_step"] / valr_s["ms_per_step"], 3),
+                         "algorithmic_bytes_per_matvec": int(valr_s["algorithmic_bytes"]),
+                         "bytes_per_dtype": results["valr"]["stats"]["bytes_per_dtype"],
+                         "roofline": valr_s["roofline"]},
         "f32_storage": {"GBs": round(f32_s["gbs"], 1), "matvecs_per_s": round(f32_s["matvecs_per_s"], 1),
                         "ms_per_step": round(f32_s["ms_per_step"], 5),
                         "speedup_vs_f64": round(main_s["ms_per_step"] / f32_s["ms_per_step"], 3),

@@ -96,13 +96,18 @@ __device__ __forceinline__ ItemPos item_pos(const DItem* __restrict__ items, int
     return ItemPos{it, d.tile0, d.tile0 + (d.ncols + V - 1) / V, d.vec_off, d.scale_off};
 }
 
+// Coefficient vectors (mode-0 outputs) are kept in one precision only: float64
+// (wsm) when the matrix accumulates in float64, else float32 (wsm32).  Only
+// the gathered x (entries below n) is held in both.
 struct Outs {
-    double* wsm;        // coefficient outputs (mode 0), entry-major
-    float* wsm32;
+    double* wsm;        // float64 entries, entry-major
+    float* wsm32;       // float32 entries
     double* ym;         // y outputs (modes 1, 2) in cluster order, entry-major
     double* partm;      // partial sums of split owners
     const double* scales;
     int R;
+    int64_t n;          // entries below n hold x (both precisions)
+    bool mat64;         // the matrix accumulates in float64
 };
 
 __device__ __forceinline__ void put(const DTask& tk, const Outs& o, int row, int j, double v) {
@@ -111,8 +116,10 @@ __device__ __forceinline__ void put(const DTask& tk, const Outs& o, int row, int
         o.partm[((int64_t)tk.part_off + (int64_t)tk.local * tk.nrows + row) * o.R + j] = v;
     } else if (tk.mode == 0) {
         const int64_t i = (int64_t)(tk.out_off + row) * o.R + j;
-        o.wsm[i] = v;
-        o.wsm32[i] = (float)v;
+        if (o.mat64)
+            o.wsm[i] = v;
+        else
+            o.wsm32[i] = (float)v;
     } else {
         o.ym[(int64_t)(tk.out_off + row) * o.R + j] += v;
     }
@@ -178,8 +185,12 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
             T s = (T)1;
             if (mysc >= 0) s = (T)o.scales[mysc + cb + c];
             if (!valid) s = (T)0;
+            // float64 products read float64 inputs where they exist: always
+            // in a float64 matrix, only x in a float32 one
+            const bool wide_in = ACC64 && (o.mat64 || myvec + cb + c < o.n);
 #pragma unroll
-            for (int b = 0; b < NRB; ++b) f.b[c][b] = (ACC64 ? (T)wsm[wi + 16 * b] : (T)wsm32[wi + 16 * b]) * s;
+            for (int b = 0; b < NRB; ++b)
+                f.b[c][b] = (wide_in ? (T)wsm[wi + 16 * b] : (T)wsm32[wi + 16 * b]) * s;
         }
     };
     auto compute = [&](const Buf& f) {
@@ -254,11 +265,12 @@ template <bool ACC64, int NRB, int MASK>
 __device__ __forceinline__ void task_wave(const DTask* __restrict__ tasks, int64_t w, int nblk,
                                           const DItem* __restrict__ items, const uint8_t* __restrict__ data,
                                           const double* __restrict__ scales, double* wsm, float* wsm32,
-                                          double* __restrict__ ym, double* __restrict__ partm, int R, int lane) {
+                                          double* __restrict__ ym, double* __restrict__ partm, int R, int64_t n,
+                                          int lane) {
     const int64_t t = w / nblk;
     const int j0 = (int)(w - t * nblk) * 16 * NRB;
     const DTask tk = tasks[t];
-    const Outs o{wsm, wsm32, ym, partm, scales, R};
+    const Outs o{wsm, wsm32, ym, partm, scales, R, n, ACC64};
     const int dt = tk.k0 < tk.k1 ? (int)items[tk.item_start].dtype : -1;
     // MASK: the dtypes that may occur in the launched stage (one bit per
     // dtype); the other cases are not compiled, which keeps the register
@@ -301,11 +313,12 @@ template <bool ACC64, int NRB, int MASK>
 __global__ __launch_bounds__(256) void k_tasks(const DTask* __restrict__ tasks, int ntasks, int nblk,
                                                const DItem* __restrict__ items, const uint8_t* __restrict__ data,
                                                const double* __restrict__ scales, double* wsm, float* wsm32,
-                                               double* __restrict__ ym, double* __restrict__ partm, int R) {
+                                               double* __restrict__ ym, double* __restrict__ partm, int R,
+                                               int64_t n) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t w = (int64_t)blockIdx.x * 4 + wave;
     if (w >= (int64_t)ntasks * nblk) return;
-    task_wave<ACC64, NRB, MASK>(tasks, w, nblk, items, data, scales, wsm, wsm32, ym, partm, R, threadIdx.x & 63);
+    task_wave<ACC64, NRB, MASK>(tasks, w, nblk, items, data, scales, wsm, wsm32, ym, partm, R, n, threadIdx.x & 63);
 }
 
 // Several matrices in one launch: the stage tasks of up to kMaxJobs
@@ -322,6 +335,7 @@ struct Job {
     double* ym;
     double* partm;
     int64_t wave0;
+    int64_t n;
     int32_t nblk, R;
 };
 struct Jobs {
@@ -339,12 +353,12 @@ __global__ __launch_bounds__(256) void k_tasks_multi(const Jobs J) {
     while (ji + 1 < J.njobs && w >= J.j[ji + 1].wave0) ++ji;
     const Job& jb = J.j[ji];
     task_wave<ACC64, NRB, MASK>(jb.tasks, w - jb.wave0, jb.nblk, jb.items, jb.data, jb.scales, jb.wsm, jb.wsm32,
-                                jb.ym, jb.partm, jb.R, threadIdx.x & 63);
+                                jb.ym, jb.partm, jb.R, jb.n, threadIdx.x & 63);
 }
 
 // Sum the partial results of split owners in task order, one wave per owner.
 __device__ __forceinline__ void reduce_owner(const DOwner& ow, const double* __restrict__ partm, double* wsm,
-                                             float* wsm32, double* __restrict__ ym, int R, int lane) {
+                                             float* wsm32, double* __restrict__ ym, int R, bool mat64, int lane) {
     const int64_t span = (int64_t)ow.nrows * R;
     for (int64_t idx = lane; idx < span; idx += 64) {
         const double* p = partm + (int64_t)ow.part_off * R + idx;
@@ -352,8 +366,10 @@ __device__ __forceinline__ void reduce_owner(const DOwner& ow, const double* __r
         for (int l = 0; l < ow.ntasks; ++l) v += p[(int64_t)l * span];
         const int64_t e = (int64_t)ow.out_off * R + idx;
         if (ow.mode == 0) {
-            wsm[e] = v;
-            wsm32[e] = (float)v;
+            if (mat64)
+                wsm[e] = v;
+            else
+                wsm32[e] = (float)v;
         } else {
             ym[e] += v;
         }
@@ -362,10 +378,11 @@ __device__ __forceinline__ void reduce_owner(const DOwner& ow, const double* __r
 
 __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list, int nlist,
                                                 const DOwner* __restrict__ owners, const double* __restrict__ partm,
-                                                double* wsm, float* wsm32, double* __restrict__ ym, int R) {
+                                                double* wsm, float* wsm32, double* __restrict__ ym, int R,
+                                                int mat64) {
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= nlist) return;
-    reduce_owner(owners[list[i]], partm, wsm, wsm32, ym, R, threadIdx.x & 63);
+    reduce_owner(owners[list[i]], partm, wsm, wsm32, ym, R, mat64 != 0, threadIdx.x & 63);
 }
 
 struct RJob {
@@ -376,7 +393,7 @@ struct RJob {
     float* wsm32;
     double* ym;
     int64_t wave0;
-    int32_t R;
+    int32_t R, mat64;
 };
 struct RJobs {
     int32_t njobs;
@@ -390,7 +407,8 @@ __global__ __launch_bounds__(256) void k_reduce_multi(const RJobs J) {
     int ji = 0;
     while (ji + 1 < J.njobs && i >= J.j[ji + 1].wave0) ++ji;
     const RJob& jb = J.j[ji];
-    reduce_owner(jb.owners[jb.list[i - jb.wave0]], jb.partm, jb.wsm, jb.wsm32, jb.ym, jb.R, threadIdx.x & 63);
+    reduce_owner(jb.owners[jb.list[i - jb.wave0]], jb.partm, jb.wsm, jb.wsm32, jb.ym, jb.R, jb.mat64 != 0,
+                 threadIdx.x & 63);
 }
 
 // X (column-major, ldx) -> wsm / wsm32 in cluster order, entry-major; the
@@ -453,7 +471,7 @@ __global__ __launch_bounds__(256) void k_scatter(YT* __restrict__ Y, int64_t ldy
 }
 
 using TaskKernel = void (*)(const DTask*, int, int, const DItem*, const uint8_t*, const double*, double*, float*,
-                            double*, double*, int);
+                            double*, double*, int, int64_t);
 
 // [acc64][NRB - 1][dtype of a single-dtype stage, or 5 = several]
 #define HM_MR_ROW(A, N)                                                                                  \
@@ -654,12 +672,12 @@ static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx
             hipLaunchKernelGGL(mr::kTasks[m->acc64 ? 1 : 0][nrb - 1][mr::variant(ph.dtype_mask)],
                                dim3((unsigned)((waves + 3) / 4)), dim3(256), 0,
                                s, m->mr_tasks + ph.t0, ph.ntasks, nblk, m->items, m->data, m->scales, m->wsm,
-                               m->wsm32, m->ym, m->partm, R);
+                               m->wsm32, m->ym, m->partm, R, n);
             if (timing) timing_end(ph, s, ev);
         }
         if (ph.nreduce > 0)
             hipLaunchKernelGGL(mr::k_reduce, dim3((unsigned)((ph.nreduce + 3) / 4)), dim3(256), 0, s, ph.reduce,
-                               ph.nreduce, m->mr_owners, m->partm, m->wsm, m->wsm32, m->ym, R);
+                               ph.nreduce, m->mr_owners, m->partm, m->wsm, m->wsm32, m->ym, R, m->acc64 ? 1 : 0);
     }
     if (!joined) {
         (void)hipEventRecord(m->ev_join, m->aux);
@@ -732,7 +750,7 @@ static hm_status mvm_many_multi(std::vector<Entry>& E, int32_t vdt, uint32_t fla
                 if (e.level[i] != L || ph.nreduce == 0) continue;
                 if (J.njobs == mr::kMaxJobs) flush();
                 J.j[J.njobs++] = mr::RJob{ph.reduce, e.m->mr_owners, e.m->partm, e.m->wsm, e.m->wsm32, e.m->ym,
-                                          J.total, e.R};
+                                          J.total, e.R, e.m->acc64 ? 1 : 0};
                 J.total += ph.nreduce;
             }
         flush();
@@ -756,7 +774,7 @@ static hm_status mvm_many_multi(std::vector<Entry>& E, int32_t vdt, uint32_t fla
                         if (e.level[i] != L || ph.ntasks == 0) continue;
                         if (J.njobs == mr::kMaxJobs) flush();
                         J.j[J.njobs++] = mr::Job{e.m->mr_tasks + ph.t0, e.m->items, e.m->data, e.m->scales, e.m->wsm,
-                                                 e.m->wsm32, e.m->ym, e.m->partm, J.total, e.nblk, e.R};
+                                                 e.m->wsm32, e.m->ym, e.m->partm, J.total, e.m->n, e.nblk, e.R};
                         J.total += (int64_t)ph.ntasks * e.nblk;
                         mask |= ph.dtype_mask;
                     }

@@ -144,20 +144,18 @@ struct Builder {
     struct Run {
         int32_t src, c0, k;
     };
-    // deltas: per-column error budget delta_j of VALR (unused otherwise)
+    // deltas: per-column error budget delta_j of VALR (unused otherwise);
+    // breaks (optional): brk[j] != 0 forces a run to start at column j
     std::vector<Run> add_factor(const double* A, int64_t m, int64_t k, const double* colfactor, int cls,
-                                const std::vector<double>& deltas) {
+                                const std::vector<double>& deltas, const std::vector<uint8_t>* brk = nullptr) {
         std::vector<Run> runs;
         if (k == 0) return runs;
-        if (factor_dt != HM_VALR_AUTO) {
-            runs.push_back(Run{add_source(A, m, k, factor_dt, colfactor, cls), 0, (int32_t)k});
-            return runs;
-        }
-        std::vector<int32_t> dts(k);
-        for (int64_t j = 0; j < k; ++j) dts[j] = valr_choose(A + j * m, m, deltas[(size_t)j]);
+        std::vector<int32_t> dts(k, factor_dt);
+        if (factor_dt == HM_VALR_AUTO)
+            for (int64_t j = 0; j < k; ++j) dts[j] = valr_choose(A + j * m, m, deltas[(size_t)j]);
         int64_t j0 = 0;
         for (int64_t j = 1; j <= k; ++j)
-            if (j == k || dts[j] != dts[j0]) {
+            if (j == k || dts[j] != dts[j0] || (brk && (*brk)[(size_t)j])) {
                 runs.push_back(Run{add_source(A + j0 * m, m, j - j0, dts[j0], colfactor ? colfactor + j0 : nullptr, cls),
                                    (int32_t)j0, (int32_t)(j - j0)});
                 j0 = j;
@@ -218,6 +216,7 @@ struct Builder {
     std::vector<DOwner> owners;
     std::vector<DItem> items;
     std::vector<uint8_t> item_floating;
+    std::vector<std::pair<int32_t, int32_t>> item_use;   // (source, index of its Use) per item
     std::vector<std::vector<DTask>> stage_tasks;
     std::vector<int64_t> stage_bytes;
     std::vector<std::string> stage_names;
@@ -270,12 +269,56 @@ struct Builder {
         it.acc64 = S.dtype == HM_F64 ? 1 : 0;
         items.push_back(it);
         item_floating.push_back(floats ? 1 : 0);
+        item_use.emplace_back(s, (int32_t)S.uses.size());
         cur.nitems++;
         cur_cols += (int32_t)ncols;
         S.uses.push_back(Use{it.data_off, r0, nr, transposed});
     }
 
+    // Order the owner's items by (floating, dtype), stably, so that each dtype
+    // is one run of columns and tasks (which hold one dtype) are cut only at
+    // the few run boundaries; mixed-format factors would otherwise split an
+    // owner at every format change.  Columns, tiles and data offsets are
+    // reassigned in the new order (the items' data is one contiguous block).
+    void group_items() {
+        const int32_t n = cur.nitems, i0 = cur.item0;
+        if (n < 2) return;
+        std::vector<int32_t> order(n);
+        for (int32_t i = 0; i < n; ++i) order[i] = i;
+        auto key = [&](int32_t i) { return item_floating[i0 + i] * 8 + items[i0 + i].dtype; };
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
+        bool same = true;
+        for (int32_t i = 0; i < n; ++i) same &= order[i] == i;
+        if (same) return;
+        std::vector<DItem> it(n);
+        std::vector<uint8_t> fl(n);
+        std::vector<std::pair<int32_t, int32_t>> us(n);
+        int64_t off = items[i0].data_off;
+        int32_t col = 0, tile = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            const int32_t i = i0 + order[k];
+            DItem d = items[i];
+            const int64_t tiles = tile_count(d.dtype, d.ncols);
+            d.data_off = off;
+            d.col0 = col;
+            d.tile0 = tile;
+            off += tiles * cur.nrows * 16;
+            col += d.ncols;
+            tile += (int32_t)tiles;
+            it[k] = d;
+            fl[k] = item_floating[i];
+            us[k] = item_use[i];
+            src[us[k].first].uses[us[k].second].data_off = d.data_off;
+        }
+        for (int32_t k = 0; k < n; ++k) {
+            items[i0 + k] = it[k];
+            item_floating[i0 + k] = fl[k];
+            item_use[i0 + k] = us[k];
+        }
+    }
+
     void end_owner() {
+        group_items();
         const int32_t owner_id = (int32_t)owners.size();
         // cut the owner's columns into tasks of about opt.task_bytes, on tile
         // boundaries, never mixing floating and fixed items in one task
@@ -437,12 +480,61 @@ struct Builder {
         return add_factor(A, m, k, nullptr, 1, d);
     }
 
+    // Input-side bases under VALR (UH column bases, H2 leaf column bases):
+    // the basis is a transposed owner whose rows are its columns, and an
+    // owner's rows must share one format.  The columns are therefore reordered
+    // so that equal formats are adjacent (stable), giving one owner per format
+    // instead of one per run; perm[p] = original column at position p (empty:
+    // unchanged).  Every consumer of the coefficient vector (coupling columns,
+    // H2 transfer rows) is permuted the same way, so the product is unchanged.
+    std::vector<Run> grouped_basis(const double* A, int64_t m, int64_t k, const double* const* sv, int32_t v,
+                                   std::vector<int32_t>& perm) {
+        perm.clear();
+        if (factor_dt != HM_VALR_AUTO || k == 0) return basis_factor(A, m, k, sv, v);
+        std::vector<double> d = deltas_for(sv[v], k, eps * norm2(sv[v], k) / (double)k);
+        std::vector<int32_t> dts((size_t)k);
+        for (int64_t j = 0; j < k; ++j) dts[(size_t)j] = valr_choose(A + j * m, m, d[(size_t)j]);
+        std::vector<int32_t> order((size_t)k);
+        for (int64_t j = 0; j < k; ++j) order[(size_t)j] = (int32_t)j;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return dts[a] < dts[b]; });
+        bool same = true;
+        for (int64_t j = 0; j < k; ++j) same &= order[(size_t)j] == j;
+        if (same) return add_factor(A, m, k, nullptr, 1, d);
+        pool.emplace_back((size_t)(m * k));
+        std::vector<double>& P = pool.back();
+        std::vector<double> dp((size_t)k);
+        for (int64_t p = 0; p < k; ++p) {
+            std::memcpy(P.data() + p * m, A + (int64_t)order[(size_t)p] * m, sizeof(double) * (size_t)m);
+            dp[(size_t)p] = d[(size_t)order[(size_t)p]];
+        }
+        perm = order;
+        return add_factor(P.data(), m, k, nullptr, 1, dp);
+    }
+    // columns of a (rows x cols) matrix in the order perm (empty: A itself)
+    const double* permute_cols(const double* A, int64_t rows, int64_t cols, const std::vector<int32_t>& perm) {
+        if (perm.empty()) return A;
+        pool.emplace_back((size_t)(rows * cols));
+        std::vector<double>& P = pool.back();
+        for (int64_t p = 0; p < cols; ++p)
+            std::memcpy(P.data() + p * rows, A + (int64_t)perm[(size_t)p] * rows, sizeof(double) * (size_t)rows);
+        return P.data();
+    }
+    // rows of a (rows x cols) column-major matrix in the order perm
+    const double* permute_rows(const double* A, int64_t rows, int64_t cols, const std::vector<int32_t>& perm) {
+        if (perm.empty()) return A;
+        pool.emplace_back((size_t)(rows * cols));
+        std::vector<double>& P = pool.back();
+        for (int64_t j = 0; j < cols; ++j)
+            for (int64_t p = 0; p < rows; ++p) P[(size_t)(p + j * rows)] = A[perm[(size_t)p] + j * rows];
+        return P.data();
+    }
+
     // --------------------------------------------------------------- H
     bool build_h() {
         if (!check_dense()) return false;
         if (!V->rank || !V->W || !V->sigma || !V->X) return check(false, "H needs rank, W, sigma, X");
         const int64_t nb = (int64_t)L.blk_tau.size();
-        std::vector<int32_t> tb_off(nb, -1), dsrc(nb, -1);
+        std::vector<int32_t> dsrc(nb, -1);
         std::vector<std::vector<Run>> urun(nb);
         for (int64_t b = 0; b < nb; ++b) {
             if (!L.blk_adm[b]) continue;
@@ -457,11 +549,11 @@ struct Builder {
         std::vector<std::vector<int32_t>> col_lr(L.node_begin.size());
         for (int64_t b = 0; b < nb; ++b)
             if (L.blk_adm[b] && V->rank[b] > 0) col_lr[L.blk_sigma[b]].push_back((int32_t)b);
-        for (auto& bl : col_lr)
-            for (int32_t b : bl) {
-                tb_off[b] = (int32_t)ws;
-                ws += V->rank[b];
-            }
+        // position of t_b[j] in the workspace; with VALR the stacked columns of
+        // a block column are reordered by the format of X (stable), so X^T
+        // gives one owner per format and t_b may be scattered in its block
+        // column's range
+        std::vector<std::vector<int32_t>> tpos(nb);
         const int32_t pa = new_stage("h_vt");
         for (int32_t s = 0; s < (int32_t)col_lr.size(); ++s) {
             if (col_lr[s].empty()) continue;
@@ -477,24 +569,63 @@ struct Builder {
             for (int32_t b : col_lr[s]) {
                 const int32_t k = V->rank[b];
                 std::memcpy(Xs.data() + c0 * ms, V->X[b], sizeof(double) * (size_t)(ms * k));
-                std::vector<double> d;
+                std::vector<double> d((size_t)k, 0.0);
                 if (factor_dt == HM_VALR_AUTO)
                     d = deltas_for(V->sigma[b], k, eps * norm2(V->sigma[b], k) / (1.0 + 2.0 * k));
-                urun[b] = add_factor(V->W[b], L.size(L.blk_tau[b]), k, V->sigma[b], 1, d);
                 Ds.insert(Ds.end(), d.begin(), d.end());
+                c0 += k;
+            }
+            // order of the stacked columns: by X's format under VALR
+            std::vector<int32_t> order((size_t)K), inv((size_t)K);
+            for (int64_t o = 0; o < K; ++o) order[(size_t)o] = (int32_t)o;
+            if (factor_dt == HM_VALR_AUTO) {
+                std::vector<int32_t> dtx((size_t)K);
+                for (int64_t o = 0; o < K; ++o) dtx[(size_t)o] = valr_choose(Xs.data() + o * ms, ms, Ds[(size_t)o]);
+                std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return dtx[a] < dtx[b]; });
+            }
+            for (int64_t p = 0; p < K; ++p) inv[(size_t)order[(size_t)p]] = (int32_t)p;
+            const int32_t base = (int32_t)ws;
+            ws += K;
+            // U side: runs of W_b never cross a jump of t_b's positions
+            c0 = 0;
+            uscale.clear();
+            for (int32_t b : col_lr[s]) {
+                const int32_t k = V->rank[b];
+                std::vector<uint8_t> brk((size_t)k, 0);
+                tpos[b].resize((size_t)k);
+                for (int32_t j = 0; j < k; ++j) {
+                    tpos[b][(size_t)j] = base + inv[(size_t)(c0 + j)];
+                    brk[(size_t)j] = j > 0 && tpos[b][(size_t)j] != tpos[b][(size_t)j - 1] + 1;
+                }
+                std::vector<double> d(Ds.begin() + c0, Ds.begin() + c0 + k);
+                urun[b] = add_factor(V->W[b], L.size(L.blk_tau[b]), k, V->sigma[b], 1, d, &brk);
                 for (int32_t j = 0; j < k; ++j) uscale.push_back(run_scale(urun[b], j));
                 c0 += k;
             }
-            std::vector<Run> xr = add_factor(Xs.data(), ms, K, nullptr, 1, Ds);
+            const double* Xo = Xs.data();
+            std::vector<double> Dp = Ds;
+            bool same = true;
+            for (int64_t p = 0; p < K; ++p) same &= order[(size_t)p] == p;
+            if (!same) {
+                pool.emplace_back((size_t)(ms * K));
+                std::vector<double>& Xp = pool.back();
+                for (int64_t p = 0; p < K; ++p) {
+                    std::memcpy(Xp.data() + p * ms, Xs.data() + (int64_t)order[(size_t)p] * ms,
+                                sizeof(double) * (size_t)ms);
+                    Dp[(size_t)p] = Ds[(size_t)order[(size_t)p]];
+                }
+                Xo = Xp.data();
+            }
+            std::vector<Run> xr = add_factor(Xo, ms, K, nullptr, 1, Dp);
             for (const Run& r : xr) {
                 // row scale: X's range scale times the U-side column scale
                 // (sigma_j and W's range scale) of the same column
                 std::vector<int64_t> a, bb;
                 for (int32_t j = 0; j < r.k; ++j) {
                     a.push_back(src[r.src].scale_off >= 0 ? src[r.src].scale_off + j : -1);
-                    bb.push_back(uscale[(size_t)(r.c0 + j)]);
+                    bb.push_back(uscale[(size_t)order[(size_t)(r.c0 + j)]]);
                 }
-                begin_owner(pa, r.k, 0, tb_off[col_lr[s][0]] + r.c0, fold_list(a, bb));
+                begin_owner(pa, r.k, 0, base + r.c0, fold_list(a, bb));
                 add_item(r.src, 0, true, (int32_t)L.node_begin[s]);
                 end_owner();
             }
@@ -507,7 +638,7 @@ struct Builder {
                 const int64_t r0 = L.node_begin[rho] - L.node_begin[t];
                 for (int32_t b : row_blocks[t])
                     if (L.blk_adm[b] && V->rank[b] > 0)
-                        for (const Run& r : urun[b]) add_item(r.src, r0, false, tb_off[b] + r.c0, true);
+                        for (const Run& r : urun[b]) add_item(r.src, r0, false, tpos[b][(size_t)r.c0], true);
             }
             add_dense_items(rho, anc, dsrc);
             end_owner();
@@ -538,10 +669,11 @@ struct Builder {
                 if (kr > 0 && kc > 0 && !V->coupling[b]) return check(false, "missing coupling");
             }
         const int32_t pf = new_stage("uh_fwd");
+        std::vector<std::vector<int32_t>> cperm(N);
         for (int32_t v = 0; v < N; ++v) {
             const int32_t kc = V->col_rank[v];
             if (kc == 0) continue;
-            for (const Run& r : basis_factor(V->col_basis[v], L.size(v), kc, V->col_sv, v)) {
+            for (const Run& r : grouped_basis(V->col_basis[v], L.size(v), kc, V->col_sv, v, cperm[v])) {
                 begin_owner(pf, r.k, 0, s_off[v] + r.c0, src[r.src].scale_off);
                 add_item(r.src, 0, true, (int32_t)L.node_begin[v]);
                 end_owner();
@@ -562,7 +694,7 @@ struct Builder {
                 const int32_t s = L.blk_sigma[b];
                 const int32_t kc = V->col_rank[s];
                 if (kc == 0) continue;
-                int32_t cs = add_source(V->coupling[b], kr, kc, coup_dt, nullptr, 2);
+                int32_t cs = add_source(permute_cols(V->coupling[b], kr, kc, cperm[s]), kr, kc, coup_dt, nullptr, 2);
                 add_item(cs, 0, false, s_off[s]);
             }
             end_owner();
@@ -605,10 +737,11 @@ struct Builder {
             if (kr > 0) { t_off[v] = (int32_t)ws; ws += kr; }
         }
         const int32_t pl = new_stage("h2_up_leaf");
+        std::vector<std::vector<int32_t>> cperm(N);
         for (int32_t g : leaves) {
             const int32_t kc = V->col_rank[g];
             if (kc == 0) continue;
-            for (const Run& r : basis_factor(V->col_basis[g], L.size(g), kc, V->col_sv, g)) {
+            for (const Run& r : grouped_basis(V->col_basis[g], L.size(g), kc, V->col_sv, g, cperm[g])) {
                 begin_owner(pl, r.k, 0, s_off[g] + r.c0, src[r.src].scale_off);
                 add_item(r.src, 0, true, (int32_t)L.node_begin[g]);
                 end_owner();
@@ -629,7 +762,8 @@ struct Builder {
                     const int32_t kcc = V->col_rank[c];
                     if (kcc == 0) continue;
                     // F_c is kcc x kc; F_c^T is kc x kcc, scaled per column of F_c^T
-                    int32_t fs = add_source_transposed(V->col_transfer[c], kcc, kc, coup_dt, 3);
+                    int32_t fs = add_source_transposed(permute_rows(V->col_transfer[c], kcc, kc, cperm[c]), kcc, kc,
+                                                       coup_dt, 3);
                     add_item(fs, 0, false, s_off[c]);
                 }
                 end_owner();
@@ -666,7 +800,7 @@ struct Builder {
                     const int32_t kc = V->col_rank[s];
                     if (kc == 0) continue;
                     if (!V->coupling[b]) return check(false, "missing coupling");
-                    int32_t cs = add_source(V->coupling[b], kr, kc, coup_dt, nullptr, 2);
+                    int32_t cs = add_source(permute_cols(V->coupling[b], kr, kc, cperm[s]), kr, kc, coup_dt, nullptr, 2);
                     add_item(cs, 0, false, s_off[s]);
                 }
                 end_owner();

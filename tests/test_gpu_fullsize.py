@@ -79,7 +79,7 @@ def test_fullsize_many_rhs_h131072():
     g = hm.BatchGraph([M], [Xd], [Yd])
     g.launch()
     torch.cuda.synchronize()
-    sv = stored.stored_values(st, "h", vals, eps=1e-6, **pol)
+    sv = stored.stored_values(st, "h", vals, dense="bf16", factor="bf16", eps=1e-6)
     Y = Yd.cpu().numpy()
     worst = 0.0
     for j in (0, 7, 31):
