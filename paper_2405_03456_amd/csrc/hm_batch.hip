@@ -271,7 +271,7 @@ __device__ __forceinline__ void task_wave(const DTask* __restrict__ tasks, int64
     const int j0 = (int)(w - t * nblk) * 16 * NRB;
     const DTask tk = tasks[t];
     const Outs o{wsm, wsm32, ym, partm, scales, R, n, ACC64};
-    const int dt = tk.k0 < tk.k1 ? (int)items[tk.item_start].dtype : -1;
+    const int dt = tk.dtype;
     // MASK: the dtypes that may occur in the launched stage (one bit per
     // dtype); the other cases are not compiled, which keeps the register
     // budget of single-dtype stages low

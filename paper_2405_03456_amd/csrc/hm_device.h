@@ -126,6 +126,7 @@ struct hm_matrix {
     // second stream for the independent dense stage, with fork/join events
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int32_t aux_grid = 0;      // workgroup cap of the second-stream stage (0 = one wave per task)
     hm_stats stats{};
     int64_t ws_elems = 0;      // x in cluster order + coefficient vectors
     int64_t part_elems = 0;    // partial sums of split owners

@@ -390,7 +390,8 @@ struct Builder {
             t.k1 = tile_of(t.c1);
             t.stream = stream;
             t.nrows = cur.nrows;
-            t.mode = cur.mode;
+            t.mode = (int16_t)cur.mode;
+            t.dtype = (int16_t)(t.c0 < t.c1 ? items[t.item_start].dtype : -1);
             t.out_off = cur.out_off;
             t.ntasks = cur.ntasks;
             t.part_off = cur.part_off;
@@ -958,6 +959,7 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
                 why = "task copy of owner fields";
                 return false;
             }
+            if (t.dtype != (t.c0 < t.c1 ? P.items[t.item_start].dtype : -1)) { why = "task dtype"; return false; }
             int32_t ncols = 0;
             if (ow.nitems) ncols = P.items[ow.item0 + ow.nitems - 1].col0 + P.items[ow.item0 + ow.nitems - 1].ncols;
             if (t.c0 < 0 || t.c0 > t.c1 || t.c1 > ncols || t.local < 0 || t.local >= ow.ntasks) {

@@ -50,9 +50,12 @@ struct DTask {            // 64 bytes; carries its owner's fields so a wave
     int32_t c0, c1;       // owner columns [c0, c1)
     int32_t item_start;   // absolute index of the item holding column c0
     int32_t local;        // task index within its owner
-    int32_t nrows, mode, out_off, ntasks, part_off, rscale_off;
+    int32_t nrows;
+    int16_t mode;
+    int16_t dtype;        // dtype of every item the task touches (-1: no columns)
+    int32_t out_off, ntasks, part_off, rscale_off;
     int32_t k0, k1;       // owner tiles [k0, k1)
-    int32_t pad;
+    int32_t pad;          // many-RHS plan: first row of the task's 64-row group
     int64_t stream;       // byte offset of the owner's tile 0 in the data arena
 };
 

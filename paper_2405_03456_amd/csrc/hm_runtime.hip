@@ -155,6 +155,16 @@ __device__ __forceinline__ void stream_grouped(const DTask& tk, const DItem* __r
     constexpr int V = Tile<DT>::V;
     constexpr int U = 4;
     const int k0 = tk.k0, k1 = tk.k1;
+    const int step = U * G;
+    uint4 qa[U], qb[U];
+    auto issue = [&](uint4* q, int kb) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            q[u] = *reinterpret_cast<const uint4*>(sb + (int64_t)min(kb + u * G + g, k1 - 1) * rt);
+    };
+    // the first tiles are requested before the inputs are staged, so both
+    // memory latencies overlap
+    issue(qa, k0);
     // stage: lw[(t - k0) * V + i] = input of column i of tile t (zero past an
     // item's last column is not needed: its data is zero)
     {
@@ -172,13 +182,6 @@ __device__ __forceinline__ void stream_grouped(const DTask& tk, const DItem* __r
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    const int step = U * G;
-    uint4 qa[U], qb[U];
-    auto issue = [&](uint4* q, int kb) {
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            q[u] = *reinterpret_cast<const uint4*>(sb + (int64_t)min(kb + u * G + g, k1 - 1) * rt);
-    };
     auto consume = [&](const uint4* q, int kb) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -186,7 +189,6 @@ __device__ __forceinline__ void stream_grouped(const DTask& tk, const DItem* __r
             if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw + (kk - k0) * V, a64, a32);
         }
     };
-    issue(qa, k0);
     for (int k = k0; k < k1; k += 2 * step) {
         issue(qb, k + step);
         __builtin_amdgcn_sched_barrier(0);
@@ -221,8 +223,9 @@ __global__ __launch_bounds__(256) void k_owner_tasks(
     __shared__ double lds_w[4][MAX_TASK_INPUTS];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * 4 + wave;
-    if (t >= ntasks) return;
+    // a grid smaller than the task count makes each wave walk tasks
+    // t, t + stride, ... (used to leave compute units to a concurrent stage)
+    for (int t = blockIdx.x * 4 + wave; t < ntasks; t += gridDim.x * 4) {
     const DTask tk = tasks[t];
     const int nrows = tk.nrows;
     int lp = 0;                         // log2 P
@@ -231,7 +234,7 @@ __global__ __launch_bounds__(256) void k_owner_tasks(
     const int G = 64 >> lp;
     const int g = lane >> lp;
     const int rl = lane & (P - 1);
-    const int dt = tk.k0 < tk.k1 ? (int)items[tk.item_start].dtype : -1;
+    const int dt = tk.dtype;   // in the descriptor: no dependent item load before the tiles
     for (int r0 = 0; r0 < nrows; r0 += P) {
         const int r = r0 + rl;
         const bool act = r < nrows;
@@ -261,6 +264,7 @@ __global__ __launch_bounds__(256) void k_owner_tasks(
             else
                 part[tk.part_off + (int64_t)tk.local * nrows + r] = v;
         }
+    }
     }
 }
 
@@ -331,6 +335,7 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     hm::Packed P;
     hm::PackOptions opt;
     if (const char* e = std::getenv("HM_TASK_BYTES")) opt.task_bytes = std::max(1024L, std::atol(e));
+    if (const char* e = std::getenv("HM_CONCURRENT_DENSE")) opt.concurrent_dense = std::atoi(e) != 0;
     hm_status st;
     try {
         st = hm::pack(layout->L, format, values, prec, opt, P);
@@ -446,6 +451,7 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         }
     }
     m->stats = P.stats;
+    if (const char* e = std::getenv("HM_DENSE_GRID")) m->aux_grid = std::max(0, std::atoi(e));
     m->h_owners = P.owners;
     m->h_items = P.items;
     m->h_tasks = P.tasks;
@@ -526,7 +532,9 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
             joined = true;
         }
         if (ph.ntasks > 0) {
-            dim3 grid((unsigned)((ph.ntasks + 3) / 4));
+            unsigned blocks = (unsigned)((ph.ntasks + 3) / 4);
+            if (ph.aux && m->aux_grid > 0) blocks = std::min<unsigned>(blocks, (unsigned)m->aux_grid);
+            dim3 grid(blocks);
             std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
             if (timing && !hm::timing_begin(m, ph, 1, stream, ev)) {
                 hm::set_error("hm_mvm: timing events failed");
