@@ -356,33 +356,33 @@ __global__ __launch_bounds__(256) void k_tasks_multi(const Jobs J) {
                                 jb.ym, jb.partm, jb.R, jb.n, threadIdx.x & 63);
 }
 
-// Sum the partial results of split owners in task order, one wave per owner.
-__device__ __forceinline__ void reduce_owner(const DOwner& ow, const double* __restrict__ partm, double* wsm,
-                                             float* wsm32, double* __restrict__ ym, int R, bool mat64, int lane) {
+// Sum the partial results of split owners in task order.  Entries are
+// independent: block (o, c) of the grid sums entries [256c, 256c + 256) of
+// owner o of the list, one thread per entry.
+__device__ __forceinline__ void reduce_entry(const DOwner& ow, int64_t idx, const double* __restrict__ partm,
+                                             double* wsm, float* wsm32, double* __restrict__ ym, int R,
+                                             bool mat64) {
     const int64_t span = (int64_t)ow.nrows * R;
-    for (int64_t idx = lane; idx < span; idx += 64) {
-        const double* p = partm + (int64_t)ow.part_off * R + idx;
-        double v = 0.0;
-        for (int l = 0; l < ow.ntasks; ++l) v += p[(int64_t)l * span];
-        const int64_t e = (int64_t)ow.out_off * R + idx;
-        if (ow.mode == 0) {
-            if (mat64)
-                wsm[e] = v;
-            else
-                wsm32[e] = (float)v;
-        } else {
-            ym[e] += v;
-        }
+    if (idx >= span) return;
+    const double* p = partm + (int64_t)ow.part_off * R + idx;
+    double v = 0.0;
+    for (int l = 0; l < ow.ntasks; ++l) v += p[(int64_t)l * span];
+    const int64_t e = (int64_t)ow.out_off * R + idx;
+    if (ow.mode == 0) {
+        if (mat64)
+            wsm[e] = v;
+        else
+            wsm32[e] = (float)v;
+    } else {
+        ym[e] += v;
     }
 }
 
-__global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list, int nlist,
-                                                const DOwner* __restrict__ owners, const double* __restrict__ partm,
-                                                double* wsm, float* wsm32, double* __restrict__ ym, int R,
-                                                int mat64) {
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= nlist) return;
-    reduce_owner(owners[list[i]], partm, wsm, wsm32, ym, R, mat64 != 0, threadIdx.x & 63);
+__global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list, const DOwner* __restrict__ owners,
+                                                const double* __restrict__ partm, double* wsm, float* wsm32,
+                                                double* __restrict__ ym, int R, int mat64) {
+    reduce_entry(owners[list[blockIdx.x]], (int64_t)blockIdx.y * 256 + threadIdx.x, partm, wsm, wsm32, ym, R,
+                 mat64 != 0);
 }
 
 struct RJob {
@@ -392,48 +392,50 @@ struct RJob {
     double* wsm;
     float* wsm32;
     double* ym;
-    int64_t wave0;
+    int64_t owner0;     // first global owner index of this job
     int32_t R, mat64;
 };
 struct RJobs {
     int32_t njobs;
-    int64_t total;
+    int64_t total;      // owners over all jobs
     RJob j[kMaxJobs];
 };
 
 __global__ __launch_bounds__(256) void k_reduce_multi(const RJobs J) {
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= J.total) return;
+    const int64_t i = blockIdx.x;
     int ji = 0;
-    while (ji + 1 < J.njobs && i >= J.j[ji + 1].wave0) ++ji;
+    while (ji + 1 < J.njobs && i >= J.j[ji + 1].owner0) ++ji;
     const RJob& jb = J.j[ji];
-    reduce_owner(jb.owners[jb.list[i - jb.wave0]], jb.partm, jb.wsm, jb.wsm32, jb.ym, jb.R, jb.mat64 != 0,
-                 threadIdx.x & 63);
+    reduce_entry(jb.owners[jb.list[i - jb.owner0]], (int64_t)blockIdx.y * 256 + threadIdx.x, jb.partm, jb.wsm,
+                 jb.wsm32, jb.ym, jb.R, jb.mat64 != 0);
 }
 
-// X (column-major, ldx) -> wsm / wsm32 in cluster order, entry-major; the
-// padding columns j >= nrhs get zeros, and ym is cleared.  64 x 64 tiles
-// transposed through LDS.
+// X (column-major, ldx, original order) -> wsm / wsm32 in cluster order,
+// entry-major; padding columns j >= nrhs get zeros and ym is cleared.  A
+// block moves a 64 (points) x 64 (columns) tile through LDS: it reads X with
+// consecutive lanes on consecutive points and writes each point's row of
+// values at its cluster position iperm[o] with consecutive lanes on
+// consecutive columns (iperm = null: cluster order already).
 template <typename XT>
 __global__ __launch_bounds__(256) void k_gather(const XT* __restrict__ X, int64_t ldx, int nrhs,
-                                                const int64_t* __restrict__ perm, int64_t n, int R,
+                                                const int64_t* __restrict__ iperm, int64_t n, int R,
                                                 double* __restrict__ wsm, float* __restrict__ wsm32,
                                                 double* __restrict__ ym) {
     __shared__ double tile[64][65];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int64_t o0 = (int64_t)blockIdx.x * 64;
     const int j0 = blockIdx.y * 64;
-    const int64_t i = i0 + tx;
-    const int64_t src = i < n ? (perm ? perm[i] : i) : 0;
+    const int64_t o = o0 + tx;
     for (int jj = ty; jj < 64; jj += 4) {
         const int j = j0 + jj;
-        tile[jj][tx] = (i < n && j < nrhs) ? (double)X[src + (int64_t)j * ldx] : 0.0;
+        tile[jj][tx] = (o < n && j < nrhs) ? (double)X[o + (int64_t)j * ldx] : 0.0;
     }
     __syncthreads();
     for (int ii = ty; ii < 64; ii += 4) {
-        const int64_t r = i0 + ii;
+        const int64_t oo = o0 + ii;
         const int j = j0 + tx;
-        if (r < n && j < R) {
+        if (oo < n && j < R) {
+            const int64_t r = iperm ? iperm[oo] : oo;
             const double v = tile[tx][ii];
             wsm[r * R + j] = v;
             wsm32[r * R + j] = (float)v;
@@ -442,28 +444,29 @@ __global__ __launch_bounds__(256) void k_gather(const XT* __restrict__ X, int64_
     }
 }
 
-// Y[perm[i], j] += alpha * ym[i * R + j]  (column-major Y, ldy), via LDS.
+// Y[o, j] += alpha * ym[iperm[o] * R + j]  (column-major Y, ldy), via LDS.
 template <typename YT>
 __global__ __launch_bounds__(256) void k_scatter(YT* __restrict__ Y, int64_t ldy, int nrhs,
-                                                 const int64_t* __restrict__ perm, int64_t n, int R,
+                                                 const int64_t* __restrict__ iperm, int64_t n, int R,
                                                  const double* __restrict__ ym, double alpha) {
     __shared__ double tile[64][65];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
+    const int64_t o0 = (int64_t)blockIdx.x * 64;
     const int j0 = blockIdx.y * 64;
     for (int ii = ty; ii < 64; ii += 4) {
-        const int64_t r = i0 + ii;
+        const int64_t oo = o0 + ii;
         const int j = j0 + tx;
-        tile[ii][tx] = (r < n && j < R) ? ym[r * R + j] : 0.0;
+        double v = 0.0;
+        if (oo < n && j < R) v = ym[(iperm ? iperm[oo] : oo) * R + j];
+        tile[ii][tx] = v;
     }
     __syncthreads();
-    const int64_t i = i0 + tx;
-    if (i < n) {
-        const int64_t dst = perm ? perm[i] : i;
+    const int64_t o = o0 + tx;
+    if (o < n) {
         for (int jj = ty; jj < 64; jj += 4) {
             const int j = j0 + jj;
             if (j < nrhs) {
-                YT* p = Y + dst + (int64_t)j * ldy;
+                YT* p = Y + o + (int64_t)j * ldy;
                 *p = (YT)((double)*p + alpha * tile[tx][jj]);
             }
         }
@@ -528,7 +531,15 @@ static hm_status ensure_mr_plan(hm_matrix* m, int64_t target) {
         o_red.push_back(off);
         off = align256(off + st.reduce.size() * sizeof(int32_t));
     }
+    // cluster position of every original index, for the block gather/scatter
+    const size_t o_iperm = off;
+    off = align256(off + (size_t)m->n * sizeof(int64_t));
     std::vector<uint8_t> host(std::max<size_t>(off, 256), 0);
+    {
+        int64_t* ip = (int64_t*)(host.data() + o_iperm);
+        const std::vector<int64_t>& perm = m->layout->L.perm;
+        for (int64_t i = 0; i < m->n; ++i) ip[perm[(size_t)i]] = i;
+    }
     std::memcpy(host.data() + o_tasks, P.tasks.data(), P.tasks.size() * sizeof(DTask));
     std::memcpy(host.data() + o_owners, P.owners.data(), P.owners.size() * sizeof(DOwner));
     for (size_t i = 0; i < P.stages.size(); ++i)
@@ -563,6 +574,8 @@ static hm_status ensure_mr_plan(hm_matrix* m, int64_t target) {
         ds.ntasks = (int32_t)(st.t1 - st.t0);
         ds.reduce = (const int32_t*)(b + o_red[i]);
         ds.nreduce = (int32_t)st.reduce.size();
+        ds.reduce_rows = 0;
+        for (int32_t o : st.reduce) ds.reduce_rows = std::max(ds.reduce_rows, P.owners[o].nrows);
         ds.nowners = 0;
         ds.dtype_mask = 0;
         for (int64_t k = st.t0; k < st.t1; ++k) {
@@ -577,6 +590,7 @@ static hm_status ensure_mr_plan(hm_matrix* m, int64_t target) {
     }
     m->mr_meta = d;
     m->mr_tasks = (const DTask*)(b + o_tasks);
+    m->mr_iperm = (const int64_t*)(b + o_iperm);
     m->mr_owners = (const DOwner*)(b + o_owners);
     if (P.part_elems > m->mr_part_elems && m->mr_arena) {
         // the partial-sum workspace no longer fits: regrow it on next use
@@ -640,7 +654,7 @@ static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx
     const int nrb = (R >= 32 && m->mr_nrb == 2) ? 2 : 1;   // blocks of 16 right-hand sides per wave
     const int nblk = R / (16 * nrb);
     const int64_t n = m->n;
-    const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : m->perm;
+    const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : m->mr_iperm;
     const bool timing = (flags & HM_TIMING) != 0;
     dim3 tgrid((unsigned)((n + 63) / 64), (unsigned)((R + 63) / 64));
     if (vdt == HM_F64)
@@ -676,8 +690,10 @@ static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx
             if (timing) timing_end(ph, s, ev);
         }
         if (ph.nreduce > 0)
-            hipLaunchKernelGGL(mr::k_reduce, dim3((unsigned)((ph.nreduce + 3) / 4)), dim3(256), 0, s, ph.reduce,
-                               ph.nreduce, m->mr_owners, m->partm, m->wsm, m->wsm32, m->ym, R, m->acc64 ? 1 : 0);
+            hipLaunchKernelGGL(mr::k_reduce,
+                               dim3((unsigned)ph.nreduce, (unsigned)(((int64_t)ph.reduce_rows * R + 255) / 256)),
+                               dim3(256), 0, s, ph.reduce, m->mr_owners, m->partm, m->wsm, m->wsm32, m->ym, R,
+                               m->acc64 ? 1 : 0);
     }
     if (!joined) {
         (void)hipEventRecord(m->ev_join, m->aux);
@@ -728,7 +744,7 @@ static hm_status mvm_many_multi(std::vector<Entry>& E, int32_t vdt, uint32_t fla
         maxL = std::max(maxL, next - 1);
     }
     for (auto& e : E) {
-        const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : e.m->perm;
+        const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : e.m->mr_iperm;
         dim3 tgrid((unsigned)((e.m->n + 63) / 64), (unsigned)((e.R + 63) / 64));
         if (vdt == HM_F64)
             hipLaunchKernelGGL(mr::k_gather<double>, tgrid, dim3(256), 0, s, (const double*)e.X, e.ldx, e.nrhs, perm,
@@ -739,10 +755,13 @@ static hm_status mvm_many_multi(std::vector<Entry>& E, int32_t vdt, uint32_t fla
     }
     auto launch_reduces = [&](int L) {
         mr::RJobs J{};
+        int64_t span = 0;   // largest nrows * R of the job's owners
         auto flush = [&]() {
             if (J.njobs > 0 && J.total > 0)
-                hipLaunchKernelGGL(mr::k_reduce_multi, dim3((unsigned)((J.total + 3) / 4)), dim3(256), 0, s, J);
+                hipLaunchKernelGGL(mr::k_reduce_multi, dim3((unsigned)J.total, (unsigned)((span + 255) / 256)),
+                                   dim3(256), 0, s, J);
             J = mr::RJobs{};
+            span = 0;
         };
         for (auto& e : E)
             for (size_t i = 0; i < e.m->mr_phases.size(); ++i) {
@@ -752,6 +771,7 @@ static hm_status mvm_many_multi(std::vector<Entry>& E, int32_t vdt, uint32_t fla
                 J.j[J.njobs++] = mr::RJob{ph.reduce, e.m->mr_owners, e.m->partm, e.m->wsm, e.m->wsm32, e.m->ym,
                                           J.total, e.R, e.m->acc64 ? 1 : 0};
                 J.total += ph.nreduce;
+                span = std::max(span, (int64_t)ph.reduce_rows * e.R);
             }
         flush();
     };
@@ -785,7 +805,7 @@ static hm_status mvm_many_multi(std::vector<Entry>& E, int32_t vdt, uint32_t fla
     }
     launch_reduces(-1);
     for (auto& e : E) {
-        const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : e.m->perm;
+        const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : e.m->mr_iperm;
         dim3 tgrid((unsigned)((e.m->n + 63) / 64), (unsigned)((e.R + 63) / 64));
         if (vdt == HM_F64)
             hipLaunchKernelGGL(mr::k_scatter<double>, tgrid, dim3(256), 0, s, (double*)e.Y, e.ldy, e.nrhs, perm,

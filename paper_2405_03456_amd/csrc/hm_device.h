@@ -92,6 +92,7 @@ struct DevStage {
     bool aux;
     int64_t t0;
     int32_t ntasks, nreduce, nowners;
+    int32_t reduce_rows = 0;   // largest owner of the reduce list (many-RHS launch shape)
     const int32_t* reduce;
     int32_t dtype_mask;
     int64_t data_bytes;
@@ -139,6 +140,7 @@ struct hm_matrix {
     void* mr_meta = nullptr;
     const hm::DTask* mr_tasks = nullptr;
     const hm::DOwner* mr_owners = nullptr;
+    const int64_t* mr_iperm = nullptr;   // cluster position of each original index
     std::vector<hm::DevStage> mr_phases;
     int64_t mr_part_elems = 0;
     int64_t mr_target = 0;
