@@ -235,16 +235,18 @@ hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double alpha, const
 /* Autotuner of the many-right-hand-side path.  The engine's two free
  * parameters are the column-chunk size of a task (bytes of stored data per
  * 64-row group: 64 KiB ... 1 MiB) and the number of 16-wide right-hand-side
- * blocks one wave carries (1 or 2).  hm_tune_batch times every candidate
- * with `reps` products of an nrhs-wide zero block (allocated and freed
- * here), keeps the fastest for this matrix and reports it.  It allocates,
+ * blocks one wave carries (1 or 2, per stage).  For every chunk size
+ * hm_tune_batch times each stage with both block counts (`reps` event-timed
+ * products of an nrhs-wide zero block, allocated and freed here), keeps the
+ * faster per stage, times that combination, and keeps the fastest chunk
+ * size for this matrix.  It allocates,
  * synchronises and rebuilds the plan: call it outside graph capture, before
  * creating graphs of the matrix.  Results of later products may differ from
  * earlier ones in rounding (a different summation order), within the
  * accumulation tolerance. */
 typedef struct {
     int64_t target_bytes;   /* chosen column-chunk size */
-    int32_t nrb;            /* chosen 16-wide blocks per wave */
+    int32_t nrb;            /* blocks per wave chosen for the stage with the most data */
     double ms;              /* its mean time per product */
     int32_t ncandidates;    /* candidates timed */
 } hm_tune_result;

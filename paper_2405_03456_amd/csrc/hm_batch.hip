@@ -646,13 +646,18 @@ static hm_status ensure_mr(hm_matrix* m, int R) {
 // Width of the padded right-hand-side block: 16 or a multiple of 32.
 static int padded_width(int nrhs) { return nrhs <= 16 ? 16 : (nrhs + 31) / 32 * 32; }
 
+// 16-wide right-hand-side blocks per wave of one stage: the stage's tuned
+// choice, else the matrix's; 2 needs R >= 32.
+static int stage_nrb(const hm_matrix* m, const DevStage& ph, int R) {
+    const int want = ph.mr_nrb ? ph.mr_nrb : m->mr_nrb;
+    return (R >= 32 && want == 2) ? 2 : 1;
+}
+
 static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx, int nrhs, void* Y, int64_t ldy,
                           int32_t vdt, uint32_t flags, hipStream_t stream) {
     const int R = padded_width(nrhs);
     hm_status st = ensure_mr(m, R);
     if (st != HM_OK) return st;
-    const int nrb = (R >= 32 && m->mr_nrb == 2) ? 2 : 1;   // blocks of 16 right-hand sides per wave
-    const int nblk = R / (16 * nrb);
     const int64_t n = m->n;
     const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : m->mr_iperm;
     const bool timing = (flags & HM_TIMING) != 0;
@@ -677,6 +682,8 @@ static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx
             joined = true;
         }
         if (ph.ntasks > 0) {
+            const int nrb = stage_nrb(m, ph, R);   // blocks of 16 right-hand sides per wave
+            const int nblk = R / (16 * nrb);
             const int64_t waves = (int64_t)ph.ntasks * nblk;
             std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
             if (timing && !timing_begin(m, ph, R, s, ev)) {
@@ -722,7 +729,7 @@ struct Entry {
     int nrhs;
     void* Y;
     int64_t ldy;
-    int R, nrb, nblk;
+    int R;
     std::vector<int> level;   // per many-RHS stage; -1 = the final reduce
 };
 
@@ -732,8 +739,6 @@ static hm_status mvm_many_multi(std::vector<Entry>& E, int32_t vdt, uint32_t fla
         e.R = padded_width(e.nrhs);
         hm_status st = ensure_mr(e.m, e.R);
         if (st != HM_OK) return st;
-        e.nrb = (e.R >= 32 && e.m->mr_nrb == 2) ? 2 : 1;
-        e.nblk = e.R / (16 * e.nrb);
         e.level.clear();
         int next = 0;
         const auto& ph = e.m->mr_phases;
@@ -788,14 +793,15 @@ static hm_status mvm_many_multi(std::vector<Entry>& E, int32_t vdt, uint32_t fla
                     mask = 0;
                 };
                 for (auto& e : E) {
-                    if ((e.m->acc64 ? 1 : 0) != acc || e.nrb != nrb) continue;
+                    if ((e.m->acc64 ? 1 : 0) != acc) continue;
                     for (size_t i = 0; i < e.m->mr_phases.size(); ++i) {
                         const DevStage& ph = e.m->mr_phases[i];
-                        if (e.level[i] != L || ph.ntasks == 0) continue;
+                        if (e.level[i] != L || ph.ntasks == 0 || stage_nrb(e.m, ph, e.R) != nrb) continue;
+                        const int nblk = e.R / (16 * nrb);
                         if (J.njobs == mr::kMaxJobs) flush();
                         J.j[J.njobs++] = mr::Job{e.m->mr_tasks + ph.t0, e.m->items, e.m->data, e.m->scales, e.m->wsm,
-                                                 e.m->wsm32, e.m->ym, e.m->partm, J.total, e.m->n, e.nblk, e.R};
-                        J.total += (int64_t)ph.ntasks * e.nblk;
+                                                 e.m->wsm32, e.m->ym, e.m->partm, J.total, e.m->n, nblk, e.R};
+                        J.total += (int64_t)ph.ntasks * nblk;
                         mask |= ph.dtype_mask;
                     }
                 }
@@ -838,25 +844,38 @@ hm_status mvm_blocks(const BlockCall* calls, int ncalls, hipStream_t stream) {
     return mvm_many_multi(E, HM_F64, 0, stream);
 }
 
-// Time one candidate (chunk size, blocks per wave) of the many-RHS plan.
-static hm_status time_candidate(hm_matrix* m, int64_t target, int nrb, int nrhs, int32_t vdt, const void* X,
-                                void* Y, int reps, hipStream_t s, double* ms) {
-    m->mr_nrb = nrb;
-    hm_status st = ensure_mr_plan(m, target);
-    if (st == HM_OK) st = mvm_many(m, 1.0, X, m->n, nrhs, Y, m->n, vdt, 0, s);   // warm-up
+// Run `reps` products on the current plan; *ms = mean time per product.  With
+// `phase_ms`, the products are event-timed per stage and the per-stage mean
+// times are returned as well.
+static hm_status time_plan(hm_matrix* m, int nrhs, int32_t vdt, const void* X, void* Y, int reps, hipStream_t s,
+                           double* ms, std::vector<double>* phase_ms) {
+    hm_status st = mvm_many(m, 1.0, X, m->n, nrhs, Y, m->n, vdt, 0, s);   // warm-up
     if (st != HM_OK) return st;
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     if (e == hipSuccess) e = hipEventRecord(a, s);
+    const uint32_t flags = phase_ms ? HM_TIMING : 0;
     for (int r = 0; r < reps && e == hipSuccess && st == HM_OK; ++r)
-        st = mvm_many(m, 1.0, X, m->n, nrhs, Y, m->n, vdt, 0, s);
+        st = mvm_many(m, 1.0, X, m->n, nrhs, Y, m->n, vdt, flags, s);
     if (e == hipSuccess) e = hipEventRecord(b, s);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     float t = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
+    if (phase_ms) {
+        phase_ms->assign(m->mr_phases.size(), 0.0);
+        for (size_t i = 0; i < m->mr_phases.size(); ++i) {
+            for (auto& ev : m->mr_phases[i].pending) {
+                float pt = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&pt, ev.first, ev.second);
+                (*phase_ms)[i] += (double)pt / reps;
+                m->event_pool.push_back(ev);
+            }
+            m->mr_phases[i].pending.clear();
+        }
+    }
     if (st != HM_OK) return st;
     if (e != hipSuccess) return hip_fail("hm_tune_batch: timing", e);
     *ms = (double)t / reps;
@@ -983,29 +1002,59 @@ extern "C" hm_status hm_tune_batch(hm_matrix* m, int32_t nrhs, int32_t vec_dtype
         (void)hipFree(Y);
         return hm::hip_fail("hm_tune_batch: hipMemset", e);
     }
+    // For every chunk size: time each stage with 1 and 2 blocks per wave,
+    // keep the faster per stage, then time that combination as a whole.
     static const int64_t targets[] = {64 * 1024, 128 * 1024, 256 * 1024, 512 * 1024, 1024 * 1024};
     const int R = hm::padded_width(nrhs);
+    const int maxnrb = R >= 32 ? 2 : 1;
     hm_tune_result best{0, 1, 0.0, 0};
+    std::vector<int32_t> best_nrb;
     hm_status st = HM_OK;
-    for (int nrb = 1; nrb <= (R >= 32 ? 2 : 1) && st == HM_OK; ++nrb)
-        for (int64_t t : targets) {
-            double ms = 0.0;
-            st = hm::time_candidate(m, t, nrb, nrhs, vec_dtype, X, Y, reps, (hipStream_t)stream, &ms);
+    for (int64_t t : targets) {
+        m->mr_nrb = 1;
+        st = hm::ensure_mr_plan(m, t);
+        if (st != HM_OK) break;
+        const size_t np = m->mr_phases.size();
+        std::vector<double> tbest(np, 0.0);
+        std::vector<int32_t> choice(np, 1);
+        double ms = 0.0;
+        for (int nrb = 1; nrb <= maxnrb && st == HM_OK; ++nrb) {
+            for (auto& ph : m->mr_phases) ph.mr_nrb = nrb;
+            std::vector<double> pm;
+            st = hm::time_plan(m, nrhs, vec_dtype, X, Y, reps, (hipStream_t)stream, &ms, &pm);
+            ++best.ncandidates;
+            for (size_t i = 0; i < np && st == HM_OK; ++i)
+                if (nrb == 1 || pm[i] < tbest[i]) {
+                    tbest[i] = pm[i];
+                    choice[i] = nrb;
+                }
+        }
+        if (st != HM_OK) break;
+        for (size_t i = 0; i < np; ++i) m->mr_phases[i].mr_nrb = choice[i];
+        if (maxnrb > 1) {
+            st = hm::time_plan(m, nrhs, vec_dtype, X, Y, reps, (hipStream_t)stream, &ms, nullptr);
             if (st != HM_OK) break;
             ++best.ncandidates;
-            if (best.target_bytes == 0 || ms < best.ms) {
-                best.target_bytes = t;
-                best.nrb = nrb;
-                best.ms = ms;
-            }
         }
+        if (best.target_bytes == 0 || ms < best.ms) {
+            best.target_bytes = t;
+            best.ms = ms;
+            best_nrb = choice;
+            // report the choice of the stage that streams the most data
+            size_t big = 0;
+            for (size_t i = 1; i < np; ++i)
+                if (m->mr_phases[i].data_bytes > m->mr_phases[big].data_bytes) big = i;
+            best.nrb = np ? choice[big] : 1;
+        }
+    }
     (void)hipDeviceSynchronize();
     (void)hipFree(X);
     (void)hipFree(Y);
     if (st != HM_OK) return st;
-    m->mr_nrb = best.nrb;
+    m->mr_nrb = 1;
     st = hm::ensure_mr_plan(m, best.target_bytes);
     if (st != HM_OK) return st;
+    for (size_t i = 0; i < m->mr_phases.size() && i < best_nrb.size(); ++i) m->mr_phases[i].mr_nrb = best_nrb[i];
     if (out) *out = best;
     return HM_OK;
 }

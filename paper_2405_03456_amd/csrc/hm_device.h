@@ -93,6 +93,7 @@ struct DevStage {
     int64_t t0;
     int32_t ntasks, nreduce, nowners;
     int32_t reduce_rows = 0;   // largest owner of the reduce list (many-RHS launch shape)
+    int32_t mr_nrb = 0;        // many-RHS blocks per wave chosen for this stage (0 = the matrix's)
     const int32_t* reduce;
     int32_t dtype_mask;
     int64_t data_bytes;
