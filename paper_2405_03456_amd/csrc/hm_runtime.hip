@@ -278,11 +278,29 @@ __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= nlist) return;
     const DOwner ow = owners[list[i]];
-    for (int r = lane; r < ow.nrows; r += 64) {
-        const double* p = part + ow.part_off + r;
-        double v = 0.0;
-        for (int l = 0; l < ow.ntasks; ++l) v += p[(int64_t)l * ow.nrows];
-        finalize(ow.mode, ow.out_off, r, v, vout, vout32, y, perm, alpha);
+    // P lanes per row group (next power of two >= nrows, at most 64); the
+    // G = 64 / P groups take tasks g, g + G, ... with two independent sums
+    // each, combined across groups by shuffles (a fixed order: deterministic)
+    const int nrows = ow.nrows, nt = ow.ntasks;
+    int lp = 0;
+    while ((1 << lp) < nrows && lp < 6) ++lp;
+    const int P = 1 << lp, G = 64 >> lp, g = lane >> lp, rl = lane & (P - 1);
+    for (int r0 = 0; r0 < nrows; r0 += P) {
+        const int r = r0 + rl;
+        const bool act = r < nrows;
+        double v0 = 0.0, v1 = 0.0;
+        if (act) {
+            const double* p = part + ow.part_off + r;
+            int l = g;
+            for (; l + G < nt; l += 2 * G) {
+                v0 += p[(int64_t)l * nrows];
+                v1 += p[(int64_t)(l + G) * nrows];
+            }
+            if (l < nt) v0 += p[(int64_t)l * nrows];
+        }
+        double v = v0 + v1;
+        for (int off = P; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+        if (act && g == 0) finalize(ow.mode, ow.out_off, r, v, vout, vout32, y, perm, alpha);
     }
 }
 
