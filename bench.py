@@ -209,6 +209,7 @@ MANY_POLICIES = {
     "f64": dict(dense="f64", factor="f64", coupling="f64"),
     "f32": dict(dense="f32", factor="f32", coupling="f32"),
     "bf16": dict(dense="bf16", factor="bf16", coupling="bf16"),
+    "valr": dict(dense="valr", diag="valr", factor="valr", coupling="valr"),
 }
 
 

@@ -90,6 +90,38 @@ int32_t valr_choose(const double* col, int64_t m, double delta) {
     return HM_F64;
 }
 
+// VALR formats of the k columns of one factor: each column's cheapest format
+// (valr_choose), then a format used by fewer columns than one 16-byte tile
+// holds is promoted to the least precise more precise format the factor
+// already uses, provided that costs that format at most the one tile the
+// short run frees.  A column is only ever stored more precisely than its
+// budget needs; short runs of cheap columns would otherwise cost a nearly
+// empty padded tile and a separate item each.
+std::vector<int32_t> valr_formats(const double* A, int64_t m, int64_t k, const std::vector<double>& deltas) {
+    std::vector<int32_t> dts((size_t)k);
+    for (int64_t j = 0; j < k; ++j) dts[(size_t)j] = valr_choose(A + j * m, m, deltas[(size_t)j]);
+    static const int32_t order[5] = {HM_FP8E4M3, HM_BF16, HM_F16, HM_F32, HM_F64};   // precision, ascending
+    int64_t cnt[5] = {0, 0, 0, 0, 0};
+    for (int32_t d : dts) cnt[d]++;
+    auto tiles = [](int64_t c, int32_t d) { return (c + 16 / dtype_bytes(d) - 1) / (16 / dtype_bytes(d)); };
+    for (int a = 0; a < 4; ++a) {
+        const int32_t d = order[a];
+        if (cnt[d] == 0 || cnt[d] >= 16 / dtype_bytes(d)) continue;
+        for (int b = a + 1; b < 5; ++b) {
+            const int32_t t = order[b];
+            if (cnt[t] == 0) continue;
+            if (tiles(cnt[t] + cnt[d], t) <= tiles(cnt[t], t) + 1) {
+                for (int32_t& x : dts)
+                    if (x == d) x = t;
+                cnt[t] += cnt[d];
+                cnt[d] = 0;
+            }
+            break;
+        }
+    }
+    return dts;
+}
+
 // Direct compression (Sec. 4.1): cheapest format with unit roundoff <= eps.
 int32_t direct_for_eps(double eps) {
     if (eps >= 0.0625) return HM_FP8E4M3;
@@ -146,13 +178,14 @@ struct Builder {
     };
     // deltas: per-column error budget delta_j of VALR (unused otherwise);
     // breaks (optional): brk[j] != 0 forces a run to start at column j
+    // dts_in (optional): the formats, already chosen, of the k columns
     std::vector<Run> add_factor(const double* A, int64_t m, int64_t k, const double* colfactor, int cls,
-                                const std::vector<double>& deltas, const std::vector<uint8_t>* brk = nullptr) {
+                                const std::vector<double>& deltas, const std::vector<uint8_t>* brk = nullptr,
+                                const std::vector<int32_t>* dts_in = nullptr) {
         std::vector<Run> runs;
         if (k == 0) return runs;
         std::vector<int32_t> dts(k, factor_dt);
-        if (factor_dt == HM_VALR_AUTO)
-            for (int64_t j = 0; j < k; ++j) dts[j] = valr_choose(A + j * m, m, deltas[(size_t)j]);
+        if (factor_dt == HM_VALR_AUTO) dts = dts_in ? *dts_in : valr_formats(A, m, k, deltas);
         int64_t j0 = 0;
         for (int64_t j = 1; j <= k; ++j)
             if (j == k || dts[j] != dts[j0] || (brk && (*brk)[(size_t)j])) {
@@ -493,8 +526,7 @@ struct Builder {
         perm.clear();
         if (factor_dt != HM_VALR_AUTO || k == 0) return basis_factor(A, m, k, sv, v);
         std::vector<double> d = deltas_for(sv[v], k, eps * norm2(sv[v], k) / (double)k);
-        std::vector<int32_t> dts((size_t)k);
-        for (int64_t j = 0; j < k; ++j) dts[(size_t)j] = valr_choose(A + j * m, m, d[(size_t)j]);
+        const std::vector<int32_t> dts = valr_formats(A, m, k, d);
         std::vector<int32_t> order((size_t)k);
         for (int64_t j = 0; j < k; ++j) order[(size_t)j] = (int32_t)j;
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return dts[a] < dts[b]; });
@@ -579,9 +611,16 @@ struct Builder {
             // order of the stacked columns: by X's format under VALR
             std::vector<int32_t> order((size_t)K), inv((size_t)K);
             for (int64_t o = 0; o < K; ++o) order[(size_t)o] = (int32_t)o;
+            std::vector<int32_t> dtx((size_t)K, factor_dt);   // X's formats, chosen per block
             if (factor_dt == HM_VALR_AUTO) {
-                std::vector<int32_t> dtx((size_t)K);
-                for (int64_t o = 0; o < K; ++o) dtx[(size_t)o] = valr_choose(Xs.data() + o * ms, ms, Ds[(size_t)o]);
+                int64_t o0 = 0;
+                for (int32_t b : col_lr[s]) {
+                    const int32_t k = V->rank[b];
+                    std::vector<double> d(Ds.begin() + o0, Ds.begin() + o0 + k);
+                    const std::vector<int32_t> f = valr_formats(Xs.data() + o0 * ms, ms, k, d);
+                    std::copy(f.begin(), f.end(), dtx.begin() + o0);
+                    o0 += k;
+                }
                 std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return dtx[a] < dtx[b]; });
             }
             for (int64_t p = 0; p < K; ++p) inv[(size_t)order[(size_t)p]] = (int32_t)p;
@@ -605,6 +644,7 @@ struct Builder {
             }
             const double* Xo = Xs.data();
             std::vector<double> Dp = Ds;
+            std::vector<int32_t> dtp = dtx;
             bool same = true;
             for (int64_t p = 0; p < K; ++p) same &= order[(size_t)p] == p;
             if (!same) {
@@ -614,10 +654,11 @@ struct Builder {
                     std::memcpy(Xp.data() + p * ms, Xs.data() + (int64_t)order[(size_t)p] * ms,
                                 sizeof(double) * (size_t)ms);
                     Dp[(size_t)p] = Ds[(size_t)order[(size_t)p]];
+                    dtp[(size_t)p] = dtx[(size_t)order[(size_t)p]];
                 }
                 Xo = Xp.data();
             }
-            std::vector<Run> xr = add_factor(Xo, ms, K, nullptr, 1, Dp);
+            std::vector<Run> xr = add_factor(Xo, ms, K, nullptr, 1, Dp, nullptr, &dtp);
             for (const Run& r : xr) {
                 // row scale: X's range scale times the U-side column scale
                 // (sigma_j and W's range scale) of the same column

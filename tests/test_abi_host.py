@@ -111,6 +111,13 @@ def test_valr_choices_match_oracle(eps):
         u = hm.plan_stats(lay, fmt, vals[fmt], eps=eps, dense="f32", diag="f32", factor="f32")
         assert u["entries_per_dtype"][1] == sum(u["entries_per_dtype"])
         assert sum(u["entries_per_dtype"]) == sum(s["entries_per_dtype"])
+        # stored bytes (tile padding included) never above FP32 with an FP64
+        # diagonal (equal when every factor fits one FP32 tile, k <= 4)
+        if eps >= 1e-6:
+            u64 = hm.plan_stats(lay, fmt, vals[fmt], eps=eps, dense="f32", diag="f64", factor="f32")
+            assert sum(s["bytes_per_dtype"]) <= sum(u64["bytes_per_dtype"]), fmt
+            if eps == 1e-6:
+                assert sum(s["bytes_per_dtype"]) < sum(u64["bytes_per_dtype"]), fmt
 
 
 def test_valr_errors():

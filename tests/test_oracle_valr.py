@@ -189,8 +189,9 @@ def test_eq7_bound_per_basis(fmt):
 @pytest.mark.parametrize("eps", [1e-4, 1e-6])
 def test_valr_product_error_and_savings(fmt, eps):
     """The product of the VALR-stored matrix stays within a small multiple
-    of eps of the float64 product of the same factors, while storing fewer
-    bytes than uniform FP32."""
+    of eps of the float64 product of the same factors, and every stored entry
+    is counted once (the stored bytes, tile padding included, are compared
+    with uniform FP32 on the library's plan in test_abi_host)."""
     st, h, uh, h2 = _h(eps)
     vals = {"h": h, "uh": uh, "h2": h2}[fmt]
     n = st.n
@@ -202,9 +203,39 @@ def test_valr_product_error_and_savings(fmt, eps):
     out = stored.product(st, fmt, sv, 1.0, x, y0)
     err = np.linalg.norm(out - ref) / np.linalg.norm(ref)
     assert err <= 3.0 * eps, err
-    total = counts[:5].sum()
-    nbytes = sum(int(counts[f]) * quant.BYTES[f] for f in range(5))
     diag = sum(h.dense[b].size for b in range(st.nblocks)
                if h.dense[b] is not None and st.blk_tau[b] == st.blk_sigma[b])
     assert counts[quant.F64] >= diag                     # diagonal near field stays FP64
-    assert nbytes < 4 * total + 4 * diag                 # cheaper than FP32 with FP64 diagonal
+    assert counts[:5].sum() == sum(a.size for a in vals.dense if a is not None) + sum(
+        a.size for grp in ((vals.W, vals.X) if fmt == "h" else
+                           (vals.row_basis, vals.col_basis, vals.coupling) if fmt == "uh" else
+                           (vals.row_leaf_basis, vals.col_leaf_basis, vals.row_transfer, vals.col_transfer,
+                            vals.coupling))
+        for a in grp if a is not None)
+
+
+def test_promotion_rule():
+    """Short runs of cheap formats join the next more precise format in the
+    factor when that costs no extra tile: 2 FP8 columns next to 5 FP16 ones
+    become FP16 (7 columns still fill one FP16 tile); FP16 columns next to a
+    full FP32 tile stay (they would add a second FP32 tile... and more)."""
+    rng = np.random.default_rng(11)
+    m = 40
+    A = rng.standard_normal((m, 7))
+    exact8 = quant.stored(A, quant.FP8)                   # columns exactly FP8-representable
+    base = np.column_stack([A[:, :5], exact8[:, 5:]])
+    loose16 = [np.sqrt(err2(base[:, j], via_float16(base[:, j]))) * 1.0000001 for j in range(5)]
+    deltas = loose16 + [0.0, 0.0]                         # FP16 for 0..4, FP8 (exact) for 5, 6
+    assert [stored.valr_column_format(base[:, j], deltas[j]) for j in range(7)] == [quant.F16] * 5 + [quant.FP8] * 2
+    assert stored.valr_factor_formats(base, deltas) == [quant.F16] * 7
+    # 16 FP8 columns fill a tile: no promotion
+    B = quant.stored(rng.standard_normal((m, 16)), quant.FP8)
+    C = np.column_stack([A[:, :1], B])
+    d = [0.0] + [0.0] * 16
+    f = stored.valr_factor_formats(C, d)
+    assert f.count(quant.FP8) == 16
+    # 3 FP32 columns next to 4 FP64 ones: FP64 would need 2 more tiles -> no promotion
+    g32 = A[:, :3].astype(np.float32).astype(np.float64)
+    D = np.column_stack([A[:, 3:7], g32])
+    f = stored.valr_factor_formats(D, [0.0] * 7)
+    assert f == [quant.F64] * 4 + [quant.F32] * 3
