@@ -540,6 +540,11 @@ static hm_status ensure_mr_plan(hm_matrix* m, int64_t target) {
         const std::vector<int64_t>& perm = m->layout->L.perm;
         for (int64_t i = 0; i < m->n; ++i) ip[perm[(size_t)i]] = i;
     }
+    // tasks of a stage ordered by dtype: the stage launches once per dtype
+    // with the kernel compiled for that dtype alone (register budget)
+    for (auto& st : P.stages)
+        std::stable_sort(P.tasks.begin() + st.t0, P.tasks.begin() + st.t1,
+                         [](const DTask& a, const DTask& b) { return a.dtype < b.dtype; });
     std::memcpy(host.data() + o_tasks, P.tasks.data(), P.tasks.size() * sizeof(DTask));
     std::memcpy(host.data() + o_owners, P.owners.data(), P.owners.size() * sizeof(DOwner));
     for (size_t i = 0; i < P.stages.size(); ++i)
@@ -580,7 +585,10 @@ static hm_status ensure_mr_plan(hm_matrix* m, int64_t target) {
         ds.dtype_mask = 0;
         for (int64_t k = st.t0; k < st.t1; ++k) {
             const DTask& t = P.tasks[k];
-            if (t.c0 < t.c1) ds.dtype_mask |= 1 << m->h_items[t.item_start].dtype;
+            if (t.c0 < t.c1) ds.dtype_mask |= 1 << t.dtype;
+            if (ds.subs.empty() || ds.subs.back().dtype != t.dtype)
+                ds.subs.push_back(DevStage::Sub{t.dtype, (int32_t)(k - st.t0), 0});
+            ds.subs.back().ntasks++;
         }
         ds.data_bytes = st.data_bytes;
         ds.data_entries = st.data_entries;
@@ -690,10 +698,15 @@ static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx
                 set_error("hm_mvm_batch: timing events failed");
                 return HM_EDEVICE;
             }
-            hipLaunchKernelGGL(mr::kTasks[m->acc64 ? 1 : 0][nrb - 1][mr::variant(ph.dtype_mask)],
-                               dim3((unsigned)((waves + 3) / 4)), dim3(256), 0,
-                               s, m->mr_tasks + ph.t0, ph.ntasks, nblk, m->items, m->data, m->scales, m->wsm,
-                               m->wsm32, m->ym, m->partm, R, n);
+            (void)waves;
+            for (const auto& sb : ph.subs) {
+                // dtype -1 (tasks without columns) runs with any variant
+                const int var = sb.dtype < 0 ? HM_F32 : sb.dtype;
+                const int64_t w = (int64_t)sb.ntasks * nblk;
+                hipLaunchKernelGGL(mr::kTasks[m->acc64 ? 1 : 0][nrb - 1][var], dim3((unsigned)((w + 3) / 4)),
+                                   dim3(256), 0, s, m->mr_tasks + ph.t0 + sb.t0, sb.ntasks, nblk, m->items, m->data,
+                                   m->scales, m->wsm, m->wsm32, m->ym, m->partm, R, n);
+            }
             if (timing) timing_end(ph, s, ev);
         }
         if (ph.nreduce > 0)
@@ -782,31 +795,34 @@ static hm_status mvm_many_multi(std::vector<Entry>& E, int32_t vdt, uint32_t fla
     };
     for (int L = 0; L <= maxL; ++L) {
         for (int acc = 0; acc < 2; ++acc)
-            for (int nrb = 1; nrb <= 2; ++nrb) {
-                mr::Jobs J{};
-                int mask = 0;
-                auto flush = [&]() {
-                    if (J.njobs > 0 && J.total > 0)
-                        hipLaunchKernelGGL(mr::kMulti[acc][nrb - 1][mr::variant(mask)],
-                                           dim3((unsigned)((J.total + 3) / 4)), dim3(256), 0, s, J);
-                    J = mr::Jobs{};
-                    mask = 0;
-                };
-                for (auto& e : E) {
-                    if ((e.m->acc64 ? 1 : 0) != acc) continue;
-                    for (size_t i = 0; i < e.m->mr_phases.size(); ++i) {
-                        const DevStage& ph = e.m->mr_phases[i];
-                        if (e.level[i] != L || ph.ntasks == 0 || stage_nrb(e.m, ph, e.R) != nrb) continue;
-                        const int nblk = e.R / (16 * nrb);
-                        if (J.njobs == mr::kMaxJobs) flush();
-                        J.j[J.njobs++] = mr::Job{e.m->mr_tasks + ph.t0, e.m->items, e.m->data, e.m->scales, e.m->wsm,
-                                                 e.m->wsm32, e.m->ym, e.m->partm, J.total, e.m->n, nblk, e.R};
-                        J.total += (int64_t)ph.ntasks * nblk;
-                        mask |= ph.dtype_mask;
+            for (int nrb = 1; nrb <= 2; ++nrb)
+                for (int dt = -1; dt < 5; ++dt) {
+                    mr::Jobs J{};
+                    const int var = dt < 0 ? HM_F32 : dt;
+                    auto flush = [&]() {
+                        if (J.njobs > 0 && J.total > 0)
+                            hipLaunchKernelGGL(mr::kMulti[acc][nrb - 1][var], dim3((unsigned)((J.total + 3) / 4)),
+                                               dim3(256), 0, s, J);
+                        J = mr::Jobs{};
+                    };
+                    for (auto& e : E) {
+                        if ((e.m->acc64 ? 1 : 0) != acc) continue;
+                        for (size_t i = 0; i < e.m->mr_phases.size(); ++i) {
+                            const DevStage& ph = e.m->mr_phases[i];
+                            if (e.level[i] != L || ph.ntasks == 0 || stage_nrb(e.m, ph, e.R) != nrb) continue;
+                            const int nblk = e.R / (16 * nrb);
+                            for (const auto& sb : ph.subs) {
+                                if (sb.dtype != dt) continue;
+                                if (J.njobs == mr::kMaxJobs) flush();
+                                J.j[J.njobs++] = mr::Job{e.m->mr_tasks + ph.t0 + sb.t0, e.m->items, e.m->data,
+                                                         e.m->scales, e.m->wsm, e.m->wsm32, e.m->ym, e.m->partm,
+                                                         J.total, e.m->n, nblk, e.R};
+                                J.total += (int64_t)sb.ntasks * nblk;
+                            }
+                        }
                     }
+                    flush();
                 }
-                flush();
-            }
         launch_reduces(L);
     }
     launch_reduces(-1);

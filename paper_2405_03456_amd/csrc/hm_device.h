@@ -94,6 +94,10 @@ struct DevStage {
     int32_t ntasks, nreduce, nowners;
     int32_t reduce_rows = 0;   // largest owner of the reduce list (many-RHS launch shape)
     int32_t mr_nrb = 0;        // many-RHS blocks per wave chosen for this stage (0 = the matrix's)
+    struct Sub {               // many-RHS: a run of tasks of one dtype (tasks sorted by dtype)
+        int32_t dtype, t0, ntasks;
+    };
+    std::vector<Sub> subs;
     const int32_t* reduce;
     int32_t dtype_mask;
     int64_t data_bytes;
