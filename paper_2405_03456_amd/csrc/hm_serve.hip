@@ -18,6 +18,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -83,6 +84,91 @@ private:
     int64_t size_ = 0, used_ = 0, peak_ = 0;
 };
 
+// Host copies of request blocks to and from the pinned staging arena, spread
+// over a few worker threads (one thread moves a few GB/s of pageable data).
+// run() cuts every job into pieces of at most kPiece values and returns when
+// all pieces are done; the calling thread works too.
+class CopyPool {
+public:
+    struct Job {
+        double* dst;
+        const double* src;
+        int64_t count;
+        double scale;   // dst = scale * src (1.0: a plain copy)
+    };
+    explicit CopyPool(int nthreads) {
+        for (int i = 0; i < nthreads; ++i) th_.emplace_back([this] { work(); });
+    }
+    ~CopyPool() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    void run(const std::vector<Job>& jobs) {
+        std::vector<Job> pieces;
+        for (const Job& j : jobs)
+            for (int64_t o = 0; o < j.count; o += kPiece)
+                pieces.push_back(Job{j.dst + o, j.src + o, std::min(kPiece, j.count - o), j.scale});
+        if (pieces.empty()) return;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            for (const Job& p : pieces) q_.push_back(p);
+            pending_ += (int64_t)pieces.size();
+        }
+        cv_.notify_all();
+        for (;;) {   // help until the queue is empty, then wait for the rest
+            Job j;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                if (q_.empty()) {
+                    done_cv_.wait(lk, [&] { return pending_ == 0; });
+                    return;
+                }
+                j = q_.front();
+                q_.pop_front();
+            }
+            exec(j);
+            finish();
+        }
+    }
+
+private:
+    static constexpr int64_t kPiece = 1 << 17;
+    static void exec(const Job& j) {
+        if (j.scale == 1.0)
+            std::memcpy(j.dst, j.src, sizeof(double) * (size_t)j.count);
+        else
+            for (int64_t i = 0; i < j.count; ++i) j.dst[i] = j.scale * j.src[i];
+    }
+    void finish() {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (--pending_ == 0) done_cv_.notify_all();
+    }
+    void work() {
+        for (;;) {
+            Job j;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
+                if (stop_ && q_.empty()) return;
+                j = q_.front();
+                q_.pop_front();
+            }
+            exec(j);
+            finish();
+        }
+    }
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    std::deque<Job> q_;
+    int64_t pending_ = 0;
+    bool stop_ = false;
+    std::vector<std::thread> th_;
+};
+
 struct Req {
     int32_t mid;
     double alpha;
@@ -108,6 +194,9 @@ struct Block {          // one matrix's concatenated columns in a group
     int64_t n = 0;
     int32_t cols = 0;
     std::vector<uint64_t> tickets;
+    std::vector<int32_t> cols_of;                   // columns of each ticket
+    std::vector<const double*> x_of;                // its X
+    std::vector<std::pair<double*, double>> y_of;   // its Y and alpha
     int64_t dev_off = -1, host_off = -1, bytes = 0;   // X block then Y block
 };
 
@@ -144,6 +233,7 @@ struct hm_server {
     int64_t next_group = 0;
     int32_t inflight_reqs = 0;
     hm_serve_stats stats{};
+    std::unique_ptr<hm::CopyPool> pool;   // host staging copies
 };
 
 namespace hm {
@@ -151,33 +241,40 @@ namespace {
 
 int64_t block_bytes(int64_t n, int32_t cols) { return 2 * (((n * cols * 8) + 255) & ~int64_t(255)); }
 
-// Copy results of a finished group to the callers and release its memory.
-// Called with the lock held.
+// Results of a finished group: the copies to the callers' Y (alpha applied),
+// made without the lock (the group's requests are not touched by other
+// threads until they are marked done).
+std::vector<CopyPool::Job> result_copies(hm_server* S, const Group& g,
+                                         const std::vector<std::pair<double*, double>>& dst) {
+    std::vector<CopyPool::Job> jobs;
+    if (g.status != HM_OK || S->opts.fake) return jobs;
+    size_t k = 0;
+    for (const Block& b : g.blocks) {
+        const double* Yst = (const double*)(S->host_base + b.host_off + b.bytes / 2);
+        int64_t c = 0;
+        for (size_t t = 0; t < b.tickets.size(); ++t, ++k) {
+            jobs.push_back(CopyPool::Job{dst[k].first, Yst + c * b.n, b.n * b.cols_of[t], dst[k].second});
+            c += b.cols_of[t];
+        }
+    }
+    return jobs;
+}
+
+// Mark a finished group's requests done and release its memory (lock held).
 void retire(hm_server* S, Group& g) {
     const double t = now_ms();
     for (Block& b : g.blocks) {
         Mat& M = S->mats[b.mid];
-        const int64_t n = b.n;
-        const int64_t half = b.bytes / 2;
-        const double* Yst = (const double*)(S->host_base + b.host_off + half);
-        int32_t c = 0;
         for (uint64_t tk : b.tickets) {
             Req& r = S->reqs[tk];
             if (g.status == HM_OK) {
-                const int64_t cnt = n * r.nrhs;
-                if (S->opts.fake) {
-                    std::memset(r.Y, 0, sizeof(double) * cnt);
-                } else {
-                    const double* src = Yst + (int64_t)c * n;
-                    for (int64_t i = 0; i < cnt; ++i) r.Y[i] = r.alpha * src[i];
-                }
+                if (S->opts.fake) std::memset(r.Y, 0, sizeof(double) * (size_t)(b.n * r.nrhs));
                 r.state = 2;
             } else {
                 r.state = 3;
                 r.status = g.status;
             }
             r.t_done = t;
-            c += r.nrhs;
             S->stats.completed++;
         }
         S->dev_arena.release(b.dev_off, b.bytes);
@@ -221,6 +318,9 @@ Group form_group(hm_server* S, int stream) {
         }
         b->cols += r.nrhs;
         b->tickets.push_back(*it);
+        b->cols_of.push_back(r.nrhs);
+        b->x_of.push_back(r.X);
+        b->y_of.emplace_back(r.Y, r.alpha);
         g.nreq++;
         it = S->queue.erase(it);
     }
@@ -274,19 +374,19 @@ hm_status launch(hm_server* S, Group& g) {
     }
     hipStream_t s = S->streams[g.stream];
     std::vector<BlockCall> calls;
+    std::vector<CopyPool::Job> xcopies;
+    for (Block& b : g.blocks) {
+        double* Xst = (double*)(S->host_base + b.host_off);
+        int64_t c = 0;
+        for (size_t t = 0; t < b.tickets.size(); ++t) {
+            xcopies.push_back(CopyPool::Job{Xst + c * b.n, b.x_of[t], b.n * b.cols_of[t], 1.0});
+            c += b.cols_of[t];
+        }
+    }
+    S->pool->run(xcopies);
     for (Block& b : g.blocks) {
         const int64_t n = b.n, half = b.bytes / 2;
         double* Xst = (double*)(S->host_base + b.host_off);
-        int32_t c = 0;
-        for (uint64_t tk : b.tickets) {
-            const Req* r;
-            {
-                std::lock_guard<std::mutex> lk(S->mu);
-                r = &S->reqs[tk];
-            }
-            std::memcpy(Xst + (int64_t)c * n, r->X, sizeof(double) * n * r->nrhs);
-            c += r->nrhs;
-        }
         double* Xd = (double*)(S->dev_base + b.dev_off);
         double* Yd = (double*)(S->dev_base + b.dev_off + half);
         hipError_t e = hipMemcpyAsync(Xd, Xst, sizeof(double) * n * b.cols, hipMemcpyHostToDevice, s);
@@ -324,11 +424,18 @@ void loop(hm_server* S) {
     if (!S->opts.fake) (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
-        // retire finished groups
+        // retire finished groups: copy results out without the lock, then
+        // mark the requests done
         for (size_t i = 0; i < S->inflight.size();) {
             if (group_finished(S, S->inflight[i])) {
-                retire(S, S->inflight[i]);
+                Group g = std::move(S->inflight[i]);
                 S->inflight.erase(S->inflight.begin() + i);
+                std::vector<std::pair<double*, double>> dst;
+                for (const Block& b : g.blocks) dst.insert(dst.end(), b.y_of.begin(), b.y_of.end());
+                lk.unlock();
+                S->pool->run(result_copies(S, g, dst));
+                lk.lock();
+                retire(S, g);
                 S->cv.notify_all();
             } else {
                 ++i;
@@ -394,6 +501,7 @@ extern "C" hm_status hm_serve_create(const hm_serve_opts* o, hm_server** out) {
         }
     }
     try {
+        S->pool.reset(new hm::CopyPool(3));
         S->th = std::thread(hm::loop, S);
     } catch (...) {
         hm_serve_destroy(S);
