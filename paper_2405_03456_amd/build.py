@@ -45,16 +45,19 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libhm.so.  Always recompiles."""
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
-    objs = []
     inc = ["-I", os.path.join(HERE, "..", "include"), "-I", CSRC]
+    jobs = []
     for s in HOST_SRCS:
         o = os.path.join(BUILD, s + ".o")
-        _run([hipcc, *COMMON, *inc, "-c", os.path.join(CSRC, s), "-o", o])
-        objs.append(o)
+        jobs.append((o, [hipcc, *COMMON, *inc, "-c", os.path.join(CSRC, s), "-o", o]))
     for s in DEVICE_SRCS:
         o = os.path.join(BUILD, s + ".o")
-        _run([hipcc, *COMMON, *DEVICE_FLAGS, *inc, "-x", "hip", "-c", os.path.join(CSRC, s), "-o", o])
-        objs.append(o)
+        jobs.append((o, [hipcc, *COMMON, *DEVICE_FLAGS, *inc, "-x", "hip", "-c", os.path.join(CSRC, s), "-o", o]))
+    # translation units compile in parallel (the device ones dominate)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(len(jobs), max(1, os.cpu_count() or 1))) as ex:
+        list(ex.map(lambda j: _run(j[1]), jobs))
+    objs = [o for o, _ in jobs]
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-lpthread"])
     os.replace(tmp, LIB)
