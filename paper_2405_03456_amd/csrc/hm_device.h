@@ -124,6 +124,7 @@ struct hm_matrix {
     double* ws = nullptr;
     float* ws32 = nullptr;
     double* part = nullptr;
+    const int64_t* dsrc = nullptr;   // per workspace entry: 0 or the partial sums forming it
     const hm::DOwner* owners = nullptr;
     const hm::DItem* items = nullptr;
     const hm::DTask* tasks = nullptr;

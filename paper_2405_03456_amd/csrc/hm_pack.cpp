@@ -380,9 +380,10 @@ struct Builder {
             }
             const int V = tile_cols(it.dtype);
             const int64_t bpt = (int64_t)cur.nrows * 16;     // bytes per tile
-            // narrow owners stage their task's inputs in LDS: at most
-            // MAX_TASK_INPUTS input values (tiles * V) per task
-            const int64_t cap = cur.nrows <= 32 ? (int64_t)(MAX_TASK_INPUTS / V) * bpt : INT64_MAX;
+            // a task may stage its inputs in LDS (narrow owners always, wide
+            // ones when they read unreduced sums): at most MAX_TASK_INPUTS
+            // input values (tiles * V) per task
+            const int64_t cap = (int64_t)(MAX_TASK_INPUTS / V) * bpt;
             const int64_t target = std::min<int64_t>(opt.task_bytes, cap);
             int32_t j = 0;
             while (j < it.ncols) {
@@ -986,6 +987,25 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
             col += it.ncols;
         }
     }
+    // workspace entries left as partial sums in the single-vector product
+    if ((int64_t)P.dsrc.size() != P.ws_elems + TILE_PAD || P.staged.size() != P.tasks.size()) {
+        why = "deferred-sum tables";
+        return false;
+    }
+    std::vector<int32_t> deferred_owner(P.ws_elems + TILE_PAD, -1);
+    for (int64_t o = 0; o < no; ++o) {
+        const DOwner& ow = P.owners[o];
+        const bool deferred = ow.mode == 0 && ow.ntasks > 1;
+        if (deferred && (ow.ntasks >= (1 << 16) || ow.nrows >= (1 << 15))) { why = "deferred-sum range"; return false; }
+        for (int32_t r = 0; r < ow.nrows && ow.mode == 0; ++r) {
+            const int64_t d = P.dsrc[ow.out_off + r];
+            const int64_t want = deferred ? deferred_sum(ow.part_off + r, ow.ntasks, ow.nrows) : 0;
+            if (d != want) { why = "deferred-sum entry"; return false; }
+            if (deferred) deferred_owner[ow.out_off + r] = (int32_t)o;
+        }
+    }
+    for (int64_t e = 0; e < P.ws_elems + TILE_PAD; ++e)
+        if (P.dsrc[e] != 0 && deferred_owner[e] < 0) { why = "deferred-sum entry without owner"; return false; }
     std::vector<int32_t> seen(no, 0), stage_of(no, -1), reduced(no, -1);
     const int32_t ns = (int32_t)P.stages.size();
     for (int32_t si = 0; si < ns; ++si) {
@@ -1024,12 +1044,27 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
                 const DItem& it = P.items[t.item_start];
                 if (t.c0 < it.col0 || t.c0 >= it.col0 + it.ncols) { why = "task first item"; return false; }
                 if ((t.c0 - it.col0) % (16 / dtype_bytes(it.dtype))) { why = "task not tile aligned"; return false; }
-                // one dtype per task; narrow owners' inputs fit the LDS slice
+                // one dtype per task; the inputs fit the LDS slice
                 for (int32_t j = t.item_start; j < ow.item0 + ow.nitems && P.items[j].col0 < t.c1; ++j)
                     if (P.items[j].dtype != it.dtype) { why = "task mixes dtypes"; return false; }
-                if (ow.nrows <= 32 && (int64_t)(t.k1 - t.k0) * (16 / dtype_bytes(it.dtype)) > MAX_TASK_INPUTS) {
+                if ((int64_t)(t.k1 - t.k0) * (16 / dtype_bytes(it.dtype)) > MAX_TASK_INPUTS) {
                     why = "task inputs exceed LDS slice";
                     return false;
+                }
+                // inputs that are unreduced sums: the task stages them, and
+                // their owner ran in an earlier stage of the dependent chain
+                for (int32_t j = t.item_start; j < ow.item0 + ow.nitems && P.items[j].col0 < t.c1; ++j) {
+                    const DItem& dj = P.items[j];
+                    const int32_t jb = std::max(t.c0 - dj.col0, 0), je = std::min(dj.ncols, t.c1 - dj.col0);
+                    for (int32_t c = jb; c < je; ++c) {
+                        const int32_t src = deferred_owner[dj.vec_off + c];
+                        if (src < 0) continue;
+                        if (!P.staged[k]) { why = "unreduced input read without staging"; return false; }
+                        if (st.aux || stage_of[src] < 0 || stage_of[src] >= si) {
+                            why = "unreduced input not produced by an earlier stage";
+                            return false;
+                        }
+                    }
                 }
             }
             ++seen[t.owner];
@@ -1043,6 +1078,15 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
             reduced[r] = si;
             if (P.owners[r].mode == 0 ? stage_of[r] != si : si != ns - 1) { why = "reduce placement"; return false; }
         }
+        // the single-vector product launches the reductions of y owners only
+        size_t ny = 0;
+        for (int32_t r : st.reduce) ny += P.owners[r].mode != 0;
+        if (st.reduce_launch.size() != ny) { why = "reduce launch list"; return false; }
+        for (size_t i = 0, j = 0; i < st.reduce.size(); ++i)
+            if (P.owners[st.reduce[i]].mode != 0 && st.reduce_launch[j++] != st.reduce[i]) {
+                why = "reduce launch list";
+                return false;
+            }
     }
     for (int64_t o = 0; o < no; ++o) {
         if (seen[o] != P.owners[o].ntasks) { why = "task count"; return false; }
@@ -1171,6 +1215,33 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
                 fin.reduce.push_back(o);
         }
         if (!fin.reduce.empty()) out.stages.push_back(std::move(fin));
+        // Single-vector product: a split coefficient owner gets no reduction
+        // launch; each later task reading one of its outputs adds the
+        // partial sums (in task order) while it stages its inputs.  The
+        // reductions of y owners stay (the final stage).
+        out.dsrc.assign(out.ws_elems + TILE_PAD, 0);
+        for (const DOwner& ow : out.owners)
+            if (ow.mode == 0 && ow.ntasks > 1)
+                for (int32_t r = 0; r < ow.nrows; ++r)
+                    out.dsrc[ow.out_off + r] = deferred_sum(ow.part_off + r, ow.ntasks, ow.nrows);
+        {
+            std::vector<int64_t> cnt(out.dsrc.size() + 1, 0);   // prefix count of deferred entries
+            for (size_t e = 0; e < out.dsrc.size(); ++e) cnt[e + 1] = cnt[e] + (out.dsrc[e] != 0);
+            out.staged.assign(out.tasks.size(), 0);
+            for (size_t k = 0; k < out.tasks.size(); ++k) {
+                const DTask& t = out.tasks[k];
+                int32_t c = t.c0;
+                for (int32_t it = t.item_start; c < t.c1; ++it) {
+                    const DItem& item = out.items[it];
+                    const int32_t jb = c - item.col0, je = std::min(item.ncols, t.c1 - item.col0);
+                    if (cnt[item.vec_off + je] > cnt[item.vec_off + jb]) out.staged[k] = 1;
+                    c = item.col0 + je;
+                }
+            }
+        }
+        for (auto& st : out.stages)
+            for (int32_t o : st.reduce)
+                if (out.owners[o].mode != 0) st.reduce_launch.push_back(o);
         for (auto& st : out.stages) {
             for (int64_t k = st.t0; k < st.t1; ++k) {
                 const DTask& t = out.tasks[k];
@@ -1226,7 +1297,7 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
     s.accum = out.acc64 ? HM_ACC_F64 : HM_ACC_F32;
     for (const Source& S : B.src) s.entries_per_dtype[S.dtype] += S.m * S.k;
     s.nlaunch = 1;   // gather
-    for (auto& st : out.stages) s.nlaunch += (st.t1 > st.t0) + !st.reduce.empty();
+    for (auto& st : out.stages) s.nlaunch += (st.t1 > st.t0) + !st.reduce_launch.empty();
     s.algorithmic_bytes = (double)(s.bytes_dense + s.bytes_factors + s.bytes_coupling + s.bytes_transfer +
                                    s.bytes_scales + s.bytes_meta) +
                           24.0 * L.n + 16.0 * (out.ws_elems - L.n);

@@ -22,6 +22,11 @@ struct Packed {
     std::vector<double> scales;    // per-column / per-row scales
     int64_t ws_elems = 0;          // x in cluster order + coefficient vectors
     int64_t part_elems = 0;        // partial sums, one region per split owner
+    // Single-vector product only: per workspace entry (ws_elems + TILE_PAD),
+    // 0 = read the workspace, else deferred_sum(...) of the partial sums
+    // that make up the entry; per task, 1 = stage the inputs through it.
+    std::vector<int64_t> dsrc;
+    std::vector<uint8_t> staged;
     hm_stats stats{};
 };
 

@@ -8,7 +8,9 @@
 // dtype.  The columns of an owner are cut into *tasks* of bounded size; one
 // wavefront runs one task with one lane per output row.  Owners with one
 // task write their result directly, the others leave per-task partial sums
-// that a reduce pass adds in task order (deterministic, no atomics).
+// that are added in task order (deterministic, no atomics): by a reduce pass
+// for y owners, and for coefficient owners of the single-vector product by
+// every later task that reads them (see deferred_sum).
 //
 // Output modes: 0 = coefficient vector (ws[out + r] = v), 1 = y in original
 // order (y[perm[out + r]] += alpha*v), 2 = y in cluster order.
@@ -83,6 +85,15 @@ struct Stage {
     double alg_bytes = 0;        // data + partial/output writes
     int32_t dtype_mask = 0;      // dtypes of the items its tasks touch
     bool aux = false;            // independent of the other stages: runs on a second stream
+    std::vector<int32_t> reduce_launch;   // the owners of `reduce` the single-vector product
+                                          // reduces with a launch (y owners)
 };
+
+// A workspace entry that the single-vector product leaves as the partial
+// sums of its split owner: value = sum over l < count of part[base + l * stride],
+// packed as base | count << 32 | stride << 48 (base < 2^32, count and stride < 2^16).
+inline int64_t deferred_sum(int64_t base, int64_t count, int64_t stride) {
+    return base | (count << 32) | (stride << 48);
+}
 
 }  // namespace hm

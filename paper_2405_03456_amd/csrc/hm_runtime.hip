@@ -93,15 +93,82 @@ __device__ __forceinline__ void tile_acc_w(const uint4& q, const double* wv, dou
     }
 }
 
+// Stage a task's inputs (times their column scales) in this wave's LDS slice
+// in tile order: lw[(t - k0) * V + i] = input of column i of tile t.  With
+// `deferred`, an input that is an unreduced sum (dsrc entry != 0) is formed
+// here from its partial sums, added in task order.  Past an item's last
+// column the values are not needed (its data is zero) but are finite.
+// Each lane takes four entries per pass and loads up to four partial sums of
+// each at once, so the loads of a pass overlap instead of queueing.
+template <int DT>
+__device__ __forceinline__ void stage_inputs(const DTask& tk, const DItem* __restrict__ items, int lane,
+                                             bool deferred, const double* __restrict__ vin,
+                                             const double* __restrict__ scales, const int64_t* __restrict__ dsrc,
+                                             const double* part, double* __restrict__ lw) {
+    constexpr int V = Tile<DT>::V;
+    constexpr int CH = 4;
+    const int k0 = tk.k0;
+    const int nval = (tk.k1 - k0) * V;
+    ItemPos st = item_pos<DT>(items, tk.item_start);
+    for (int base = lane; base < nval; base += 64 * CH) {
+        int e[CH], sc[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int idx = min(base + u * 64, nval - 1);   // a clamped entry is staged twice, same value
+            const int t = k0 + idx / V;
+            while (t >= st.k1) st = item_pos<DT>(items, st.it + 1);
+            const int c = (t - st.k0) * V + idx % V;
+            e[u] = st.vec + c;
+            sc[u] = st.sc >= 0 ? st.sc + c : -1;
+        }
+        int64_t d[CH];
+        double v[CH], f[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            d[u] = deferred ? dsrc[e[u]] : 0;
+            v[u] = vin[e[u]];
+            f[u] = sc[u] >= 0 ? scales[sc[u]] : 1.0;
+        }
+        if (deferred) {
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                if (d[u] == 0) continue;
+                const double* p = part + (uint32_t)d[u];
+                const int cnt = (int)(((uint64_t)d[u] >> 32) & 0xffff);
+                const int64_t stride = (int64_t)((uint64_t)d[u] >> 48);
+                double acc = 0.0;
+                for (int l = 0; l < cnt; l += 4) {
+                    double q[4];
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) q[w] = l + w < cnt ? p[(l + w) * stride] : 0.0;
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) acc += q[w];
+                }
+                v[u] = acc;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int idx = base + u * 64;
+            if (idx < nval) lw[idx] = v[u] * f[u];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Wide owners (more than 32 rows): the wave walks the task's tiles together,
 // a prefetched batch of U tiles always in flight; item bookkeeping is
 // uniform and the inputs are scalar loads (lgkmcnt), so waiting for them
 // never drains the data prefetch (vmcnt).
-template <int DT, bool WIDE>
+template <int DT, bool WIDE, bool STAGED>
 __device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __restrict__ items,
-                                               const uint8_t* __restrict__ sb, int64_t rt,
+                                               const uint8_t* __restrict__ sb, int64_t rt, int lane,
                                                const double* __restrict__ vin, const float* __restrict__ vin32,
-                                               const double* __restrict__ scales, double& a64, float& a32) {
+                                               const double* __restrict__ scales, const int64_t* __restrict__ dsrc,
+                                               const double* part, double* __restrict__ lw, double& a64,
+                                               float& a32) {
     constexpr int V = Tile<DT>::V;
     constexpr int U = Tile<DT>::V <= 4 ? 8 : 4;
     const int k0 = tk.k0, k1 = tk.k1;
@@ -115,6 +182,10 @@ __device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __r
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int kk = kb + u;
+            if (STAGED) {
+                if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw + (kk - k0) * V, a64, a32);
+                continue;
+            }
             if (kk < k1) {
                 while (kk >= st.k1) st = item_pos<DT>(items, st.it + 1);
                 const int c = (kk - st.k0) * V;
@@ -133,6 +204,7 @@ __device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __r
         }
     };
     issue(qa, k0);
+    if (STAGED) stage_inputs<DT>(tk, items, lane, true, vin, scales, dsrc, part, lw);
     for (int k = k0; k < k1; k += 2 * U) {
         issue(qb, k + U);
         __builtin_amdgcn_sched_barrier(0);
@@ -150,8 +222,10 @@ __device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __r
 template <int DT, bool WIDE>
 __device__ __forceinline__ void stream_grouped(const DTask& tk, const DItem* __restrict__ items,
                                                const uint8_t* __restrict__ sb, int64_t rt, int g, int G, int lane,
-                                               const double* __restrict__ vin, const double* __restrict__ scales,
-                                               double* __restrict__ lw, double& a64, float& a32) {
+                                               bool deferred, const double* __restrict__ vin,
+                                               const double* __restrict__ scales, const int64_t* __restrict__ dsrc,
+                                               const double* part, double* __restrict__ lw, double& a64,
+                                               float& a32) {
     constexpr int V = Tile<DT>::V;
     constexpr int U = 4;
     const int k0 = tk.k0, k1 = tk.k1;
@@ -165,23 +239,7 @@ __device__ __forceinline__ void stream_grouped(const DTask& tk, const DItem* __r
     // the first tiles are requested before the inputs are staged, so both
     // memory latencies overlap
     issue(qa, k0);
-    // stage: lw[(t - k0) * V + i] = input of column i of tile t (zero past an
-    // item's last column is not needed: its data is zero)
-    {
-        const int nval = (k1 - k0) * V;
-        ItemPos st = item_pos<DT>(items, tk.item_start);
-        for (int idx = lane; idx < nval; idx += 64) {
-            const int t = k0 + idx / V;
-            while (t >= st.k1) st = item_pos<DT>(items, st.it + 1);
-            const int c = (t - st.k0) * V + idx % V;
-            double v = vin[st.vec + c];
-            if (st.sc >= 0) v *= scales[st.sc + c];
-            lw[idx] = v;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    stage_inputs<DT>(tk, items, lane, deferred, vin, scales, dsrc, part, lw);
     auto consume = [&](const uint4* q, int kb) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -201,13 +259,18 @@ __device__ __forceinline__ void stream_grouped(const DTask& tk, const DItem* __r
 
 template <int DT, bool ACC64>
 __device__ __forceinline__ void stream_task(const DTask& tk, const DItem* items, const uint8_t* sb, int64_t rt,
-                                            int g, int G, int lane, const double* vin, const float* vin32,
-                                            const double* scales, double* lw, double& a64, float& a32) {
+                                            int g, int G, int lane, bool deferred, const double* vin,
+                                            const float* vin32, const double* scales, const int64_t* dsrc,
+                                            const double* part, double* lw, double& a64, float& a32) {
     constexpr bool WIDE = ACC64 || DT == HM_F64;
-    if (G == 1)
-        stream_uniform<DT, WIDE>(tk, items, sb, rt, vin, vin32, scales, a64, a32);
-    else
-        stream_grouped<DT, WIDE>(tk, items, sb, rt, g, G, lane, vin, scales, lw, a64, a32);
+    if (G == 1) {
+        if (deferred)
+            stream_uniform<DT, WIDE, true>(tk, items, sb, rt, lane, vin, vin32, scales, dsrc, part, lw, a64, a32);
+        else
+            stream_uniform<DT, WIDE, false>(tk, items, sb, rt, lane, vin, vin32, scales, dsrc, part, lw, a64, a32);
+    } else {
+        stream_grouped<DT, WIDE>(tk, items, sb, rt, g, G, lane, deferred, vin, scales, dsrc, part, lw, a64, a32);
+    }
 }
 
 // One wavefront per task.  Lane geometry: P = rows per group (next power of
@@ -219,7 +282,8 @@ __global__ __launch_bounds__(256) void k_owner_tasks(
     const DTask* __restrict__ tasks, int ntasks, const DOwner* __restrict__ owners,
     const DItem* __restrict__ items, const uint8_t* __restrict__ data, const double* __restrict__ scales,
     const double* __restrict__ vin, const float* __restrict__ vin32, double* vout, float* vout32,
-    double* __restrict__ part, double* __restrict__ y, const int64_t* __restrict__ perm, double alpha) {
+    double* __restrict__ part, const int64_t* __restrict__ dsrc, double* __restrict__ y,
+    const int64_t* __restrict__ perm, double alpha) {
     __shared__ double lds_w[4][MAX_TASK_INPUTS];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -235,6 +299,8 @@ __global__ __launch_bounds__(256) void k_owner_tasks(
     const int g = lane >> lp;
     const int rl = lane & (P - 1);
     const int dt = tk.dtype;   // in the descriptor: no dependent item load before the tiles
+    const int mode = tk.mode & 3;
+    const bool deferred = (tk.mode & 4) != 0;   // some inputs are unreduced sums
     for (int r0 = 0; r0 < nrows; r0 += P) {
         const int r = r0 + rl;
         const bool act = r < nrows;
@@ -245,22 +311,31 @@ __global__ __launch_bounds__(256) void k_owner_tasks(
         const uint8_t* sb = data + tk.stream + (uint32_t)(rr * 16);
         double* lw = lds_w[wave];
         if constexpr ((MASK & (1 << HM_F64)) != 0)
-            if (dt == HM_F64) stream_task<HM_F64, ACC64>(tk, items, sb, rt, g, G, lane, vin, vin32, scales, lw, a64, a32);
+            if (dt == HM_F64)
+                stream_task<HM_F64, ACC64>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
+                                           a64, a32);
         if constexpr ((MASK & (1 << HM_F32)) != 0)
-            if (dt == HM_F32) stream_task<HM_F32, ACC64>(tk, items, sb, rt, g, G, lane, vin, vin32, scales, lw, a64, a32);
+            if (dt == HM_F32)
+                stream_task<HM_F32, ACC64>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
+                                           a64, a32);
         if constexpr ((MASK & (1 << HM_BF16)) != 0)
-            if (dt == HM_BF16) stream_task<HM_BF16, ACC64>(tk, items, sb, rt, g, G, lane, vin, vin32, scales, lw, a64, a32);
+            if (dt == HM_BF16)
+                stream_task<HM_BF16, ACC64>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
+                                            a64, a32);
         if constexpr ((MASK & (1 << HM_F16)) != 0)
-            if (dt == HM_F16) stream_task<HM_F16, ACC64>(tk, items, sb, rt, g, G, lane, vin, vin32, scales, lw, a64, a32);
+            if (dt == HM_F16)
+                stream_task<HM_F16, ACC64>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
+                                           a64, a32);
         if constexpr ((MASK & (1 << HM_FP8E4M3)) != 0)
             if (dt == HM_FP8E4M3)
-                stream_task<HM_FP8E4M3, ACC64>(tk, items, sb, rt, g, G, lane, vin, vin32, scales, lw, a64, a32);
+                stream_task<HM_FP8E4M3, ACC64>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part,
+                                               lw, a64, a32);
         double v = a64 + (double)a32;
         for (int off = P; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);   // across column groups
         if (act && g == 0) {
             if (tk.rscale_off >= 0) v *= scales[tk.rscale_off + r];
             if (tk.ntasks == 1)
-                finalize(tk.mode, tk.out_off, r, v, vout, vout32, y, perm, alpha);
+                finalize(mode, tk.out_off, r, v, vout, vout32, y, perm, alpha);
             else
                 part[tk.part_off + (int64_t)tk.local * nrows + r] = v;
         }
@@ -317,8 +392,8 @@ __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ x, co
 }
 
 using TaskKernel = void (*)(const DTask*, int, const DOwner*, const DItem*, const uint8_t*, const double*,
-                           const double*, const float*, double*, float*, double*, double*, const int64_t*,
-                           double);
+                           const double*, const float*, double*, float*, double*, const int64_t*, double*,
+                           const int64_t*, double);
 
 template <bool ACC64, int... M>
 constexpr std::array<TaskKernel, sizeof...(M)> task_kernels(std::integer_sequence<int, M...>) {
@@ -371,11 +446,14 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     meta = align256(meta + P.items.size() * sizeof(hm::DItem));
     const size_t o_tasks = meta;
     meta = align256(meta + P.tasks.size() * sizeof(hm::DTask));
+    // the single-vector product launches reductions for y owners only
     std::vector<size_t> o_red;
     for (auto& st : P.stages) {
         o_red.push_back(meta);
-        meta = align256(meta + st.reduce.size() * sizeof(int32_t));
+        meta = align256(meta + st.reduce_launch.size() * sizeof(int32_t));
     }
+    const size_t o_dsrc = meta;
+    meta = align256(meta + P.dsrc.size() * sizeof(int64_t));
     const int64_t n = layout->L.n;
     size_t o_perm = meta;
     size_t o_data = align256(o_perm + n * sizeof(int64_t));
@@ -408,11 +486,17 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         if (!bytes) return hipSuccess;
         return hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice);
     };
+    // device task table: mode bit 2 marks tasks that stage their inputs
+    // through the deferred-sum table
+    std::vector<hm::DTask> dtasks = P.tasks;
+    for (size_t k = 0; k < dtasks.size(); ++k)
+        if (P.staged[k]) dtasks[k].mode = (int16_t)(dtasks[k].mode | 4);
     e = copy(o_owners, P.owners.data(), P.owners.size() * sizeof(hm::DOwner));
     if (e == hipSuccess) e = copy(o_items, P.items.data(), P.items.size() * sizeof(hm::DItem));
-    if (e == hipSuccess) e = copy(o_tasks, P.tasks.data(), P.tasks.size() * sizeof(hm::DTask));
+    if (e == hipSuccess) e = copy(o_tasks, dtasks.data(), dtasks.size() * sizeof(hm::DTask));
     for (size_t i = 0; i < P.stages.size() && e == hipSuccess; ++i)
-        e = copy(o_red[i], P.stages[i].reduce.data(), P.stages[i].reduce.size() * sizeof(int32_t));
+        e = copy(o_red[i], P.stages[i].reduce_launch.data(), P.stages[i].reduce_launch.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = copy(o_dsrc, P.dsrc.data(), P.dsrc.size() * sizeof(int64_t));
     if (e == hipSuccess) e = copy(o_perm, layout->L.perm.data(), n * sizeof(int64_t));
     if (e == hipSuccess) e = copy(o_data, P.data.data(), P.data.size());
     if (e == hipSuccess) e = copy(o_scales, P.scales.data(), P.scales.size() * sizeof(double));
@@ -420,6 +504,8 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     // zero-data padding columns multiply whatever they read
     if (e == hipSuccess) e = hipMemset(base + o_ws, 0, (P.ws_elems + hm::TILE_PAD) * sizeof(double));
     if (e == hipSuccess) e = hipMemset(base + o_ws32, 0, (P.ws_elems + hm::TILE_PAD) * sizeof(float));
+    // partial sums too: a padding column may read an unreduced sum
+    if (e == hipSuccess) e = hipMemset(base + o_part, 0, std::max<int64_t>(P.part_elems, 1) * sizeof(double));
     if (e != hipSuccess) {
         (void)hipFree(m->arena);
         delete m;
@@ -436,6 +522,7 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     m->ws = (double*)(base + o_ws);
     m->ws32 = (float*)(base + o_ws32);
     m->part = (double*)(base + o_part);
+    m->dsrc = (const int64_t*)(base + o_dsrc);
     m->owners = (const hm::DOwner*)(base + o_owners);
     m->items = (const hm::DItem*)(base + o_items);
     m->tasks = (const hm::DTask*)(base + o_tasks);
@@ -447,7 +534,7 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         d.t0 = st.t0;
         d.ntasks = (int32_t)(st.t1 - st.t0);
         d.reduce = (const int32_t*)(base + o_red[i]);
-        d.nreduce = (int32_t)st.reduce.size();
+        d.nreduce = (int32_t)st.reduce_launch.size();
         d.nowners = 0;
         d.dtype_mask = st.dtype_mask;
         d.data_bytes = st.data_bytes;
@@ -560,7 +647,7 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
             }
             hipLaunchKernelGGL(hm::dev::kTasks[m->acc64 ? 1 : 0][ph.dtype_mask & 31], grid, dim3(256), 0, stream,
                                m->tasks + ph.t0, ph.ntasks, m->owners, m->items, m->data, m->scales, m->ws, m->ws32,
-                               m->ws, m->ws32, m->part, y, perm, alpha);
+                               m->ws, m->ws32, m->part, m->dsrc, y, perm, alpha);
             if (timing) hm::timing_end(ph, stream, ev);
         }
         if (ph.nreduce > 0) {
