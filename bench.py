@@ -82,6 +82,8 @@ def run_variant(hm, torch, lay, fmt, vals, eps, pol, steps, warmup, x, target):
     ncopies = int(min(8, max(1, math.ceil(target / max(stored, 1)))))
     for _ in range(ncopies - 1):
         mats.append(hm.Matrix(lay, fmt, vals, eps=eps, **pol))
+    # fork point of the dense stage, timed per matrix (hm_tune_mvm) before capture
+    tuned = [m.tune_mvm(reps=10) for m in mats]
     y = torch.zeros_like(x)
     graphs = [m.graph(x, y) for m in mats]
     for i in range(warmup):
@@ -118,7 +120,8 @@ def run_variant(hm, torch, lay, fmt, vals, eps, pol, steps, warmup, x, target):
         g.free()
     for m in mats:
         m.free()
-    return dict(stats=s0, ncopies=ncopies, seconds=dt, seconds_eager=dt_eager, phases=phases, y=y_out)
+    return dict(stats=s0, ncopies=ncopies, seconds=dt, seconds_eager=dt_eager, phases=phases, y=y_out,
+                fork_after=[t["fork_after"] for t in tuned])
 
 
 def summarize(res, steps):
@@ -137,11 +140,11 @@ def summarize(res, steps):
                 "bytes_per_launch": int(dom["algorithmic_bytes"])}
     return dict(ms_per_step=ms, gbs=gbs, matvecs_per_s=1e3 / ms, roofline=roof,
                 eager_ms_per_step=res["seconds_eager"] * 1e3 / steps,
-                algorithmic_bytes=s["algorithmic_bytes"], copies=res["ncopies"],
+                algorithmic_bytes=s["algorithmic_bytes"], copies=res["ncopies"], fork_after=res["fork_after"],
                 phases=[{"name": p["name"], "ntasks": p["ntasks"],
                          "us_avg": round(p["ms_total"] * 1e3 / max(p["launches"], 1), 2),
-                         "GBs": round(p["algorithmic_bytes"] / max(p["ms_total"] / max(p["launches"], 1), 1e-9)
-                                      / 1e6, 1)} for p in res["phases"]])
+                         "GBs": (round(p["algorithmic_bytes"] / (p["ms_total"] / p["launches"]) / 1e6, 1)
+                                 if p["launches"] and p["ms_total"] > 0 else None)} for p in res["phases"]])
 
 
 def measured_traffic(workload, policy):
@@ -471,12 +474,14 @@ def main():
                    "storage": "f64", "accumulation": "f64", "rotated_copies": main_s["copies"]},
         "matvecs_per_s": round(main_s["matvecs_per_s"], 1),
         "timing": "graph replay (one hipGraph per rotated copy); roofline from event-timed eager products",
+        "fork_after": main_s["fork_after"],
         "eager_ms_per_step": round(main_s["eager_ms_per_step"], 5),
         "algorithmic_bytes_per_matvec": int(main_s["algorithmic_bytes"]),
         "roofline": main_s["roofline"],
         "phases_f64": main_s["phases"],
         "valr_storage": {"GBs": round(valr_s["gbs"], 1), "matvecs_per_s": round(valr_s["matvecs_per_s"], 1),
                          "ms_per_step": round(valr_s["ms_per_step"], 5),
+                         "fork_after": valr_s["fork_after"],
                          "speedup_vs_f64": round(main_s["ms_per_step"] / valr_s["ms_per_step"], 3),
                          "algorithmic_bytes_per_matvec": int(valr_s["algorithmic_bytes"]),
                          "bytes_per_dtype": results["valr"]["stats"]["bytes_per_dtype"],

@@ -253,6 +253,28 @@ typedef struct {
 hm_status hm_tune_batch(hm_matrix* m, int32_t nrhs, int32_t vec_dtype, int32_t reps, hm_stream_t stream,
                         hm_tune_result* out);
 
+/* Autotuner of the single-vector product.  The dependent chain of stages
+ * (cluster-basis and coupling passes) runs on the caller's stream and the
+ * dense near-field stage, which reads only x, on a second stream.  Its one
+ * free parameter is the fork point: how many chain stages complete before
+ * the dense stage starts (0 = right after x is gathered).  Starting it later
+ * keeps it off the chain's bandwidth-heavy first stages and lets it fill the
+ * latency-bound ones.  hm_tune_mvm times every fork point (`reps` replays of
+ * a captured graph of the product on a zero vector, allocated and freed
+ * here) and keeps the fastest for this matrix.  The fork point changes no
+ * arithmetic: products are bitwise identical for every choice.  It
+ * allocates and synchronises: call it outside graph capture, before
+ * creating graphs of the matrix (graphs keep the fork point they were
+ * captured with).  A matrix without a dense stage reports one candidate.
+ * Errors: HM_EINVAL, HM_ENOMEM, HM_EDEVICE. */
+typedef struct {
+    int32_t fork_after;     /* chosen: chain stages completed before the dense stage starts */
+    int32_t ncandidates;    /* fork points timed */
+    double ms;              /* mean time per product at the chosen fork point */
+    double ms_first;        /* ... at fork point 0 */
+} hm_tune_mvm_result;
+hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream, hm_tune_mvm_result* out);
+
 /* A product captured into a HIP graph: the kernels of one hm_mvm call with
  * fixed (alpha, x, y, flags) recorded once and replayed with one launch.
  * Replays read x and update y in place exactly like hm_mvm; results are

@@ -204,6 +204,12 @@ class Matrix:
                                             _stream_ptr(stream), ctypes.byref(r)))
         return dict(target_bytes=r.target_bytes, nrb=r.nrb, ms=r.ms, ncandidates=r.ncandidates)
 
+    def tune_mvm(self, reps: int = 10, stream=None) -> dict:
+        """Pick the single-vector fork point of the dense stage (hm_tune_mvm)."""
+        r = _lib.TuneMvmResult()
+        _lib.check(_lib.lib().hm_tune_mvm(self._h, int(reps), _stream_ptr(stream), ctypes.byref(r)))
+        return dict(fork_after=r.fork_after, ncandidates=r.ncandidates, ms=r.ms, ms_first=r.ms_first)
+
     def graph(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None) -> "Graph":
         """Capture one product (fixed x, y, alpha) into a replayable HIP graph."""
         return Graph(self, x, y, alpha, cluster_order, stream)

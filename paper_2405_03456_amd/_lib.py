@@ -66,6 +66,10 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("target_bytes", c_int64), ("nrb", c_int32), ("ms", c_double), ("ncandidates", c_int32)]
 
 
+class TuneMvmResult(ctypes.Structure):
+    _fields_ = [("fork_after", c_int32), ("ncandidates", c_int32), ("ms", c_double), ("ms_first", c_double)]
+
+
 class ServeOpts(ctypes.Structure):
     _fields_ = [("mem_budget", c_int64), ("max_slots", c_int32), ("max_queue", c_int32), ("max_cols", c_int32),
                 ("fake", c_int32), ("fake_us", c_int32)]
@@ -97,6 +101,7 @@ SIGNATURES = {
                                P(c_void_p), P(c_int64), c_int32, c_uint32, c_void_p]),
     "hm_graph_create": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p, P(c_void_p)]),
     "hm_tune_batch": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, P(TuneResult)]),
+    "hm_tune_mvm": (c_int32, [c_void_p, c_int32, c_void_p, P(TuneMvmResult)]),
     "hm_graph_create_batch": (c_int32, [P(c_void_p), c_int32, c_double, P(c_void_p), P(c_int64), P(c_int32),
                                         P(c_void_p), P(c_int64), c_int32, c_uint32, c_void_p, P(c_void_p)]),
     "hm_graph_launch": (c_int32, [c_void_p, c_void_p]),

@@ -125,6 +125,7 @@ struct hm_matrix {
     float* ws32 = nullptr;
     double* part = nullptr;
     const int64_t* dsrc = nullptr;   // per workspace entry: 0 or the partial sums forming it
+    int32_t fork_after = 0;          // main-stream stages before the second stream starts
     const hm::DOwner* owners = nullptr;
     const hm::DItem* items = nullptr;
     const hm::DTask* tasks = nullptr;

@@ -343,7 +343,7 @@ __global__ __launch_bounds__(256) void k_owner_tasks(
     }
 }
 
-// Sum the partial results of split owners in task order, one wave per owner.
+// Sum the partial results of split owners in a fixed order, one wave per owner.
 __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list, int nlist,
                                                 const DOwner* __restrict__ owners,
                                                 const double* __restrict__ part, double* vout, float* vout32,
@@ -363,19 +363,35 @@ __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list
     for (int r0 = 0; r0 < nrows; r0 += P) {
         const int r = r0 + rl;
         const bool act = r < nrows;
-        double v0 = 0.0, v1 = 0.0;
+        // y owners: the destination is read before the partial sums, so
+        // its latency overlaps theirs
+        double* yp = nullptr;
+        double y0 = 0.0;
+        if (act && g == 0 && ow.mode != 0) {
+            yp = y + (ow.mode == 1 && perm ? perm[ow.out_off + r] : (int64_t)(ow.out_off + r));
+            y0 = *yp;
+        }
+        // eight sums, each over every 8G-th partial: the loads of a pass are
+        // independent (missing ones read as zero)
+        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (act) {
             const double* p = part + ow.part_off + r;
-            int l = g;
-            for (; l + G < nt; l += 2 * G) {
-                v0 += p[(int64_t)l * nrows];
-                v1 += p[(int64_t)(l + G) * nrows];
+            for (int l = g; l < nt; l += 8 * G) {
+                double q[8];
+#pragma unroll
+                for (int w = 0; w < 8; ++w) q[w] = l + w * G < nt ? p[(int64_t)(l + w * G) * nrows] : 0.0;
+#pragma unroll
+                for (int w = 0; w < 8; ++w) acc[w] += q[w];
             }
-            if (l < nt) v0 += p[(int64_t)l * nrows];
         }
-        double v = v0 + v1;
+        double v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         for (int off = P; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-        if (act && g == 0) finalize(ow.mode, ow.out_off, r, v, vout, vout32, y, perm, alpha);
+        if (act && g == 0) {
+            if (yp)
+                *yp = y0 + alpha * v;
+            else
+                finalize(ow.mode, ow.out_off, r, v, vout, vout32, y, perm, alpha);
+        }
     }
 }
 
@@ -557,6 +573,7 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     }
     m->stats = P.stats;
     if (const char* e = std::getenv("HM_DENSE_GRID")) m->aux_grid = std::max(0, std::atoi(e));
+    if (const char* e = std::getenv("HM_FORK_AFTER")) m->fork_after = std::max(0, std::atoi(e));
     m->h_owners = P.owners;
     m->h_items = P.items;
     m->h_tasks = P.tasks;
@@ -622,13 +639,24 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
     const int64_t* perm = cluster ? nullptr : m->perm;
     const bool timing = (flags & HM_TIMING) != 0;
     const hipStream_t main_stream = stream;
-    if (m->aux) {
-        // fork: the dense stage runs on the second stream after x is gathered
+    int fork_left = m->fork_after;   // main-stream stages launched before the second stream starts
+    auto fork = [&]() {
+        // fork: the dense stage runs on the second stream once x is gathered
+        // and the first fork_after stages of the chain are done
         (void)hipEventRecord(m->ev_fork, main_stream);
         (void)hipStreamWaitEvent(m->aux, m->ev_fork, 0);
+    };
+    bool forked = m->aux == nullptr;
+    if (!forked && fork_left <= 0) {
+        fork();
+        forked = true;
     }
     bool joined = m->aux == nullptr;
     for (auto& ph : m->phases) {
+        if (ph.aux && !forked) {   // at the latest before the second-stream stage
+            fork();
+            forked = true;
+        }
         stream = ph.aux ? m->aux : main_stream;
         if (!joined && !ph.aux && ph.ntasks == 0 && &ph == &m->phases.back()) {
             // join before the final reduction of the row owners
@@ -654,6 +682,10 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
             dim3 grid((unsigned)((ph.nreduce + 3) / 4));
             hipLaunchKernelGGL(hm::dev::k_reduce, grid, dim3(256), 0, stream, ph.reduce, ph.nreduce, m->owners,
                                m->part, m->ws, m->ws32, y, perm, alpha);
+        }
+        if (!forked && !ph.aux && ph.ntasks > 0 && --fork_left == 0) {
+            fork();
+            forked = true;
         }
     }
     if (!joined) {   // no final reduction stage: still join the second stream
@@ -757,6 +789,78 @@ extern "C" hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x
     return capture_graph("hm_graph_create", stream_, out, [&](hm_stream_t s) {
         return hm_mvm(m, alpha, x, y, flags, s);
     });
+}
+
+extern "C" hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream_, hm_tune_mvm_result* out) {
+    if (!m || !out || reps < 1) {
+        hm::set_error("hm_tune_mvm: null argument or reps < 1");
+        return HM_EINVAL;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != m->device) {
+        hm::set_error("hm_tune_mvm: current device differs from the matrix's device");
+        return HM_EINVAL;
+    }
+    *out = hm_tune_mvm_result{0, 0, 0.0, 0.0};
+    int32_t nchain = 0;   // main-stream stages with tasks: the possible fork points are 0 ... nchain
+    for (auto& ph : m->phases) nchain += !ph.aux && ph.ntasks > 0;
+    const int32_t last = m->aux ? nchain : 0;
+    const hipStream_t stream = (hipStream_t)stream_;
+    const size_t bytes = (size_t)m->n * sizeof(double);
+    double* x = nullptr;
+    double* y = nullptr;
+    if (hipMalloc((void**)&x, std::max<size_t>(bytes, 8)) != hipSuccess ||
+        hipMalloc((void**)&y, std::max<size_t>(bytes, 8)) != hipSuccess) {
+        if (x) (void)hipFree(x);
+        hm::set_error("hm_tune_mvm: hipMalloc of the trial vectors failed");
+        return HM_ENOMEM;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMemset(x, 0, std::max<size_t>(bytes, 8));
+    if (e == hipSuccess) e = hipMemset(y, 0, std::max<size_t>(bytes, 8));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    hm_status st = e == hipSuccess ? HM_OK : hip_fail("hm_tune_mvm: set-up", e);
+    const int32_t keep = m->fork_after;
+    int32_t best = keep;
+    double best_ms = 0.0;
+    for (int32_t f = 0; f <= last && st == HM_OK; ++f) {
+        m->fork_after = f;
+        hm_graph* g = nullptr;
+        st = hm_graph_create(m, 1.0, x, y, 0, stream_, &g);
+        if (st != HM_OK) break;
+        float ms = 0.0f;
+        e = hipSuccess;
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipGraphLaunch(g->exec, stream);   // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, stream);
+        for (int i = 0; i < reps && e == hipSuccess; ++i) e = hipGraphLaunch(g->exec, stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        hm_graph_free(g);
+        if (e != hipSuccess) {
+            st = hip_fail("hm_tune_mvm: timing", e);
+            break;
+        }
+        const double t = (double)ms / reps;
+        ++out->ncandidates;
+        if (f == 0) out->ms_first = t;
+        if (f == 0 || t < best_ms) {
+            best = f;
+            best_ms = t;
+        }
+    }
+    m->fork_after = st == HM_OK ? best : keep;
+    if (st == HM_OK) {
+        out->fork_after = best;
+        out->ms = best_ms;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(x);
+    (void)hipFree(y);
+    return st;
 }
 
 extern "C" hm_status hm_graph_create_batch(hm_matrix* const* mats, int32_t nmat, double alpha,

@@ -124,3 +124,33 @@ def test_identity_kernel_rank_zero_blocks():
     for fmt in ("h", "uh", "h2"):
         out = run_gpu(lay, fmt, vals[fmt], x, y, -0.5)
         assert np.array_equal(out, y - 0.5 * x), fmt
+
+
+@pytest.mark.parametrize("fmt", ["uh", "h2"])
+def test_tune_mvm_keeps_results_bitwise(fmt):
+    """hm_tune_mvm times every fork point of the dense stage and keeps the
+    fastest; the fork point moves work in time only, so eager products and
+    graph replays after tuning equal the untuned product bit for bit."""
+    import paper_2405_03456_amd as hm
+    torch = torch_cuda()
+    n = 2048
+    p, st, lay, vals = make(n, 1e-8)
+    x, y = gaussian_vector(n, 12), gaussian_vector(n, 13)
+    M = hm.Matrix(lay, fmt, vals[fmt], dense="valr", diag="valr", factor="valr", eps=1e-6)
+    xd = torch.from_numpy(x).cuda()
+    y0 = torch.from_numpy(y.copy()).cuda()
+    M.mvm(xd, y0, alpha=0.5)
+    r = M.tune_mvm(reps=3)
+    # one candidate per fork point 0 ... number of chain stages with tasks
+    nchain = sum(1 for ph in M.timing() if ph["ntasks"] > 0 and ph["name"] != "dense")
+    assert r["ncandidates"] == nchain + 1 and 0 <= r["fork_after"] < r["ncandidates"]
+    assert r["ms"] > 0 and r["ms"] <= r["ms_first"]
+    y1 = torch.from_numpy(y.copy()).cuda()
+    M.mvm(xd, y1, alpha=0.5)
+    y2 = torch.from_numpy(y.copy()).cuda()
+    g = M.graph(xd, y2, alpha=0.5)
+    g.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1) and torch.equal(y0, y2)
+    g.free()
+    M.free()
