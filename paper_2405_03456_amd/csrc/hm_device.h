@@ -185,10 +185,9 @@ hm_status batch_prepare(hm_matrix* const* mats, int32_t nmat, const int32_t* nrh
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-// HM_TIMING: record the start event of one phase launch of block width
-// `width` on `s` (pending pairs of another width are dropped first).
-inline bool timing_begin(hm_matrix* m, DevStage& ph, int32_t width, hipStream_t s,
-                         std::pair<hipEvent_t, hipEvent_t>& ev) {
+// HM_TIMING: take an event pair for one phase launch of block width
+// `width` (pending pairs of another width are dropped first).
+inline bool timing_acquire(hm_matrix* m, DevStage& ph, int32_t width, std::pair<hipEvent_t, hipEvent_t>& ev) {
     if (ph.timed_nrhs != width) {
         for (auto& e : ph.pending) m->event_pool.push_back(e);
         ph.pending.clear();
@@ -200,7 +199,14 @@ inline bool timing_begin(hm_matrix* m, DevStage& ph, int32_t width, hipStream_t 
         ev = m->event_pool.back();
         m->event_pool.pop_back();
     }
-    return hipEventRecord(ev.first, s) == hipSuccess;
+    return true;
+}
+
+// ... and record its start event on `s` (phases of several launches: the
+// pair brackets all of them)
+inline bool timing_begin(hm_matrix* m, DevStage& ph, int32_t width, hipStream_t s,
+                         std::pair<hipEvent_t, hipEvent_t>& ev) {
+    return timing_acquire(m, ph, width, ev) && hipEventRecord(ev.first, s) == hipSuccess;
 }
 
 inline void timing_end(DevStage& ph, hipStream_t s, const std::pair<hipEvent_t, hipEvent_t>& ev) {

@@ -9,6 +9,7 @@
 // No lane ever reduces with another lane, and no output is written by two
 // waves: owners split over several tasks write partial sums that a second
 // kernel adds in task order.  The product is therefore deterministic.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -668,15 +669,25 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
             unsigned blocks = (unsigned)((ph.ntasks + 3) / 4);
             if (ph.aux && m->aux_grid > 0) blocks = std::min<unsigned>(blocks, (unsigned)m->aux_grid);
             dim3 grid(blocks);
-            std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-            if (timing && !hm::timing_begin(m, ph, 1, stream, ev)) {
-                hm::set_error("hm_mvm: timing events failed");
-                return HM_EDEVICE;
+            const hm::dev::TaskKernel kern = hm::dev::kTasks[m->acc64 ? 1 : 0][ph.dtype_mask & 31];
+            if (timing) {
+                // the event pair is part of the dispatch: it brackets the
+                // kernel's execution, as a kernel trace does
+                std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+                if (!hm::timing_acquire(m, ph, 1, ev)) {
+                    hm::set_error("hm_mvm: timing events failed");
+                    return HM_EDEVICE;
+                }
+                hipExtLaunchKernelGGL(kern, grid, dim3(256), 0, stream, ev.first, ev.second, 0, m->tasks + ph.t0,
+                                      ph.ntasks, m->owners, m->items, m->data, m->scales, (const double*)m->ws,
+                                      (const float*)m->ws32, m->ws, m->ws32, m->part, (const int64_t*)m->dsrc, y,
+                                      perm, alpha);
+                ph.pending.push_back(ev);
+            } else {
+                hipLaunchKernelGGL(kern, grid, dim3(256), 0, stream, m->tasks + ph.t0, ph.ntasks, m->owners,
+                                   m->items, m->data, m->scales, m->ws, m->ws32, m->ws, m->ws32, m->part, m->dsrc, y,
+                                   perm, alpha);
             }
-            hipLaunchKernelGGL(hm::dev::kTasks[m->acc64 ? 1 : 0][ph.dtype_mask & 31], grid, dim3(256), 0, stream,
-                               m->tasks + ph.t0, ph.ntasks, m->owners, m->items, m->data, m->scales, m->ws, m->ws32,
-                               m->ws, m->ws32, m->part, m->dsrc, y, perm, alpha);
-            if (timing) hm::timing_end(ph, stream, ev);
         }
         if (ph.nreduce > 0) {
             dim3 grid((unsigned)((ph.nreduce + 3) / 4));
