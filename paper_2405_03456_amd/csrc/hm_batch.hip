@@ -356,17 +356,25 @@ __global__ __launch_bounds__(256) void k_tasks_multi(const Jobs J) {
                                 jb.ym, jb.partm, jb.R, jb.n, threadIdx.x & 63);
 }
 
-// Sum the partial results of split owners in task order.  Entries are
+// Sum the partial results of split owners in a fixed order.  Entries are
 // independent: block (o, c) of the grid sums entries [256c, 256c + 256) of
-// owner o of the list, one thread per entry.
+// owner o of the list, one thread per entry, with eight independent sums
+// (the loads of a pass are all in flight at once; missing ones read zero).
 __device__ __forceinline__ void reduce_entry(const DOwner& ow, int64_t idx, const double* __restrict__ partm,
                                              double* wsm, float* wsm32, double* __restrict__ ym, int R,
                                              bool mat64) {
     const int64_t span = (int64_t)ow.nrows * R;
     if (idx >= span) return;
     const double* p = partm + (int64_t)ow.part_off * R + idx;
-    double v = 0.0;
-    for (int l = 0; l < ow.ntasks; ++l) v += p[(int64_t)l * span];
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int l = 0; l < ow.ntasks; l += 8) {
+        double q[8];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) q[w] = l + w < ow.ntasks ? p[(int64_t)(l + w) * span] : 0.0;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) acc[w] += q[w];
+    }
+    const double v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     const int64_t e = (int64_t)ow.out_off * R + idx;
     if (ow.mode == 0) {
         if (mat64)
