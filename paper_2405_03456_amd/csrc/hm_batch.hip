@@ -10,13 +10,16 @@
 //   * lane l = 16*kq + rl loads the 16-byte tile row `rl` of tile kb + kq,
 //     so one wave load brings in 4 tiles of 16 rows (1 KiB);
 //   * element c of that tile row is the A operand A[rl][kq] of MFMA #c, the
-//     matching input value W[col(kb + kq, c)][j0 + rl] the B operand, so the
-//     V MFMAs of a load step cover all 4*V columns of the 4 tiles;
+//     matching input value W[col(kb + kq, c)][j0 + NRB*rl + b] the B operand
+//     of right-hand-side block b, so the V MFMAs of a load step cover all
+//     4*V columns of the 4 tiles;
 //   * each wave owns up to 64 rows (4 row groups) and 16*NRB right-hand
-//     sides, and keeps 4*NRB accumulator tiles in registers.
+//     sides, and keeps 4*NRB accumulator tiles in registers.  Output column
+//     rl of block b is right-hand side j0 + NRB*rl + b: the NRB values one
+//     lane needs are adjacent and come in one load.
 //
 // Vectors live in entry-major workspaces (value j of entry i at i*R + j), so
-// the B operands of 16 lanes are 16 consecutive values.  The input X is
+// the B operands of 16 lanes are 16*NRB consecutive values.  The input X is
 // gathered into cluster order and the output accumulated into a cluster-
 // order buffer; both are transposed through LDS to and from the caller's
 // column-major X and Y.
@@ -181,16 +184,29 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
         const int cb = (tc - myt0) * V;
 #pragma unroll
         for (int c = 0; c < V; ++c) {
-            const int64_t wi = (int64_t)(myvec + cb + c) * R + j0 + rl;
+            const int64_t wi = (int64_t)(myvec + cb + c) * R + j0 + NRB * rl;
             T s = (T)1;
             if (mysc >= 0) s = (T)o.scales[mysc + cb + c];
             if (!valid) s = (T)0;
             // float64 products read float64 inputs where they exist: always
             // in a float64 matrix, only x in a float32 one
             const bool wide_in = ACC64 && (o.mat64 || myvec + cb + c < o.n);
+            if constexpr (NRB == 2) {
+                // R and j0 are multiples of 32: wi is even, the pair aligned
+                if (wide_in) {
+                    const double2 w = *reinterpret_cast<const double2*>(wsm + wi);
+                    f.b[c][0] = (T)w.x * s;
+                    f.b[c][1] = (T)w.y * s;
+                } else {
+                    const float2 w = *reinterpret_cast<const float2*>(wsm32 + wi);
+                    f.b[c][0] = (T)w.x * s;
+                    f.b[c][1] = (T)w.y * s;
+                }
+            } else {
 #pragma unroll
-            for (int b = 0; b < NRB; ++b)
-                f.b[c][b] = (wide_in ? (T)wsm[wi + 16 * b] : (T)wsm32[wi + 16 * b]) * s;
+                for (int b = 0; b < NRB; ++b)
+                    f.b[c][b] = (wide_in ? (T)wsm[wi + b] : (T)wsm32[wi + b]) * s;
+            }
         }
     };
     auto compute = [&](const Buf& f) {
@@ -254,7 +270,7 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
                         v = acc[g][b][i];
                     else
                         v = sum[g][b][i];
-                    put(tk, o, row, j0 + 16 * b + rl, v);
+                    put(tk, o, row, j0 + NRB * rl + b, v);
                 }
         }
     }
