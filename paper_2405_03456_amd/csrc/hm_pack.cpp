@@ -992,11 +992,14 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
         why = "deferred-sum tables";
         return false;
     }
+    // an owner is deferred when its first entry is (then all of them are)
     std::vector<int32_t> deferred_owner(P.ws_elems + TILE_PAD, -1);
+    std::vector<uint8_t> is_deferred(no, 0);
     for (int64_t o = 0; o < no; ++o) {
         const DOwner& ow = P.owners[o];
-        const bool deferred = ow.mode == 0 && ow.ntasks > 1;
+        const bool deferred = ow.mode == 0 && ow.ntasks > 1 && P.dsrc[ow.out_off] != 0;
         if (deferred && (ow.ntasks >= (1 << 16) || ow.nrows >= (1 << 15))) { why = "deferred-sum range"; return false; }
+        is_deferred[o] = deferred;
         for (int32_t r = 0; r < ow.nrows && ow.mode == 0; ++r) {
             const int64_t d = P.dsrc[ow.out_off + r];
             const int64_t want = deferred ? deferred_sum(ow.part_off + r, ow.ntasks, ow.nrows) : 0;
@@ -1078,12 +1081,14 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
             reduced[r] = si;
             if (P.owners[r].mode == 0 ? stage_of[r] != si : si != ns - 1) { why = "reduce placement"; return false; }
         }
-        // the single-vector product launches the reductions of y owners only
-        size_t ny = 0;
-        for (int32_t r : st.reduce) ny += P.owners[r].mode != 0;
-        if (st.reduce_launch.size() != ny) { why = "reduce launch list"; return false; }
+        // the single-vector product launches the reductions of the owners
+        // that are not deferred (y owners, coefficient owners of stages with
+        // a long owner), in the order of `reduce`
+        size_t nl = 0;
+        for (int32_t r : st.reduce) nl += !is_deferred[r];
+        if (st.reduce_launch.size() != nl) { why = "reduce launch list"; return false; }
         for (size_t i = 0, j = 0; i < st.reduce.size(); ++i)
-            if (P.owners[st.reduce[i]].mode != 0 && st.reduce_launch[j++] != st.reduce[i]) {
+            if (!is_deferred[st.reduce[i]] && st.reduce_launch[j++] != st.reduce[i]) {
                 why = "reduce launch list";
                 return false;
             }
@@ -1215,15 +1220,29 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
                 fin.reduce.push_back(o);
         }
         if (!fin.reduce.empty()) out.stages.push_back(std::move(fin));
-        // Single-vector product: a split coefficient owner gets no reduction
-        // launch; each later task reading one of its outputs adds the
-        // partial sums (in task order) while it stages its inputs.  The
-        // reductions of y owners stay (the final stage).
+        // Single-vector product: the split coefficient owners of a stage get
+        // no reduction launch when none of them has more than
+        // kMaxDeferredTasks tasks; each later task reading one of their
+        // outputs adds the partial sums (in task order) while it stages its
+        // inputs.  A stage with a longer owner keeps its launch (every
+        // consumer re-adding hundreds of partials costs more than one
+        // launch).  The reductions of y owners stay (the final stage).
+        constexpr int32_t kMaxDeferredTasks = 16;
         out.dsrc.assign(out.ws_elems + TILE_PAD, 0);
-        for (const DOwner& ow : out.owners)
-            if (ow.mode == 0 && ow.ntasks > 1)
-                for (int32_t r = 0; r < ow.nrows; ++r)
-                    out.dsrc[ow.out_off + r] = deferred_sum(ow.part_off + r, ow.ntasks, ow.nrows);
+        for (auto& st : out.stages) {
+            int32_t longest = 0;
+            for (int32_t o : st.reduce)
+                if (out.owners[o].mode == 0) longest = std::max(longest, out.owners[o].ntasks);
+            const bool defer = longest <= kMaxDeferredTasks;
+            for (int32_t o : st.reduce) {
+                const DOwner& ow = out.owners[o];
+                if (ow.mode == 0 && defer)
+                    for (int32_t r = 0; r < ow.nrows; ++r)
+                        out.dsrc[ow.out_off + r] = deferred_sum(ow.part_off + r, ow.ntasks, ow.nrows);
+                else
+                    st.reduce_launch.push_back(o);
+            }
+        }
         {
             std::vector<int64_t> cnt(out.dsrc.size() + 1, 0);   // prefix count of deferred entries
             for (size_t e = 0; e < out.dsrc.size(); ++e) cnt[e + 1] = cnt[e] + (out.dsrc[e] != 0);
@@ -1239,9 +1258,6 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
                 }
             }
         }
-        for (auto& st : out.stages)
-            for (int32_t o : st.reduce)
-                if (out.owners[o].mode != 0) st.reduce_launch.push_back(o);
         for (auto& st : out.stages) {
             for (int64_t k = st.t0; k < st.t1; ++k) {
                 const DTask& t = out.tasks[k];
