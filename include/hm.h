@@ -169,7 +169,9 @@ typedef struct hm_matrix hm_matrix;
  * the environment at upload: HM_TASK_BYTES (stored bytes per task, default
  * 32768), HM_CONCURRENT_DENSE (0 = spread the dense leaves over the
  * dependent stages instead of one stage on a second stream), HM_DENSE_GRID
- * (cap on the workgroups of that second-stream stage; 0 = none).  Blocks whose value pointers
+ * (cap on the workgroups of that second-stream stage; 0 = none),
+ * HM_FORK_AFTER (initial fork point of that stage, see hm_tune_mvm;
+ * default 0).  Blocks whose value pointers
  * are required but NULL, ranks that are negative or exceed the block size,
  * and non-finite values give HM_EINVAL / HM_ELAYOUT.  The layout must stay
  * alive as long as the matrix.  Returns after the copy has completed. */
