@@ -7,8 +7,10 @@
 // column-major slab), widens it from its storage format, and accumulates
 // A[r, j] * w_j, where w_j = input[j] * scale_j is uniform across the wave.
 // No lane ever reduces with another lane, and no output is written by two
-// waves: owners split over several tasks write partial sums that a second
-// kernel adds in task order.  The product is therefore deterministic.
+// waves: owners split over several tasks write partial sums that are added
+// in a fixed order, by a reduction kernel (y owners, and coefficient owners
+// of stages with long owners) or by every later task that reads them while
+// it stages its inputs.  The product is therefore deterministic.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
