@@ -229,3 +229,32 @@ def test_batch_many_matrices_merged_launches():
         assert torch.equal(Ys[i], Y0[i]), i
     for M in Ms:
         M.free()
+
+
+def test_batch_maximum_width_and_beyond():
+    """HM_MAX_NRHS columns in one call match the oracle column by column;
+    one column more is rejected before anything runs."""
+    import torch
+    import paper_2405_03456_amd as hm
+    n = 300
+    p = sphere_points(n, 79)
+    st = trees.build_structure(p)
+    lay = hm.Layout(p)
+    h = compress_h(p, KERNEL_LAPLACE, st, 1e-8, method="svd")
+    vals = {"h": h, "uh": to_uh(h, st)}
+    pp, tol = POLICIES["f32"]
+    for fmt in ("h", "uh"):
+        M = hm.Matrix(lay, fmt, vals[fmt], **pp)
+        r = 1024
+        X, Y = gaussian_matrix(n, r, 700), gaussian_matrix(n, r, 701)
+        sv = stored.stored_values(st, fmt, vals[fmt], dense=pp["dense"], factor=pp["factor"], eps=pp["eps"])
+        ref = stored.product_many(st, fmt, sv, 0.5, X, Y)
+        Xd, Yd = padded(torch, X, n, torch.float64), padded(torch, Y, n, torch.float64)
+        M.mvm_many(Xd, Yd, alpha=0.5)
+        torch.cuda.synchronize()
+        assert colerr(Yd.cpu().numpy(), ref, Y) <= tol, fmt
+        Xb = padded(torch, np.zeros((n, r + 1)), n, torch.float64)
+        Yb = padded(torch, np.zeros((n, r + 1)), n, torch.float64)
+        with pytest.raises(hm.HMError):
+            M.mvm_many(Xb, Yb)
+        M.free()
