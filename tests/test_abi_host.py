@@ -133,3 +133,27 @@ def test_valr_errors():
         hm.plan_stats(lay, "uh", uh, eps=1e-6, factor="valr")
     assert "row_sv" in str(ex.value)
     hm.plan_stats(lay, "uh", uh, eps=1e-6, factor="f32")  # not needed otherwise
+
+
+def test_plan_launch_counts(monkeypatch):
+    """Host plan (hm_plan_stats): with the default task size every split
+    coefficient owner of UH/H2 is summed by its consumers, so one product is
+    the gather, one launch per task stage and the final y reduction; with
+    2000-byte tasks some owners exceed the deferral limit and their stages
+    keep a reduction launch."""
+    from synth import KERNEL_LAPLACE, compress_h, to_h2, to_uh
+    n = 2048
+    p = sphere_points(n, 1001)
+    st = trees.build_structure(p)
+    lay = hm.Layout(p)
+    h = compress_h(p, KERNEL_LAPLACE, st, 1e-8, method="svd")
+    vals = {"uh": to_uh(h, st), "h2": to_h2(h, st)}
+    uh_stages = 4   # forward, coupling, backward, dense
+    counts = {}
+    for tb in ("32768", "2000"):
+        monkeypatch.setenv("HM_TASK_BYTES", tb)
+        for fmt, v in vals.items():
+            counts[(tb, fmt)] = hm.plan_stats(lay, fmt, v, eps=1e-8)["nlaunch"]
+    assert counts[("32768", "uh")] == 1 + uh_stages + 1
+    for fmt in vals:
+        assert counts[("2000", fmt)] > counts[("32768", fmt)], fmt
