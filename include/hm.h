@@ -109,6 +109,30 @@ typedef struct {
 hm_status hm_layout_export(const hm_layout* layout, hm_layout_view* view);
 void hm_layout_free(hm_layout* layout);
 
+/* Structure statistics of a layout (Def. 2.1, 2.2), from the partition
+ * alone: no values are needed.  Per level l (distance from the root):
+ * cluster-tree nodes, dense (inadmissible) and low-rank (admissible) block
+ * leaves, and the areas sum |t|*|s| those leaves cover.  The areas of all
+ * leaves add up to n*n (exact cover).  Levels at or beyond
+ * HM_MAX_LEVELS - 1 are counted in the last entry.
+ * Errors: HM_EINVAL (null argument). */
+#define HM_MAX_LEVELS 64
+typedef struct {
+    int64_t n, nnodes, nleaves, nblocks, ndense, nlowrank;
+    int64_t ndiag;                  /* dense leaves with t == s */
+    int32_t depth;                  /* largest node level */
+    int32_t min_leaf, max_leaf;     /* smallest / largest leaf cluster size */
+    double dense_area;              /* sum over dense leaves of |t|*|s| */
+    double lowrank_area;            /* sum over admissible leaves of |t|*|s| */
+    int64_t nodes_per_level[HM_MAX_LEVELS];
+    int64_t dense_per_level[HM_MAX_LEVELS];
+    int64_t lowrank_per_level[HM_MAX_LEVELS];
+    double dense_area_per_level[HM_MAX_LEVELS];
+    double lowrank_area_per_level[HM_MAX_LEVELS];
+} hm_layout_info;
+
+hm_status hm_layout_stats(const hm_layout* layout, hm_layout_info* info);
+
 /* --------------------------------------------------------------- values */
 
 /* float64 values of one matrix, indexed by the layout's node and block ids.
@@ -164,19 +188,39 @@ typedef struct {
 
 typedef struct hm_matrix hm_matrix;
 
+/* Engine options of hm_upload (NULL, or every field 0, gives the defaults).
+ * None of them changes what is computed; they change how the work is cut
+ * into tasks and launches, and valr_promote the storage choice.
+ *   task_bytes     target stored bytes per task (one wavefront); 0 = 32768,
+ *                  else at least 1024
+ *   spread_dense   1 = spread the dense leaves over the dependent stages
+ *                  instead of one stage on a second stream
+ *   dense_grid     cap on the workgroups of that second-stream stage (0 = none)
+ *   fork_after     initial fork point of that stage (see hm_tune_mvm)
+ *   valr_promote   1 = under HM_VALR_AUTO, a format used by fewer columns of
+ *                  a factor than one 16-byte tile holds is stored in the
+ *                  factor's next more precise format present when that costs
+ *                  no extra tile.  Such columns are stored more precisely
+ *                  than their budget delta_i asks (Sec. 4.2), so the bounds
+ *                  of eq. 6 and eq. 7 still hold.  0 = the paper's rule:
+ *                  every column in its own cheapest format. */
+typedef struct {
+    int64_t task_bytes;
+    int32_t spread_dense;
+    int32_t dense_grid;
+    int32_t fork_after;
+    int32_t valr_promote;
+} hm_upload_opts;
+
 /* Quantise on the host per `prec`, pack into level- and row-cluster-ordered
- * streams and copy to the current HIP device.  Tuning overrides read from
- * the environment at upload: HM_TASK_BYTES (stored bytes per task, default
- * 32768), HM_CONCURRENT_DENSE (0 = spread the dense leaves over the
- * dependent stages instead of one stage on a second stream), HM_DENSE_GRID
- * (cap on the workgroups of that second-stream stage; 0 = none),
- * HM_FORK_AFTER (initial fork point of that stage, see hm_tune_mvm;
- * default 0).  Blocks whose value pointers
- * are required but NULL, ranks that are negative or exceed the block size,
- * and non-finite values give HM_EINVAL / HM_ELAYOUT.  The layout must stay
- * alive as long as the matrix.  Returns after the copy has completed. */
+ * streams and copy to the current HIP device.  opts may be NULL (defaults).
+ * Blocks whose value pointers are required but NULL, ranks that are
+ * negative or exceed the block size, non-finite values and out-of-range
+ * options give HM_EINVAL / HM_ELAYOUT.  The layout must stay alive as long
+ * as the matrix.  Returns after the copy has completed. */
 hm_status hm_upload(const hm_layout* layout, int32_t format, const hm_values* values,
-                    const hm_precision* prec, hm_stream_t stream, hm_matrix** out);
+                    const hm_precision* prec, const hm_upload_opts* opts, hm_stream_t stream,
+                    hm_matrix** out);
 void hm_matrix_free(hm_matrix* m);
 
 /* Storage statistics of an uploaded matrix (bytes as stored on the device). */
@@ -202,7 +246,7 @@ hm_status hm_matrix_stats(const hm_matrix* m, hm_stats* s);
  * errors are those of hm_upload.  Used to inspect the per-dtype storage
  * that VALR (Sec. 4.2) selects before committing device memory. */
 hm_status hm_plan_stats(const hm_layout* layout, int32_t format, const hm_values* values,
-                        const hm_precision* prec, hm_stats* out);
+                        const hm_precision* prec, const hm_upload_opts* opts, hm_stats* out);
 
 /* ------------------------------------------------------------- products */
 
@@ -226,7 +270,9 @@ hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double* y, uint32_
  * float64 throughout for float64 data and for matrices that accumulate in
  * float64).  Each matrix keeps a workspace sized for the widest block seen;
  * growing it synchronises the device and allocates, so the first call at a
- * new width must not be inside a graph capture.  Enqueued on `stream`;
+ * new width must not be inside a graph capture, and it invalidates every
+ * graph captured earlier from a product of that matrix (hm_graph_launch
+ * then refuses them).  Enqueued on `stream`;
  * calls on one matrix must not overlap in time.
  * Errors: HM_EINVAL (arguments), HM_ENOMEM (workspace), HM_EDEVICE. */
 #define HM_MAX_NRHS 1024
@@ -243,7 +289,8 @@ hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double alpha, const
  * faster per stage, times that combination, and keeps the fastest chunk
  * size for this matrix.  It allocates,
  * synchronises and rebuilds the plan: call it outside graph capture, before
- * creating graphs of the matrix.  Results of later products may differ from
+ * creating graphs of the matrix (graphs of its many-RHS products captured
+ * earlier are invalidated, as when the workspace grows).  Results of later products may differ from
  * earlier ones in rounding (a different summation order), within the
  * accumulation tolerance. */
 typedef struct {
@@ -291,6 +338,10 @@ hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x, double* y
 hm_status hm_graph_create_batch(hm_matrix* const* mats, int32_t nmat, double alpha, const void* const* X,
                                 const int64_t* ldx, const int32_t* nrhs, void* const* Y, const int64_t* ldy,
                                 int32_t vec_dtype, uint32_t flags, hm_stream_t stream, hm_graph** out);
+/* Replays a graph.  Graphs hold device addresses of the matrices' buffers:
+ * a graph whose matrices have since replaced a many-RHS workspace or plan
+ * (a wider hm_mvm_batch, hm_tune_batch) is refused with HM_EINVAL before
+ * anything is launched; capture it again. */
 hm_status hm_graph_launch(hm_graph* g, hm_stream_t stream);
 void hm_graph_free(hm_graph* g);
 
@@ -345,7 +396,7 @@ typedef struct {
     int64_t mem_budget;     /* device bytes for request blocks (and pinned host staging) */
     int32_t max_slots;      /* requests in flight at most (> 0) */
     int32_t max_queue;      /* queued requests at most; submit returns HM_EBUSY beyond */
-    int32_t max_cols;       /* columns per matrix and launch group at most (a wider request runs alone) */
+    int32_t max_cols;       /* columns per matrix and launch group at most, and the widest request */
     int32_t fake;           /* 1 = no device work (see above) */
     int32_t fake_us;        /* duration of a fake launch group */
 } hm_serve_opts;
@@ -369,15 +420,16 @@ typedef struct {
 typedef struct hm_server hm_server;
 hm_status hm_serve_create(const hm_serve_opts* opts, hm_server** out);
 /* Register a resident matrix (its many-RHS workspace is sized for max_cols
- * here); *matrix_id identifies it in hm_serve_submit. */
+ * here, so serving never allocates); *matrix_id identifies it in
+ * hm_serve_submit. */
 hm_status hm_serve_register(hm_server* s, hm_matrix* m, int32_t* matrix_id);
 /* Register a placeholder of n rows for a fake server (no matrix). */
 hm_status hm_serve_register_shape(hm_server* s, int64_t n, int32_t* matrix_id);
 /* Y_host := alpha * M * X_host.  X_host, Y_host: host float64 arrays of
  * n x nrhs values, column-major (leading dimension n), caller-owned and
  * valid until hm_serve_poll reports the ticket done; nrhs in
- * [1, HM_MAX_NRHS].  Non-blocking; HM_EBUSY when max_queue requests wait,
- * HM_ENOMEM when the request could never fit mem_budget. */
+ * [1, max_cols] (wider: HM_EINVAL).  Non-blocking; HM_EBUSY when max_queue
+ * requests wait, HM_ENOMEM when the request could never fit mem_budget. */
 hm_status hm_serve_submit(hm_server* s, int32_t matrix_id, double alpha, const double* X_host, int32_t nrhs,
                           double* Y_host, uint64_t* ticket);
 /* Non-blocking.  *done = 1 once Y_host holds the result (the ticket is then

@@ -12,8 +12,11 @@ permuted to cluster order (perm[i] = original index of cluster position i).
 
 * H (Sec. 3.1): dense leaf y|t += a D x|s, low-rank leaf
   y|t += a U (V^T x|s) with U = W diag(sigma), V = X.  Three evaluation
-  orders are provided: block order (Alg. 1), root-to-leaf block-row order
-  (Alg. 3) and expansion to a dense matrix (small n only).
+  orders are provided: block order (eq. 4 summed block by block), leaf-row
+  order (each output row cluster rho sums the rows of rho of every block
+  whose row cluster contains it; the leaves of the cluster tree partition
+  the rows, so every row is summed exactly once) and expansion to a dense
+  matrix (small n only).
 * UH (Sec. 3.2): forward transformation s_s = X_s^T x|s for every column
   cluster (Alg. 4), coupling sums t_t = sum S_ts s_s over the low-rank blocks
   of each block row (eq. 5), backward transformation y|t += a W_t t_t and the
@@ -47,6 +50,10 @@ def _seg(st: Structure, v: int):
     return slice(int(st.begin[v]), int(st.end[v]))
 
 
+def _leaves(st: Structure):
+    return [v for v in range(st.nnodes) if st.is_leaf(v)]
+
+
 # ----------------------------------------------------------------------------- H
 
 def h_mvm(st: Structure, dense, W, sigma, X, alpha: float, x: np.ndarray, y: np.ndarray,
@@ -65,17 +72,24 @@ def h_mvm(st: Structure, dense, W, sigma, X, alpha: float, x: np.ndarray, y: np.
         else:
             yc[_seg(st, t)] += alpha * (dense[b] @ xc[_seg(st, s)])
 
-    if order == "block":                      # Alg. 1
+    if order == "block":                      # eq. 4, one block after the other
         for b in range(st.nblocks):
             apply(b)
-    elif order == "tree":                     # Alg. 3: block row of t, then its sons
-        rows = st.row_blocks(None)
-        stack = [0]
-        while stack:
-            t = stack.pop()
-            for b in rows.get(t, []):
-                apply(b)
-            stack.extend(reversed(st.sons(t)))
+    elif order == "rows":                     # per leaf row cluster rho
+        for rho in _leaves(st):
+            r0, r1 = int(st.begin[rho]), int(st.end[rho])
+            acc = np.zeros(r1 - r0)
+            for b in range(st.nblocks):
+                t, s = int(st.blk_tau[b]), int(st.blk_sigma[b])
+                if not (st.begin[t] <= r0 and r1 <= st.end[t]):
+                    continue
+                rows = slice(r0 - int(st.begin[t]), r1 - int(st.begin[t]))
+                if st.blk_adm[b]:
+                    if sigma[b] is not None and len(sigma[b]):
+                        acc += W[b][rows] @ (sigma[b] * (X[b].T @ xc[_seg(st, s)]))
+                else:
+                    acc += dense[b][rows] @ xc[_seg(st, s)]
+            yc[r0:r1] += alpha * acc
     elif order == "dense":
         M = h_to_dense(st, dense, W, sigma, X)
         yc += alpha * (M @ xc)
@@ -119,18 +133,25 @@ def uh_mvm(st: Structure, dense, row_basis, col_basis, coupling, alpha: float,
         for b in range(st.nblocks):
             if not st.blk_adm[b]:
                 yc[_seg(st, int(st.blk_tau[b]))] += alpha * (dense[b] @ xc[_seg(st, int(st.blk_sigma[b]))])
-    elif order == "tree":                           # Alg. 5, root to leaves
-        stack = [0]
-        while stack:
-            t = stack.pop()
-            tt = np.zeros(row_basis[t].shape[1])
-            for b in rows_lr.get(t, []):
-                tt += coupling[b] @ s[int(st.blk_sigma[b])]
-            yp = row_basis[t] @ tt
-            for b in rows_d.get(t, []):
-                yp = yp + dense[b] @ xc[_seg(st, int(st.blk_sigma[b]))]
-            yc[_seg(st, t)] += alpha * yp
-            stack.extend(reversed(st.sons(t)))
+    elif order == "rows":                           # per leaf row cluster rho
+        # t_tau by eq. 5 for every row cluster, then y|rho sums, over every
+        # tau containing rho, the rows of rho of W_tau t_tau and of the dense
+        # blocks of tau's block row
+        tt = [np.zeros(row_basis[t].shape[1]) for t in range(st.nnodes)]
+        for b in range(st.nblocks):
+            if st.blk_adm[b]:
+                tt[int(st.blk_tau[b])] += coupling[b] @ s[int(st.blk_sigma[b])]
+        for rho in _leaves(st):
+            r0, r1 = int(st.begin[rho]), int(st.end[rho])
+            acc = np.zeros(r1 - r0)
+            for t in range(st.nnodes):
+                if not (st.begin[t] <= r0 and r1 <= st.end[t]):
+                    continue
+                rows = slice(r0 - int(st.begin[t]), r1 - int(st.begin[t]))
+                acc += row_basis[t][rows] @ tt[t]
+                for b in rows_d.get(t, []):
+                    acc += dense[b][rows] @ xc[_seg(st, int(st.blk_sigma[b]))]
+            yc[r0:r1] += alpha * acc
     else:
         raise ValueError(order)
     return _from_cluster(st, yc)

@@ -53,32 +53,11 @@ def valr_column_format(w: np.ndarray, delta: float) -> int:
 
 
 def valr_factor_formats(A, deltas) -> list:
-    """VALR formats of the columns of one factor (Sec. 4.2): each column's
-    cheapest format, then a format used by fewer columns than one 16-byte
-    tile holds (FP8 16, BF16/FP16 8, FP32 4) is promoted to the least precise
-    more precise format the factor already uses (precision order FP8, BF16,
-    FP16, FP32, FP64), if that format's tile count grows by at most the one
-    tile the short run frees.  Promotion only stores a column more
-    precisely; it avoids a nearly empty padded tile per short run."""
+    """VALR formats of the columns of one factor (Sec. 4.2): column j is
+    stored in the cheapest format whose error meets its own budget
+    deltas[j], independently of every other column."""
     A = np.asarray(A, dtype=np.float64)
-    f = [valr_column_format(A[:, j], deltas[j]) for j in range(A.shape[1])]
-    order = [quant.FP8, quant.BF16, quant.F16, quant.F32, quant.F64]
-
-    def tiles(c, d):
-        v = 16 // quant.BYTES[d]
-        return -(-c // v)
-    for a, d in enumerate(order[:-1]):
-        c = f.count(d)
-        if c == 0 or c >= 16 // quant.BYTES[d]:
-            continue
-        for t in order[a + 1:]:
-            ct = f.count(t)
-            if ct == 0:
-                continue
-            if tiles(ct + c, t) <= tiles(ct, t) + 1:
-                f = [t if x == d else x for x in f]
-            break
-    return f
+    return [valr_column_format(A[:, j], deltas[j]) for j in range(A.shape[1])]
 
 
 def _norm2(s) -> float:

@@ -58,6 +58,16 @@ class Layout:
                     blk_tau=arr(v.blk_tau, B, np.int64), blk_sigma=arr(v.blk_sigma, B, np.int64),
                     blk_adm=arr(v.blk_adm, B, np.int64).astype(bool))
 
+    def stats(self) -> dict:
+        """Partition statistics per level (hm_layout_stats); no values needed."""
+        s = _lib.LayoutInfo()
+        _lib.check(_lib.lib().hm_layout_stats(self._h, ctypes.byref(s)))
+        out = {}
+        for k, _ in _lib.LayoutInfo._fields_:
+            v = getattr(s, k)
+            out[k] = list(v)[: s.depth + 1] if k.endswith("_per_level") else v
+        return out
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value and _lib is not None and _lib._lib is not None:
@@ -134,6 +144,13 @@ def make_precision(eps=0.0, dense="f64", diag=None, factor="f64", coupling=None,
                           DTYPES[coupling or factor], accum)
 
 
+def make_opts(task_bytes: int = 0, spread_dense: bool = False, dense_grid: int = 0, fork_after: int = 0,
+              valr_promote: bool = False):
+    """hm_upload_opts (all zero = the library's defaults)."""
+    return _lib.UploadOpts(int(task_bytes), int(bool(spread_dense)), int(dense_grid), int(fork_after),
+                           int(bool(valr_promote)))
+
+
 def _stats_dict(s) -> dict:
     out = {k: getattr(s, k) for k, _ in _lib.Stats._fields_}
     out["bytes_per_dtype"] = list(s.bytes_per_dtype)
@@ -142,14 +159,16 @@ def _stats_dict(s) -> dict:
 
 
 def plan_stats(layout: "Layout", fmt: str, values, eps: float = 0.0, dense="f64", diag=None,
-               factor="f64", coupling=None, accum: int = HM_ACC_AUTO) -> dict:
+               factor="f64", coupling=None, accum: int = HM_ACC_AUTO, **opts) -> dict:
     """Storage statistics hm_upload would produce, computed on the host
-    only (hm_plan_stats): no device memory is touched."""
+    only (hm_plan_stats): no device memory is touched.  `opts` are the
+    hm_upload_opts fields (see make_opts)."""
     v, tabs = marshal_values(fmt, values)
     prec = make_precision(eps, dense, diag, factor, coupling, accum)
+    o = make_opts(**opts)
     s = _lib.Stats()
     _lib.check(_lib.lib().hm_plan_stats(layout.handle, FORMATS[fmt], ctypes.byref(v), ctypes.byref(prec),
-                                        ctypes.byref(s)))
+                                        ctypes.byref(o), ctypes.byref(s)))
     del tabs
     return _stats_dict(s)
 
@@ -163,18 +182,20 @@ class Matrix:
       h2: dense, row_rank, col_rank, row_leaf_basis, row_transfer,
           col_leaf_basis, col_transfer, coupling
     and for VALR storage ("valr") of UH/H2 bases also row_sv, col_sv.
+    Keyword `opts` are the engine options of hm_upload_opts (make_opts).
     """
 
     def __init__(self, layout: Layout, fmt: str, values, eps: float = 0.0, dense="f64", diag=None,
-                 factor="f64", coupling=None, accum: int = HM_ACC_AUTO, stream=None):
+                 factor="f64", coupling=None, accum: int = HM_ACC_AUTO, stream=None, **opts):
         L = _lib.lib()
         self.layout = layout
         self.fmt = fmt
         f = FORMATS[fmt]
         v, tabs = marshal_values(fmt, values)
         prec = make_precision(eps, dense, diag, factor, coupling, accum)
+        o = make_opts(**opts)
         h = ctypes.c_void_p()
-        _lib.check(L.hm_upload(layout.handle, f, ctypes.byref(v), ctypes.byref(prec),
+        _lib.check(L.hm_upload(layout.handle, f, ctypes.byref(v), ctypes.byref(prec), ctypes.byref(o),
                                _stream_ptr(stream), ctypes.byref(h)))
         self._h = h
 

@@ -33,6 +33,24 @@ class LayoutView(ctypes.Structure):
                 ("blk_adm", P(c_int32))]
 
 
+HM_MAX_LEVELS = 64
+
+
+class LayoutInfo(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("nnodes", c_int64), ("nleaves", c_int64), ("nblocks", c_int64),
+                ("ndense", c_int64), ("nlowrank", c_int64), ("ndiag", c_int64), ("depth", c_int32),
+                ("min_leaf", c_int32), ("max_leaf", c_int32), ("dense_area", c_double),
+                ("lowrank_area", c_double), ("nodes_per_level", c_int64 * HM_MAX_LEVELS),
+                ("dense_per_level", c_int64 * HM_MAX_LEVELS), ("lowrank_per_level", c_int64 * HM_MAX_LEVELS),
+                ("dense_area_per_level", c_double * HM_MAX_LEVELS),
+                ("lowrank_area_per_level", c_double * HM_MAX_LEVELS)]
+
+
+class UploadOpts(ctypes.Structure):
+    _fields_ = [("task_bytes", c_int64), ("spread_dense", c_int32), ("dense_grid", c_int32),
+                ("fork_after", c_int32), ("valr_promote", c_int32)]
+
+
 class Values(ctypes.Structure):
     _fields_ = [("dense", c_void_p), ("rank", c_void_p), ("W", c_void_p), ("sigma", c_void_p),
                 ("X", c_void_p), ("row_rank", c_void_p), ("col_rank", c_void_p),
@@ -92,10 +110,11 @@ SIGNATURES = {
     "hm_build_layout": (c_int32, [P(c_double), c_int64, P(LayoutOpts), P(c_void_p)]),
     "hm_layout_export": (c_int32, [c_void_p, P(LayoutView)]),
     "hm_layout_free": (None, [c_void_p]),
-    "hm_upload": (c_int32, [c_void_p, c_int32, P(Values), P(Precision), c_void_p, P(c_void_p)]),
+    "hm_layout_stats": (c_int32, [c_void_p, P(LayoutInfo)]),
+    "hm_upload": (c_int32, [c_void_p, c_int32, P(Values), P(Precision), P(UploadOpts), c_void_p, P(c_void_p)]),
     "hm_matrix_free": (None, [c_void_p]),
     "hm_matrix_stats": (c_int32, [c_void_p, P(Stats)]),
-    "hm_plan_stats": (c_int32, [c_void_p, c_int32, P(Values), P(Precision), P(Stats)]),
+    "hm_plan_stats": (c_int32, [c_void_p, c_int32, P(Values), P(Precision), P(UploadOpts), P(Stats)]),
     "hm_mvm": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p]),
     "hm_mvm_batch": (c_int32, [P(c_void_p), c_int32, c_double, P(c_void_p), P(c_int64), P(c_int32),
                                P(c_void_p), P(c_int64), c_int32, c_uint32, c_void_p]),

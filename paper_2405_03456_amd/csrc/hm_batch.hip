@@ -621,6 +621,7 @@ static hm_status ensure_mr_plan(hm_matrix* m, int64_t target) {
         m->mr_phases.push_back(ds);
     }
     m->mr_meta = d;
+    m->mr_gen++;
     m->mr_tasks = (const DTask*)(b + o_tasks);
     m->mr_iperm = (const int64_t*)(b + o_iperm);
     m->mr_owners = (const DOwner*)(b + o_owners);
@@ -667,6 +668,7 @@ static hm_status ensure_mr(hm_matrix* m, int R) {
     }
     uint8_t* b = (uint8_t*)p;
     m->mr_arena = p;
+    m->mr_gen++;
     m->mr_cap = R;
     m->wsm = (double*)(b + o_wsm);
     m->wsm32 = (float*)(b + o_wsm32);

@@ -156,6 +156,9 @@ struct hm_matrix {
     // of ws / ws32 / part, entry-major (value j of entry i at i * R + j)
     void* mr_arena = nullptr;
     int32_t mr_cap = 0;
+    // bumped whenever mr_meta or mr_arena is replaced: graphs captured from
+    // many-RHS products record it and are refused once it moved on
+    uint64_t mr_gen = 0;
     double* wsm = nullptr;
     float* wsm32 = nullptr;
     double* ym = nullptr;      // y contributions in cluster order

@@ -4,7 +4,10 @@
 // diameter/distance predicates are evaluated as written (one rounding per
 // operation, sums over x, y, z in that order), so a layout is a
 // deterministic function of the points.
+#include <algorithm>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 
@@ -218,3 +221,45 @@ extern "C" hm_status hm_layout_export(const hm_layout* layout, hm_layout_view* v
 }
 
 extern "C" void hm_layout_free(hm_layout* layout) { delete layout; }
+
+extern "C" hm_status hm_layout_stats(const hm_layout* layout, hm_layout_info* info) {
+    if (!layout || !info) {
+        hm::set_error("hm_layout_stats: null argument");
+        return HM_EINVAL;
+    }
+    const hm::Layout& L = layout->L;
+    *info = hm_layout_info{};
+    auto lv = [](int32_t l) { return l < HM_MAX_LEVELS - 1 ? l : HM_MAX_LEVELS - 1; };
+    info->n = L.n;
+    info->nnodes = (int64_t)L.node_begin.size();
+    info->nblocks = (int64_t)L.blk_tau.size();
+    info->depth = L.depth;
+    info->min_leaf = INT32_MAX;
+    for (int32_t v = 0; v < (int32_t)info->nnodes; ++v) {
+        info->nodes_per_level[lv(L.node_level[v])]++;
+        if (L.leaf(v)) {
+            info->nleaves++;
+            info->min_leaf = std::min<int32_t>(info->min_leaf, (int32_t)L.size(v));
+            info->max_leaf = std::max<int32_t>(info->max_leaf, (int32_t)L.size(v));
+        }
+    }
+    if (info->nleaves == 0) info->min_leaf = 0;
+    for (size_t b = 0; b < L.blk_tau.size(); ++b) {
+        const int32_t t = L.blk_tau[b], s = L.blk_sigma[b];
+        const double area = (double)L.size(t) * (double)L.size(s);
+        const int32_t l = lv(L.node_level[t]);
+        if (L.blk_adm[b]) {
+            info->nlowrank++;
+            info->lowrank_per_level[l]++;
+            info->lowrank_area += area;
+            info->lowrank_area_per_level[l] += area;
+        } else {
+            info->ndense++;
+            info->ndiag += t == s;
+            info->dense_per_level[l]++;
+            info->dense_area += area;
+            info->dense_area_per_level[l] += area;
+        }
+    }
+    return HM_OK;
+}

@@ -91,15 +91,18 @@ int32_t valr_choose(const double* col, int64_t m, double delta) {
 }
 
 // VALR formats of the k columns of one factor: each column's cheapest format
-// (valr_choose), then a format used by fewer columns than one 16-byte tile
-// holds is promoted to the least precise more precise format the factor
-// already uses, provided that costs that format at most the one tile the
-// short run frees.  A column is only ever stored more precisely than its
+// (valr_choose, Sec. 4.2).  With `promote` (a storage choice of this
+// library, off by default), a format used by fewer columns than one 16-byte
+// tile holds is then promoted to the least precise more precise format the
+// factor already uses, provided that costs that format at most the one tile
+// the short run frees.  A promoted column is stored more precisely than its
 // budget needs; short runs of cheap columns would otherwise cost a nearly
 // empty padded tile and a separate item each.
-std::vector<int32_t> valr_formats(const double* A, int64_t m, int64_t k, const std::vector<double>& deltas) {
+std::vector<int32_t> valr_formats(const double* A, int64_t m, int64_t k, const std::vector<double>& deltas,
+                                  bool promote) {
     std::vector<int32_t> dts((size_t)k);
     for (int64_t j = 0; j < k; ++j) dts[(size_t)j] = valr_choose(A + j * m, m, deltas[(size_t)j]);
+    if (!promote) return dts;
     static const int32_t order[5] = {HM_FP8E4M3, HM_BF16, HM_F16, HM_F32, HM_F64};   // precision, ascending
     int64_t cnt[5] = {0, 0, 0, 0, 0};
     for (int32_t d : dts) cnt[d]++;
@@ -185,7 +188,7 @@ struct Builder {
         std::vector<Run> runs;
         if (k == 0) return runs;
         std::vector<int32_t> dts(k, factor_dt);
-        if (factor_dt == HM_VALR_AUTO) dts = dts_in ? *dts_in : valr_formats(A, m, k, deltas);
+        if (factor_dt == HM_VALR_AUTO) dts = dts_in ? *dts_in : valr_formats(A, m, k, deltas, opt.valr_promote);
         int64_t j0 = 0;
         for (int64_t j = 1; j <= k; ++j)
             if (j == k || dts[j] != dts[j0] || (brk && (*brk)[(size_t)j])) {
@@ -527,7 +530,7 @@ struct Builder {
         perm.clear();
         if (factor_dt != HM_VALR_AUTO || k == 0) return basis_factor(A, m, k, sv, v);
         std::vector<double> d = deltas_for(sv[v], k, eps * norm2(sv[v], k) / (double)k);
-        const std::vector<int32_t> dts = valr_formats(A, m, k, d);
+        const std::vector<int32_t> dts = valr_formats(A, m, k, d, opt.valr_promote);
         std::vector<int32_t> order((size_t)k);
         for (int64_t j = 0; j < k; ++j) order[(size_t)j] = (int32_t)j;
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return dts[a] < dts[b]; });
@@ -618,7 +621,7 @@ struct Builder {
                 for (int32_t b : col_lr[s]) {
                     const int32_t k = V->rank[b];
                     std::vector<double> d(Ds.begin() + o0, Ds.begin() + o0 + k);
-                    const std::vector<int32_t> f = valr_formats(Xs.data() + o0 * ms, ms, k, d);
+                    const std::vector<int32_t> f = valr_formats(Xs.data() + o0 * ms, ms, k, d, opt.valr_promote);
                     std::copy(f.begin(), f.end(), dtx.begin() + o0);
                     o0 += k;
                 }
@@ -1416,16 +1419,37 @@ void build_mr_plan(const std::vector<DOwner>& owners, const std::vector<DItem>& 
 
 }  // namespace hm
 
+namespace hm {
+
+hm_status pack_options(const hm_upload_opts* o, PackOptions& opt) {
+    opt = PackOptions{};
+    if (!o) return HM_OK;
+    if (o->task_bytes != 0 && o->task_bytes < 1024) {
+        set_error("hm_upload: task_bytes must be 0 (default) or at least 1024");
+        return HM_EINVAL;
+    }
+    if (o->dense_grid < 0 || o->fork_after < 0 || (o->spread_dense & ~1) || (o->valr_promote & ~1)) {
+        set_error("hm_upload: negative dense_grid / fork_after, or a flag other than 0 / 1");
+        return HM_EINVAL;
+    }
+    if (o->task_bytes) opt.task_bytes = o->task_bytes;
+    opt.concurrent_dense = o->spread_dense == 0;
+    opt.valr_promote = o->valr_promote != 0;
+    return HM_OK;
+}
+
+}  // namespace hm
+
 extern "C" hm_status hm_plan_stats(const hm_layout* layout, int32_t format, const hm_values* values,
-                                   const hm_precision* prec, hm_stats* out) {
+                                   const hm_precision* prec, const hm_upload_opts* opts, hm_stats* out) {
     if (!layout || !values || !prec || !out) {
         hm::set_error("hm_plan_stats: null argument");
         return HM_EINVAL;
     }
     hm::Packed P;
     hm::PackOptions opt;
-    if (const char* e = std::getenv("HM_TASK_BYTES")) opt.task_bytes = std::max(1024L, std::atol(e));
-    hm_status st;
+    hm_status st = hm::pack_options(opts, opt);
+    if (st != HM_OK) return st;
     try {
         st = hm::pack(layout->L, format, values, prec, opt, P);
     } catch (const std::bad_alloc&) {

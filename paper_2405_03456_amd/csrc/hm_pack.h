@@ -9,7 +9,11 @@ namespace hm {
 struct PackOptions {
     int64_t task_bytes = 32768;   // target matrix bytes per task (one wavefront)
     bool concurrent_dense = true; // dense leaves as one independent stage (else spread over the stages)
+    bool valr_promote = false;    // VALR: fill the 16-byte tiles of short format runs (see valr_formats)
 };
+
+// Validated PackOptions from the ABI's hm_upload_opts (NULL = defaults).
+hm_status pack_options(const hm_upload_opts* o, PackOptions& opt);
 
 struct Packed {
     int32_t format = 0;

@@ -437,7 +437,8 @@ extern "C" const char* hm_last_error(void) { return hm::g_err.c_str(); }
 extern "C" const char* hm_version(void) { return "hm 0.1 gfx950"; }
 
 extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm_values* values,
-                               const hm_precision* prec, hm_stream_t stream, hm_matrix** out) {
+                               const hm_precision* prec, const hm_upload_opts* opts, hm_stream_t stream,
+                               hm_matrix** out) {
     (void)stream;
     if (!layout || !values || !prec || !out) {
         hm::set_error("hm_upload: null argument");
@@ -446,9 +447,8 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     *out = nullptr;
     hm::Packed P;
     hm::PackOptions opt;
-    if (const char* e = std::getenv("HM_TASK_BYTES")) opt.task_bytes = std::max(1024L, std::atol(e));
-    if (const char* e = std::getenv("HM_CONCURRENT_DENSE")) opt.concurrent_dense = std::atoi(e) != 0;
-    hm_status st;
+    hm_status st = hm::pack_options(opts, opt);
+    if (st != HM_OK) return st;
     try {
         st = hm::pack(layout->L, format, values, prec, opt, P);
     } catch (const std::bad_alloc&) {
@@ -575,8 +575,10 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         }
     }
     m->stats = P.stats;
-    if (const char* e = std::getenv("HM_DENSE_GRID")) m->aux_grid = std::max(0, std::atoi(e));
-    if (const char* e = std::getenv("HM_FORK_AFTER")) m->fork_after = std::max(0, std::atoi(e));
+    if (opts) {
+        m->aux_grid = opts->dense_grid;
+        m->fork_after = opts->fork_after;
+    }
     m->h_owners = P.owners;
     m->h_items = P.items;
     m->h_tasks = P.tasks;
@@ -750,6 +752,8 @@ extern "C" hm_status hm_timing_read(hm_matrix* m, hm_phase_timing* out, int32_t 
 struct hm_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // many-RHS buffers the recorded kernels address: (matrix, mr_gen at capture)
+    std::vector<std::pair<const hm_matrix*, uint64_t>> deps;
 };
 
 // Record whatever `enqueue` puts on a private capturing stream (ordered after
@@ -887,9 +891,13 @@ extern "C" hm_status hm_graph_create_batch(hm_matrix* const* mats, int32_t nmat,
     // workspaces are sized (allocated) before the capture starts
     hm_status st = hm::batch_prepare(mats, nmat, nrhs, vec_dtype);
     if (st != HM_OK) return st;
-    return capture_graph("hm_graph_create_batch", stream_, out, [&](hm_stream_t s) {
+    st = capture_graph("hm_graph_create_batch", stream_, out, [&](hm_stream_t s) {
         return hm_mvm_batch(mats, nmat, alpha, X, ldx, nrhs, Y, ldy, vec_dtype, flags, s);
     });
+    if (st == HM_OK)
+        for (int32_t i = 0; i < nmat; ++i)
+            if (nrhs[i] > 0) (*out)->deps.emplace_back(mats[i], mats[i]->mr_gen);
+    return st;
 }
 
 extern "C" hm_status hm_graph_launch(hm_graph* g, hm_stream_t stream) {
@@ -897,6 +905,12 @@ extern "C" hm_status hm_graph_launch(hm_graph* g, hm_stream_t stream) {
         hm::set_error("hm_graph_launch: null graph");
         return HM_EINVAL;
     }
+    for (auto& d : g->deps)
+        if (d.first->mr_gen != d.second) {
+            hm::set_error("hm_graph_launch: a matrix of this graph replaced its many-RHS workspace or plan "
+                          "after the capture (wider product or hm_tune_batch); capture the graph again");
+            return HM_EINVAL;
+        }
     hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail("hm_graph_launch", e);
     return HM_OK;

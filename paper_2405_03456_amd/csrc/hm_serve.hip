@@ -549,6 +549,10 @@ extern "C" hm_status hm_serve_submit(hm_server* S, int32_t mid, double alpha, co
         hm::set_error("hm_serve_submit: unknown matrix id");
         return HM_EINVAL;
     }
+    if (nrhs > S->opts.max_cols) {
+        hm::set_error("hm_serve_submit: nrhs exceeds the server's max_cols (its workspaces are sized for that)");
+        return HM_EINVAL;
+    }
     if (hm::block_bytes(S->mats[mid].n, nrhs) > S->opts.mem_budget) {
         hm::set_error("hm_serve_submit: request larger than the memory budget");
         return HM_ENOMEM;

@@ -149,7 +149,7 @@ def to_uh(h: HValues, st: Structure, eps: float | None = None) -> UHValues:
     cols_lr = st.col_blocks(True)
     for side, groups, fac, basis, svs in (("row", rows_lr, h.W, row_basis, row_sv),
                                           ("col", cols_lr, h.X, col_basis, col_sv)):
-        for v in range(N):
+        def one(v, groups=groups, fac=fac, basis=basis, svs=svs):
             parts = []
             for b in groups.get(v, []):
                 s = h.sigma[b]
@@ -164,6 +164,7 @@ def to_uh(h: HValues, st: Structure, eps: float | None = None) -> UHValues:
             else:
                 basis[v] = np.zeros((st.size(v), 0), order="F")
                 svs[v] = np.zeros(0)
+        _levels(st, one, root_first=True)     # every node is independent
     coupling = [None] * st.nblocks
     for b in np.nonzero(st.blk_adm)[0]:
         t, s = int(st.blk_tau[b]), int(st.blk_sigma[b])
@@ -176,14 +177,29 @@ def to_uh(h: HValues, st: Structure, eps: float | None = None) -> UHValues:
     return UHValues(h.kernel, eps, list(h.dense), row_basis, row_sv, col_basis, col_sv, coupling)
 
 
+def _levels(st: Structure, fn, root_first: bool) -> None:
+    """fn(v) for every node, one tree level after the other (root first or
+    leaves first); the nodes of one level are independent and run on a
+    thread pool (LAPACK releases the GIL), with one BLAS thread each."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    lv = np.asarray(st.level)
+    levels = range(int(lv.max()) + 1) if root_first else range(int(lv.max()), -1, -1)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with threadpool_limits(limits=1), ThreadPoolExecutor(max_workers=workers) as ex:
+        for lev in levels:
+            nodes = [int(v) for v in np.nonzero(lv == lev)[0]]
+            list(ex.map(fn, nodes))
+
+
 def _nested_side(st: Structure, groups: dict, fac: list, sigma: list, eps: float, cond_eps: float):
     """Nested basis for one side.  Returns explicit bases per node (for the
     couplings), ranks, leaf bases, transfers and leaf singular values."""
     N = st.nnodes
-    order = np.argsort(st.level, kind="stable")      # root first
     cond = [None] * N
-    for v in order:
-        v = int(v)
+
+    def condense(v):
         parts = []
         for b in groups.get(v, []):
             s = sigma[b]
@@ -200,13 +216,14 @@ def _nested_side(st: Structure, groups: dict, fac: list, sigma: list, eps: float
             cond[v] = U[:, :r] * sv[:r][None, :]
         else:
             cond[v] = np.zeros((st.size(v), 0))
+
     explicit = [None] * N
     rank = np.zeros(N, dtype=np.int64)
     leaf_basis = [None] * N
     transfer = [None] * N
     svals = [None] * N
-    for v in order[::-1]:
-        v = int(v)
+
+    def nest(v):
         if st.is_leaf(v):
             U, sv = _svd_left(cond[v])
             k = _trunc_rank(sv, eps)
@@ -231,8 +248,11 @@ def _nested_side(st: Structure, groups: dict, fac: list, sigma: list, eps: float
                                                        explicit[s1] @ transfer[s1]]))
             svals[v] = sv[:k].copy()
             rank[v] = k
-    root = int(order[0])
-    transfer[root] = None
+        cond[v] = None if not st.is_leaf(v) else cond[v]
+
+    _levels(st, condense, root_first=True)
+    _levels(st, nest, root_first=False)
+    transfer[0] = None
     return explicit, rank, leaf_basis, transfer, svals
 
 

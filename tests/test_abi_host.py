@@ -111,13 +111,19 @@ def test_valr_choices_match_oracle(eps):
         u = hm.plan_stats(lay, fmt, vals[fmt], eps=eps, dense="f32", diag="f32", factor="f32")
         assert u["entries_per_dtype"][1] == sum(u["entries_per_dtype"])
         assert sum(u["entries_per_dtype"]) == sum(s["entries_per_dtype"])
-        # stored bytes (tile padding included) never above FP32 with an FP64
-        # diagonal (equal when every factor fits one FP32 tile, k <= 4)
+        # with the library's tile promotion (valr_promote) a column only
+        # moves to a more precise format, and the stored bytes (tile padding
+        # included) stay at or below FP32 with an FP64 diagonal
+        sp = hm.plan_stats(lay, fmt, vals[fmt], eps=eps, dense="valr", diag="valr", factor="valr",
+                           valr_promote=True)
+        assert sum(sp["entries_per_dtype"]) == sum(s["entries_per_dtype"])
+        assert sp["entries_per_dtype"][_lib.HM_FP8E4M3] <= s["entries_per_dtype"][_lib.HM_FP8E4M3]
+        assert sp["entries_per_dtype"][_lib.HM_F64] >= s["entries_per_dtype"][_lib.HM_F64]
         if eps >= 1e-6:
             u64 = hm.plan_stats(lay, fmt, vals[fmt], eps=eps, dense="f32", diag="f64", factor="f32")
-            assert sum(s["bytes_per_dtype"]) <= sum(u64["bytes_per_dtype"]), fmt
+            assert sum(sp["bytes_per_dtype"]) <= sum(u64["bytes_per_dtype"]), fmt
             if eps == 1e-6:
-                assert sum(s["bytes_per_dtype"]) < sum(u64["bytes_per_dtype"]), fmt
+                assert sum(sp["bytes_per_dtype"]) < sum(u64["bytes_per_dtype"]), fmt
 
 
 def test_valr_errors():
@@ -135,7 +141,7 @@ def test_valr_errors():
     hm.plan_stats(lay, "uh", uh, eps=1e-6, factor="f32")  # not needed otherwise
 
 
-def test_plan_launch_counts(monkeypatch):
+def test_plan_launch_counts():
     """Host plan (hm_plan_stats): with the default task size every split
     coefficient owner of UH/H2 is summed by its consumers, so one product is
     the gather, one launch per task stage and the final y reduction; with
@@ -151,9 +157,58 @@ def test_plan_launch_counts(monkeypatch):
     uh_stages = 4   # forward, coupling, backward, dense
     counts = {}
     for tb in ("32768", "2000"):
-        monkeypatch.setenv("HM_TASK_BYTES", tb)
         for fmt, v in vals.items():
-            counts[(tb, fmt)] = hm.plan_stats(lay, fmt, v, eps=1e-8)["nlaunch"]
+            counts[(tb, fmt)] = hm.plan_stats(lay, fmt, v, eps=1e-8, task_bytes=int(tb))["nlaunch"]
     assert counts[("32768", "uh")] == 1 + uh_stages + 1
     for fmt in vals:
         assert counts[("2000", fmt)] > counts[("32768", fmt)], fmt
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (2048, 1001), (32768, 1002)])
+def test_layout_stats_match_the_oracle_partition(n, seed):
+    """hm_layout_stats (no values needed) against counts taken from the
+    oracle's own cluster and block trees; the leaf areas cover n*n exactly."""
+    p = sphere_points(n, seed)
+    st = trees.build_structure(p)
+    s = hm.Layout(p).stats()
+    sizes = (st.end - st.begin).astype(np.int64)
+    leaves = st.son0 < 0
+    assert s["n"] == n and s["nnodes"] == st.nnodes and s["nblocks"] == st.nblocks
+    assert s["depth"] == int(st.level.max()) and s["nleaves"] == int(leaves.sum())
+    assert s["min_leaf"] == int(sizes[leaves].min()) and s["max_leaf"] == int(sizes[leaves].max())
+    assert s["nodes_per_level"] == list(np.bincount(st.level, minlength=s["depth"] + 1))
+    adm = st.blk_adm.astype(bool)
+    area = sizes[st.blk_tau].astype(np.float64) * sizes[st.blk_sigma]
+    lev = st.level[st.blk_tau]
+    assert s["nlowrank"] == int(adm.sum()) and s["ndense"] == int((~adm).sum())
+    assert s["ndiag"] == int(((st.blk_tau == st.blk_sigma) & ~adm).sum())
+    for name, mask in (("dense", ~adm), ("lowrank", adm)):
+        assert s[f"{name}_per_level"] == list(np.bincount(lev[mask], minlength=s["depth"] + 1))
+        assert s[f"{name}_area"] == float(area[mask].sum())
+        assert np.allclose(s[f"{name}_area_per_level"],
+                           np.bincount(lev[mask], weights=area[mask], minlength=s["depth"] + 1), rtol=0, atol=0)
+    assert s["dense_area"] + s["lowrank_area"] == float(n) * n
+
+
+def test_upload_options_are_validated():
+    from synth import KERNEL_LAPLACE, compress_h
+    p = sphere_points(300, 5)
+    st = trees.build_structure(p)
+    lay = hm.Layout(p)
+    h = compress_h(p, KERNEL_LAPLACE, st, 1e-6, method="svd")
+    hm.plan_stats(lay, "h", h, eps=1e-6, task_bytes=1024)
+    for bad in (dict(task_bytes=100), dict(task_bytes=-5), dict(dense_grid=-1), dict(fork_after=-2)):
+        with pytest.raises(hm.HMError) as ex:
+            hm.plan_stats(lay, "h", h, eps=1e-6, **bad)
+        assert ex.value.status == _lib.HM_EINVAL, bad
+    o = hm.make_opts()
+    o.valr_promote = 2
+    v, keep = hm.marshal_values("h", h)
+    prec = hm.make_precision(1e-6)
+    s = _lib.Stats()
+    assert _lib.lib().hm_plan_stats(lay.handle, 0, ctypes.byref(v), ctypes.byref(prec), ctypes.byref(o),
+                                    ctypes.byref(s)) == _lib.HM_EINVAL
+    # NULL options are the defaults
+    assert _lib.lib().hm_plan_stats(lay.handle, 0, ctypes.byref(v), ctypes.byref(prec), None,
+                                    ctypes.byref(s)) == _lib.HM_OK
+    assert s.nlaunch == hm.plan_stats(lay, "h", h, eps=1e-6)["nlaunch"]

@@ -158,11 +158,10 @@ def test_tune_mvm_keeps_results_bitwise(fmt):
 
 @pytest.mark.parametrize("fmt", ["h", "uh", "h2"])
 @pytest.mark.parametrize("pol", ["f64", "valr6"])
-def test_parity_small_tasks(fmt, pol, monkeypatch):
+def test_parity_small_tasks(fmt, pol):
     """2000-byte tasks split coefficient owners into many tasks: stages whose
     owners exceed the deferral limit keep their reduction launch, the others
     are summed by their consumers; both against the oracle."""
-    monkeypatch.setenv("HM_TASK_BYTES", "2000")
     n = 2048
     p, st, lay, vals = make(n, 1e-8)
     pp = dict(POLICIES[pol])
@@ -170,6 +169,6 @@ def test_parity_small_tasks(fmt, pol, monkeypatch):
     sv = stored.stored_values(st, fmt, vals[fmt], dense=pp["dense"], diag=pp.get("diag"),
                               factor=pp["factor"], coupling=pp.get("coupling"), eps=pp["eps"])
     ref = stored.product(st, fmt, sv, 0.75, x, y)
-    out = run_gpu(lay, fmt, vals[fmt], x, y, 0.75, **pp)
+    out = run_gpu(lay, fmt, vals[fmt], x, y, 0.75, task_bytes=2000, **pp)
     tol = TOL64 if pol in ACC64 else TOL32
     assert rel(out, ref, y) <= tol

@@ -141,12 +141,12 @@ def test_three_orders_agree(kernel):
     p, st, h = setup(n, kernel, 1e-8, seed=1001)
     x, y = gaussian_vector(n, 2001), gaussian_vector(n, 3001)
     a = hm(st, h, 1.0, x, y, "block")
-    b = hm(st, h, 1.0, x, y, "tree")
+    b = hm(st, h, 1.0, x, y, "rows")
     c = hm(st, h, 1.0, x, y, "dense")
     assert rel(a, b, a - y) < 1e-13 and rel(a, c, a - y) < 1e-13
     u = to_uh(h, st)
     a = mvm.uh_mvm(st, u.dense, u.row_basis, u.col_basis, u.coupling, 1.0, x, y, "phases")
-    b = mvm.uh_mvm(st, u.dense, u.row_basis, u.col_basis, u.coupling, 1.0, x, y, "tree")
+    b = mvm.uh_mvm(st, u.dense, u.row_basis, u.col_basis, u.coupling, 1.0, x, y, "rows")
     c = mvm.uh_mvm(st, u.dense, u.row_basis, u.col_basis, u.coupling, 1.0, x, y, "dense")
     assert rel(a, b, a - y) < 1e-13 and rel(a, c, a - y) < 1e-13
 

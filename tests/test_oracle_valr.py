@@ -206,6 +206,11 @@ def test_valr_product_error_and_savings(fmt, eps):
     diag = sum(h.dense[b].size for b in range(st.nblocks)
                if h.dense[b] is not None and st.blk_tau[b] == st.blk_sigma[b])
     assert counts[quant.F64] >= diag                     # diagonal near field stays FP64
+    # Sec. 4.2/4.3: VALR stores fewer bytes than uniform FP32 storage with
+    # the same FP64 diagonal near field (counted on the stored entries)
+    stored_b = sum(int(counts[f]) * quant.BYTES[f] for f in range(5))
+    total = int(counts[:5].sum())
+    assert stored_b < 4 * (total - diag) + 8 * diag, (stored_b, total, diag)
     assert counts[:5].sum() == sum(a.size for a in vals.dense if a is not None) + sum(
         a.size for grp in ((vals.W, vals.X) if fmt == "h" else
                            (vals.row_basis, vals.col_basis, vals.coupling) if fmt == "uh" else
@@ -214,11 +219,11 @@ def test_valr_product_error_and_savings(fmt, eps):
         for a in grp if a is not None)
 
 
-def test_promotion_rule():
-    """Short runs of cheap formats join the next more precise format in the
-    factor when that costs no extra tile: 2 FP8 columns next to 5 FP16 ones
-    become FP16 (7 columns still fill one FP16 tile); FP16 columns next to a
-    full FP32 tile stay (they would add a second FP32 tile... and more)."""
+def test_factor_formats_are_per_column():
+    """Sec. 4.2 decides every column on its own budget: the format of a
+    column does not depend on its neighbours.  Two FP8-exact columns next to
+    five columns that need FP16 stay FP8, and the choice of every column of a
+    factor equals the choice for that column alone."""
     rng = np.random.default_rng(11)
     m = 40
     A = rng.standard_normal((m, 7))
@@ -226,16 +231,10 @@ def test_promotion_rule():
     base = np.column_stack([A[:, :5], exact8[:, 5:]])
     loose16 = [np.sqrt(err2(base[:, j], via_float16(base[:, j]))) * 1.0000001 for j in range(5)]
     deltas = loose16 + [0.0, 0.0]                         # FP16 for 0..4, FP8 (exact) for 5, 6
-    assert [stored.valr_column_format(base[:, j], deltas[j]) for j in range(7)] == [quant.F16] * 5 + [quant.FP8] * 2
-    assert stored.valr_factor_formats(base, deltas) == [quant.F16] * 7
-    # 16 FP8 columns fill a tile: no promotion
-    B = quant.stored(rng.standard_normal((m, 16)), quant.FP8)
-    C = np.column_stack([A[:, :1], B])
-    d = [0.0] + [0.0] * 16
-    f = stored.valr_factor_formats(C, d)
-    assert f.count(quant.FP8) == 16
-    # 3 FP32 columns next to 4 FP64 ones: FP64 would need 2 more tiles -> no promotion
-    g32 = A[:, :3].astype(np.float32).astype(np.float64)
-    D = np.column_stack([A[:, 3:7], g32])
-    f = stored.valr_factor_formats(D, [0.0] * 7)
-    assert f == [quant.F64] * 4 + [quant.F32] * 3
+    assert stored.valr_factor_formats(base, deltas) == [quant.F16] * 5 + [quant.FP8] * 2
+    B = rng.standard_normal((m, 12))
+    d = list(np.geomspace(1e-1, 1e-9, 12))
+    whole = stored.valr_factor_formats(B, d)
+    alone = [stored.valr_factor_formats(B[:, j:j + 1], [d[j]])[0] for j in range(12)]
+    assert whole == alone
+    assert len(set(whole)) >= 3                           # the budgets span several formats

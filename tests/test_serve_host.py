@@ -52,8 +52,15 @@ def test_memory_admission_respects_the_budget():
     s = S.stats()
     assert s["peak_arena_bytes"] <= budget
     assert s["completed"] == 18 and s["groups"] >= 6
-    with pytest.raises(hm.HMError) as ex:   # could never fit
-        S.submit(ids[0], np.ones((n, 13)))
+    with pytest.raises(hm.HMError) as ex:   # wider than max_cols: its workspace was never sized for it
+        S.submit(ids[0], np.ones((n, 5)))
+    assert ex.value.status == _lib.HM_EINVAL
+    S.close()
+    # a request within max_cols that could never fit the budget
+    S = hm.Server(mem_budget=block_bytes(n, 4), max_slots=4, max_queue=10, max_cols=16, fake=True, fake_us=10)
+    m = S.register_shape(n)
+    with pytest.raises(hm.HMError) as ex:
+        S.submit(m, np.ones((n, 13)))
     assert ex.value.status == _lib.HM_ENOMEM
     S.close()
 
