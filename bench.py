@@ -1,17 +1,28 @@
 """Benchmark: hierarchical-matrix product y += A x on one MI355X.
 
-Default workload: uniform-H matrix, n = 32768 points uniform on the unit
-sphere, Laplace kernel 1/(4 pi r) (zero diagonal), leaf size 64, eta = 2,
-eps = 1e-6, one right-hand side x ~ N(0,1); float64 storage ("plain FP64
-GPU") and uniform float32 storage.  A step is one full product (every phase
-of the format).  Several copies of each matrix are uploaded and used in turn
-so that the timed working set exceeds the 256 MB Infinity Cache: the
-numbers are HBM numbers, not cache numbers.
+Default workload: H^2 matrix, n = 262144 points uniform on the unit sphere,
+Laplace kernel 1/(4 pi r) (zero diagonal), leaf size 64, eta = 2, eps = 1e-6,
+nested bases with transfer matrices, one right-hand side x ~ N(0,1).  The
+headline (`value`) is the plain FP64 GPU product; beside it the storage
+ladder of compressed formats (FP32 / BF16 / FP8 factors, couplings and
+transfers with per-column scales, VALR per column, FP64 diagonal near
+field), one variant with the whole near field in FP64, and as extra keys the
+uniform-H n=32768 FP64 / FP32 product and the H n=2048 correctness case.
 
-Printed: one JSON line (rank 0) with the achieved algorithmic GB/s of the
-float64 product as `value`, matvecs/s, the float32-storage variant, a
-roofline object for the dominant kernel (HIP-event timed inside the timed
-region) and the oracle's CPU throughput on a bounded sample.
+A step is one full product (every phase of the format), replayed from a
+captured HIP graph.  Inputs are resident in HBM before timing; matrices
+smaller than the timed working set target are uploaded several times and
+used in turn, so the numbers are HBM numbers, not Infinity Cache numbers.
+Each replay is bracketed by HIP events: ms_per_step is the median, with
+p10/p90 beside it and the wall-clock mean of the same loop.  GB/s counts the
+method's bytes (every stored entry once at its element size, per-column
+scales of FP16/FP8 columns, x, y and the coefficient vectors); tile padding
+and plan metadata are reported separately as overhead.
+
+Printed: one JSON line with `value` = FP64 GB/s, matvecs/s, the compressed
+legs with their measured errors, a roofline object for the dominant kernel
+(HIP-event timed inside the timed region), and the CPU oracle (C/OpenMP,
+same product) timed on the host's cores.
 """
 from __future__ import annotations
 
@@ -32,23 +43,32 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     # name: (format, n, eps, point seed, x seed, description)
-    "uh32768": ("uh", 32768, 1e-6, 1002, 2002,
-                "UH-matrix n=32768 sphere points, Laplace 1/(4 pi r), leaf 64, eta 2, eps 1e-6, 1 RHS"),
     "h2_262144": ("h2", 262144, 1e-6, 1003, 2003,
                   "H2-matrix n=262144 sphere points, Laplace 1/(4 pi r), leaf 64, eta 2, eps 1e-6, 1 RHS"),
+    "uh32768": ("uh", 32768, 1e-6, 1002, 2002,
+                "UH-matrix n=32768 sphere points, Laplace 1/(4 pi r), leaf 64, eta 2, eps 1e-6, 1 RHS"),
     "h131072": ("h", 131072, 1e-6, 1004, 2004,
                 "H-matrix n=131072 sphere points, Laplace 1/(4 pi r), leaf 64, eta 2, eps 1e-6, 1 RHS"),
     "h2048": ("h", 2048, 1e-8, 1001, 2001,
               "H-matrix n=2048 sphere points, Laplace 1/(4 pi r), leaf 64, eta 2, eps 1e-8, 1 RHS"),
 }
 
+# storage policies of the single-vector legs
 POLICIES = {
-    "f64": dict(dense="f64", factor="f64", coupling="f64"),
-    "f32": dict(dense="f32", factor="f32", coupling="f32"),
-    # VALR at the workload's eps: per-column formats of the bases, direct
-    # formats of dense/coupling blocks, FP64 diagonal near field
+    "f64": dict(dense="f64", diag="f64", factor="f64", coupling="f64"),
+    # compressed: factors / bases, couplings and transfers in the named format;
+    # near-field dense leaves FP32 (direct compression at eps 1e-6, Table 1),
+    # diagonal near field FP64
+    "f32": dict(dense="f32", diag="f64", factor="f32", coupling="f32"),
+    "bf16": dict(dense="f32", diag="f64", factor="bf16", coupling="bf16"),
+    "fp8": dict(dense="f32", diag="f64", factor="fp8", coupling="fp8"),
     "valr": dict(dense="valr", diag="valr", factor="valr", coupling="valr"),
+    # the whole near field in FP64 (the Amdahl cap of compressing only the far field)
+    "fp8_nearfield_f64": dict(dense="f64", diag="f64", factor="fp8", coupling="fp8"),
+    # uniform FP32 storage of every block (the UH config's FP32 variant)
+    "f32_all": dict(dense="f32", diag="f32", factor="f32", coupling="f32"),
 }
+DEFAULT_LEGS = {"h2": "f64,f32,bf16,fp8,valr,fp8_nearfield_f64", "uh": "f64,f32_all,valr", "h": "f64,f32_all,valr"}
 
 
 def log(*a):
@@ -62,9 +82,9 @@ def structure_from_layout(lay):
                      e["son1"], e["blk_tau"], e["blk_sigma"], e["blk_adm"])
 
 
-def make_values(fmt, points, st, eps):
-    from synth import KERNEL_LAPLACE, compress_h, to_h2, to_uh
-    h = compress_h(points, KERNEL_LAPLACE, st, eps, method="auto")
+def make_values(fmt, points, st, eps, kernel=0):
+    from synth import compress_h, to_h2, to_uh
+    h = compress_h(points, kernel, st, eps, method="auto")
     if fmt == "h":
         return h
     if fmt == "uh":
@@ -72,10 +92,25 @@ def make_values(fmt, points, st, eps):
     return to_h2(h, st)
 
 
+def workload_inputs(hm, name):
+    """(layout, structure, values, points) of a workload, generated once per
+    machine (synth.cache)."""
+    from synth import cache, sphere_points
+    fmt, n, eps, pseed, _, _ = WORKLOADS[name]
+    points = sphere_points(n, pseed)
+    lay = hm.Layout(points)
+    st = structure_from_layout(lay)
+
+    def build():
+        return make_values(fmt, points, st, eps)
+    vals = cache.cached(("bench", name, fmt, n, eps, pseed), build)
+    return lay, st, vals, points
+
+
 def run_variant(hm, torch, lay, fmt, vals, eps, pol, steps, warmup, x, target):
-    """Upload rotating copies, time `steps` graph-replayed products (the
-    throughput), then `steps` eager products with per-stage HIP events (the
-    per-kernel roofline)."""
+    """Upload rotated copies, replay `steps` captured products with a HIP
+    event pair around each replay, then `steps` eager products with
+    per-stage HIP events (the per-kernel roofline)."""
     mats = [hm.Matrix(lay, fmt, vals, eps=eps, **pol)]
     s0 = mats[0].stats()
     stored = s0["bytes_dense"] + s0["bytes_factors"] + s0["bytes_coupling"] + s0["bytes_transfer"]
@@ -86,23 +121,26 @@ def run_variant(hm, torch, lay, fmt, vals, eps, pol, steps, warmup, x, target):
     tuned = [m.tune_mvm(reps=10) for m in mats]
     y = torch.zeros_like(x)
     graphs = [m.graph(x, y) for m in mats]
+    stream = torch.cuda.current_stream()
     for i in range(warmup):
-        graphs[i % ncopies].launch()
+        graphs[i % ncopies].launch(stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        graphs[i % ncopies].launch()
+        ev[i][0].record(stream)
+        graphs[i % ncopies].launch(stream)
+        ev[i][1].record(stream)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    wall = time.perf_counter() - t0
+    times = np.array([a.elapsed_time(b) for a, b in ev])      # ms per replay
     # eager products with per-stage event timing
     for m in mats:
         m.timing()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     for i in range(steps):
         mats[i % ncopies].mvm(x, y, timing=True)
     torch.cuda.synchronize()
-    dt_eager = time.perf_counter() - t1
     phases = []
     for m in mats:
         for i, ph in enumerate(m.timing()):
@@ -120,90 +158,144 @@ def run_variant(hm, torch, lay, fmt, vals, eps, pol, steps, warmup, x, target):
         g.free()
     for m in mats:
         m.free()
-    return dict(stats=s0, ncopies=ncopies, seconds=dt, seconds_eager=dt_eager, phases=phases, y=y_out,
+    return dict(stats=s0, ncopies=ncopies, times=times, wall=wall, phases=phases, y=y_out,
                 fork_after=[t["fork_after"] for t in tuned])
 
 
 def summarize(res, steps):
     s = res["stats"]
-    ms = res["seconds"] * 1e3 / steps
-    gbs = s["algorithmic_bytes"] / (ms * 1e-3) / 1e9
+    t = res["times"]
+    ms = float(np.median(t))
+    mb = float(s["method_bytes"])
+    gbs = mb / (ms * 1e-3) / 1e9
     with_tasks = [p for p in res["phases"] if p["ntasks"] > 0 and p["launches"] > 0]
     dom = max(with_tasks, key=lambda p: p["ms_total"]) if with_tasks else None
     roof = None
     if dom and dom["launches"]:
         avg_ms = dom["ms_total"] / dom["launches"]
-        ach = dom["algorithmic_bytes"] / (avg_ms * 1e-3) / 1e9
+        ach = dom["method_bytes"] / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": f"k_owner_tasks[{dom['name']}]", "avg_launch_us": round(avg_ms * 1e3, 2),
-                "bytes_per_launch": int(dom["algorithmic_bytes"])}
-    return dict(ms_per_step=ms, gbs=gbs, matvecs_per_s=1e3 / ms, roofline=roof,
-                eager_ms_per_step=res["seconds_eager"] * 1e3 / steps,
-                algorithmic_bytes=s["algorithmic_bytes"], copies=res["ncopies"], fork_after=res["fork_after"],
+                "bytes_per_launch": int(dom["method_bytes"]),
+                "bytes_per_launch_with_padding": int(dom["algorithmic_bytes"])}
+    return dict(ms_per_step=ms, p10_ms=float(np.percentile(t, 10)), p90_ms=float(np.percentile(t, 90)),
+                wall_ms_per_step=res["wall"] * 1e3 / steps, gbs=gbs, matvecs_per_s=1e3 / ms, roofline=roof,
+                method_bytes=mb, overhead_bytes=float(s["algorithmic_bytes"]) - mb,
+                copies=res["ncopies"], fork_after=res["fork_after"],
                 phases=[{"name": p["name"], "ntasks": p["ntasks"],
                          "us_avg": round(p["ms_total"] * 1e3 / max(p["launches"], 1), 2),
-                         "GBs": (round(p["algorithmic_bytes"] / (p["ms_total"] / p["launches"]) / 1e6, 1)
+                         "GBs": (round(p["method_bytes"] / (p["ms_total"] / p["launches"]) / 1e6, 1)
                                  if p["launches"] and p["ms_total"] > 0 else None)} for p in res["phases"]])
 
 
-def measured_traffic(workload, policy):
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hm_runtime.hip", "hm_device.h", "hm_plan.h", "hm_pack.cpp", "hm_pack.h"):
+        with open(os.path.join(ROOT, "paper_2405_03456_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, policy, kernel):
     """HBM bytes per launch of the dominant kernel from the committed PMC
     summary (FETCH_SIZE/WRITE_SIZE scaled by a copy-kernel calibration), or
-    None if there is none or the kernel/packer sources changed since."""
+    None if there is none or the kernel sources changed since."""
     import glob
-    import hashlib
-    here = os.path.dirname(os.path.abspath(__file__))
-
-    def sha(p):
-        with open(os.path.join(here, p), "rb") as f:
-            return hashlib.sha256(f.read()).hexdigest()[:16]
-    cur = sha("paper_2405_03456_amd/csrc/hm_runtime.hip") + "+" + sha("paper_2405_03456_amd/csrc/hm_pack.cpp")
-    for path in glob.glob(os.path.join(here, "profiles", "*.md")):
+    cur = kernel_sources_sha()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
         with open(path) as f:
             for line in f:
                 if line.startswith("traffic_json:"):
                     t = json.loads(line.split(":", 1)[1])
-                    if t["workload"] == workload and t["policy"] == policy and t["source_sha"] == cur:
+                    if (t["workload"] == workload and t["policy"] == policy and t.get("kernel") == kernel
+                            and t["source_sha"] == cur):
                         return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
     return None
 
 
-def cpu_baseline(fmt, st, vals, x, budget_s, gpu_results, points, eps):
-    """The oracle, timed on the host on a bounded sample of the same workload."""
-    from oracle import stored, trees
-    from oracle import dense as odense
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        cores = 1
-    ost = trees.build_structure(points)
-    for k in ("perm", "begin", "end", "blk_tau", "blk_sigma", "blk_adm"):
-        assert np.array_equal(getattr(ost, k), getattr(st, k)), "oracle and library layouts differ"
+def cpu_baseline(fmt, st, vals, x, mb, reps=5):
+    """The oracle's C/OpenMP product (same stored FP64 values, same
+    definition) timed on every core this process may use and on one core:
+    median of `reps` products each, plus a host triad probe."""
+    from oracle import omp
+    P = omp.Prepared(st, fmt, vals)
     y0 = np.zeros(len(x))
-    reps, t0 = 0, time.perf_counter()
-    ref = None
-    while True:
-        ref = stored.product(ost, fmt, vals, 1.0, x, y0)
-        reps += 1
-        if time.perf_counter() - t0 >= budget_s or reps >= 200:
-            break
-    dt = (time.perf_counter() - t0) / reps
-    errs = {}
-    for name, r in gpu_results.items():
-        pol = POLICIES[name]
-        sv = stored.stored_values(ost, fmt, vals, dense=pol["dense"], diag=pol.get("diag"), factor=pol["factor"],
-                                  coupling=pol["coupling"], eps=eps)
-        rs = ref if name == "f64" else stored.product(ost, fmt, sv, 1.0, x, y0)
-        errs[name] = {"vs_oracle_same_storage": float(np.linalg.norm(r["y"] - rs) / np.linalg.norm(rs))}
-    # error against the dense kernel matrix on sampled rows (the stated accuracy)
-    rows = np.arange(0, len(x), max(1, len(x) // 2048))
+    out = {}
+    for label, threads in (("all_cores", 0), ("one_core", 1)):
+        ts, used = [], 1
+        P.product(1.0, x, y0, threads)                       # warm-up
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            _, used = P.product(1.0, x, y0, threads)
+            ts.append(time.perf_counter() - t0)
+        dt = float(np.median(ts))
+        out[label] = {"seconds": dt, "GBs": mb / dt / 1e9, "matvecs_per_s": 1.0 / dt, "threads": used}
+    triad, tused = omp.triad_gbs()
+    out["triad_GBs"] = triad
+    out["triad_threads"] = tused
+    return out
+
+
+def parity(fmt, st, vals, pol, eps, x, y_gpu, points, rows):
+    """Relative errors of a GPU result: against the oracle's product of the
+    same stored values (C/OpenMP oracle on the dequantised values), and
+    against the dense kernel product on sampled rows (the stated accuracy)."""
+    from oracle import dense as odense
+    from oracle import omp, stored
+    y0 = np.zeros(len(x))
+    sv = vals if pol == POLICIES["f64"] else stored.stored_values(
+        st, fmt, vals, dense=pol["dense"], diag=pol.get("diag"), factor=pol["factor"],
+        coupling=pol["coupling"], eps=eps)
+    ref = omp.product(st, fmt, sv, 1.0, x, y0)
+    del sv
     yd = odense.dense_product(0, points, 1.0, x, y0, rows=rows)
-    for name, r in gpu_results.items():
-        errs[name]["vs_dense_sampled_rows"] = float(np.linalg.norm(r["y"][rows] - yd[rows]) /
-                                                  np.linalg.norm(yd[rows]))
-    return dt, reps, cores, errs
+    return {"vs_oracle_same_storage": float(np.linalg.norm(y_gpu - ref) / np.linalg.norm(ref)),
+            "vs_dense_sampled_rows": float(np.linalg.norm(y_gpu[rows] - yd[rows]) / np.linalg.norm(yd[rows])),
+            "oracle_vs_dense_sampled_rows": float(np.linalg.norm(ref[rows] - yd[rows]) / np.linalg.norm(yd[rows]))}
+
+
+def single_vector(args, hm, torch, name, legs, with_cpu, with_parity):
+    """All storage legs of one single-vector workload."""
+    from synth import gaussian_vector
+    fmt, n, eps, pseed, xseed, desc = WORKLOADS[name]
+    t0 = time.perf_counter()
+    lay, st, vals, points = workload_inputs(hm, name)
+    log(f"[bench] {name}: inputs ready in {time.perf_counter() - t0:.1f}s (blocks={st.nblocks})")
+    x_np = gaussian_vector(n, xseed)
+    x = torch.from_numpy(x_np).cuda()
+    rows = np.arange(0, n, max(1, n // 2048))
+    out = {"workload": desc, "format": fmt, "n": n, "eps": eps, "legs": {}}
+    base = None
+    for leg in legs:
+        pol = POLICIES[leg]
+        r = run_variant(hm, torch, lay, fmt, vals, eps, pol, args.steps, args.warmup, x, args.copies_bytes)
+        sm = summarize(r, args.steps)
+        row = {"GBs": round(sm["gbs"], 1), "matvecs_per_s": round(sm["matvecs_per_s"], 1),
+               "ms_per_step": round(sm["ms_per_step"], 5), "p10_ms": round(sm["p10_ms"], 5),
+               "p90_ms": round(sm["p90_ms"], 5), "wall_ms_per_step": round(sm["wall_ms_per_step"], 5),
+               "method_bytes_per_matvec": int(sm["method_bytes"]),
+               "overhead_bytes_per_matvec": int(sm["overhead_bytes"]),
+               "bytes_per_dtype": r["stats"]["bytes_per_dtype"], "entries_per_dtype": r["stats"]["entries_per_dtype"],
+               "fork_after": sm["fork_after"], "copies": sm["copies"], "roofline": sm["roofline"],
+               "policy": pol}
+        if base is None:
+            base = sm
+        row["speedup_vs_f64"] = round(base["ms_per_step"] / sm["ms_per_step"], 3)
+        if with_parity:
+            row["rel_err"] = parity(fmt, st, vals, pol, eps, x_np, r["y"], points, rows)
+        out["legs"][leg] = row
+        out.setdefault("phases", {})[leg] = sm["phases"]
+        log(f"[bench] {name} {leg}: {sm['ms_per_step'] * 1e3:.1f} us/step (p10 {sm['p10_ms'] * 1e3:.1f}, "
+            f"p90 {sm['p90_ms'] * 1e3:.1f}), {sm['gbs']:.0f} GB/s, copies={r['ncopies']}, "
+            f"rel_err={row.get('rel_err')}")
+    if with_cpu:
+        mb = out["legs"][legs[0]]["method_bytes_per_matvec"]
+        cb = cpu_baseline(fmt, st, vals, x_np, mb)
+        out["cpu"] = cb
+        log(f"[bench] {name} cpu oracle: {json.dumps(cb)}")
+    return out
 
 
 MFMA_PEAK_TFS = {True: 78.6, False: 157.3}     # float64 / float32 dense matrix-core peaks
@@ -228,16 +320,17 @@ def many_rhs(args, hm, torch, lay, fmt, vals, eps, n, points, st, desc):
     for pname in pols:
         M = hm.Matrix(lay, fmt, vals, eps=eps, **MANY_POLICIES[pname])
         ref = None
-        if not args.no_cpu:
+        if not args.no_parity:
+            from oracle import omp as oomp
             from oracle import stored as ostored
-            from oracle import trees as otrees
-            ost = otrees.build_structure(points)
-            sv = ostored.stored_values(ost, fmt, vals, eps=eps, **MANY_POLICIES[pname])
-            ref = ostored.product(ost, fmt, sv, 1.0, Xall[:, 0], np.zeros(n))
+            sv = ostored.stored_values(st, fmt, vals, eps=eps, **MANY_POLICIES[pname])
+            ref = oomp.product(st, fmt, sv, 1.0, Xall[:, 0], np.zeros(n))
             del sv
         s = M.stats()
         entries = sum(s["entries_per_dtype"])
-        stored_b = s["bytes_dense"] + s["bytes_factors"] + s["bytes_coupling"] + s["bytes_transfer"]
+        esize = (8, 4, 2, 2, 1)
+        stored_b = float(sum(c * esize[d] for d, c in enumerate(s["entries_per_dtype"])))
+        vec_b = float(s["method_bytes"]) - stored_b        # x, y, coefficients (+ FP16/FP8 column scales)
         acc64 = s["accum"] == hm.HM_ACC_F64
         for r in widths:
             X = torch.from_numpy(np.ascontiguousarray(Xall[:, :r].T)).cuda().T
@@ -266,7 +359,7 @@ def many_rhs(args, hm, torch, lay, fmt, vals, eps, n, points, st, desc):
             us = dom["ms_total"] * 1e3 / dom["launches"]
             flops = 2.0 * dom["data_entries"] * r
             gbs_dom = dom["data_bytes"] / (us * 1e-6) / 1e9
-            alg = stored_b + s["bytes_scales"] + s["bytes_meta"] + 24.0 * n * r
+            alg = stored_b + vec_b * r                        # the method's bytes for r columns
             row = {"policy": pname, "nrhs": r, "ms_per_step": round(ms, 4), "tuned": tuned,
                    "columns_per_s": round(r * 1e3 / ms, 1), "GBs": round(alg / (ms * 1e-3) / 1e9, 1),
                    "TFLOPs": round(2.0 * entries * r / (ms * 1e-3) / 1e12, 2),
@@ -390,9 +483,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="uh32768", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="h2_262144", choices=sorted(WORKLOADS))
+    ap.add_argument("--legs", default=None, help="comma-separated storage legs (default per format)")
+    ap.add_argument("--extra", default="uh32768,h2048",
+                    help="comma-separated extra single-vector workloads reported beside the headline ('' = none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline leg")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-parity", action="store_true", help="skip the oracle comparison of every leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, run a plain 1 GiB device copy (known traffic) to scale PMC counters")
     ap.add_argument("--copies-bytes", type=float, default=2.0e9,
@@ -403,7 +499,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="--nrhs runs: keep the default plan parameters")
     ap.add_argument("--serve", action="store_true", help="run the serving mix instead")
     ap.add_argument("--serve-matrices", type=int, default=16)
-    ap.add_argument("--serve-nmax", type=int, default=32768, help="largest n of the serving mix (full: 131072)")
+    ap.add_argument("--serve-nmax", type=int, default=131072, help="largest n of the serving mix")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget", type=float, default=4e9)
     args = ap.parse_args()
@@ -416,32 +512,25 @@ def main():
     import paper_2405_03456_amd as hm
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
-    from synth import gaussian_vector, sphere_points
 
     if args.serve:
         args.serve_budget = int(args.serve_budget)
         serve_mix(args, hm, torch)
         return
-    fmt, n, eps, pseed, xseed, desc = WORKLOADS[args.workload]
-    t0 = time.perf_counter()
-    points = sphere_points(n, pseed)
-    lay = hm.Layout(points)
-    st = structure_from_layout(lay)
-    vals = make_values(fmt, points, st, eps)
-    log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f}s (n={n}, fmt={fmt}, blocks={st.nblocks})")
     if args.nrhs:
+        fmt, n, eps, pseed, xseed, desc = WORKLOADS[args.workload]
+        lay, st, vals, points = workload_inputs(hm, args.workload)
         many_rhs(args, hm, torch, lay, fmt, vals, eps, n, points, st, desc)
         return
-    x_np = gaussian_vector(n, xseed)
-    x = torch.from_numpy(x_np).cuda()
-
-    results = {}
-    for name, pol in POLICIES.items():
-        r = run_variant(hm, torch, lay, fmt, vals, eps, pol, args.steps, args.warmup, x, args.copies_bytes)
-        results[name] = r
-        sm = summarize(r, args.steps)
-        log(f"[bench] {name}: {sm['ms_per_step'] * 1e3:.1f} us/step, {sm['gbs']:.0f} GB/s, "
-            f"copies={r['ncopies']}, phases={sm['phases']}")
+    fmt = WORKLOADS[args.workload][0]
+    legs = (args.legs or DEFAULT_LEGS[fmt]).split(",")
+    if legs[0] != "f64":
+        legs = ["f64"] + [leg for leg in legs if leg != "f64"]
+    main_w = single_vector(args, hm, torch, args.workload, legs, not args.no_cpu, not args.no_parity)
+    extras = {}
+    for name in [w for w in args.extra.split(",") if w and w != args.workload]:
+        extras[name] = single_vector(args, hm, torch, name, DEFAULT_LEGS[WORKLOADS[name][0]].split(","),
+                                     False, not args.no_parity)
 
     if args.calibrate_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
@@ -451,54 +540,51 @@ def main():
         torch.cuda.synchronize()
         log("[bench] calibration: 3 copies of 1 GiB (read 1 GiB + write 1 GiB each)")
 
-    main_s = summarize(results["f64"], args.steps)
-    if main_s["roofline"] is not None:
-        tr = measured_traffic(args.workload, "f64")
-        main_s["roofline"]["traffic"] = None if tr is None else int(tr)
-    f32_s = summarize(results["f32"], args.steps)
-    valr_s = summarize(results["valr"], args.steps)
+    f64 = main_w["legs"]["f64"]
+    roof = f64["roofline"]
+    if roof is not None:
+        tr = measured_traffic(args.workload, "f64", roof["kernel"])
+        roof["traffic"] = None if tr is None else int(tr)
     out = {
         "metric": METRIC,
-        "value": round(main_s["gbs"], 1),
+        "value": f64["GBs"],
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(main_s["ms_per_step"], 5),
+        "ms_per_step": f64["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded sphere points, Laplace kernel, ACA-compressed)",
-        "config": {"workload": desc, "format": fmt, "n": n, "eps": eps, "nrhs": 1,
-                   "storage": "f64", "accumulation": "f64", "rotated_copies": main_s["copies"]},
-        "matvecs_per_s": round(main_s["matvecs_per_s"], 1),
-        "timing": "graph replay (one hipGraph per rotated copy); roofline from event-timed eager products",
-        "fork_after": main_s["fork_after"],
-        "eager_ms_per_step": round(main_s["eager_ms_per_step"], 5),
-        "algorithmic_bytes_per_matvec": int(main_s["algorithmic_bytes"]),
-        "roofline": main_s["roofline"],
-        "phases_f64": main_s["phases"],
-        "valr_storage": {"GBs": round(valr_s["gbs"], 1), "matvecs_per_s": round(valr_s["matvecs_per_s"], 1),
-                         "ms_per_step": round(valr_s["ms_per_step"], 5),
-                         "fork_after": valr_s["fork_after"],
-                         "speedup_vs_f64": round(main_s["ms_per_step"] / valr_s["ms_per_step"], 3),
-                         "algorithmic_bytes_per_matvec": int(valr_s["algorithmic_bytes"]),
-                         "bytes_per_dtype": results["valr"]["stats"]["bytes_per_dtype"],
-                         "roofline": valr_s["roofline"]},
-        "f32_storage": {"GBs": round(f32_s["gbs"], 1), "matvecs_per_s": round(f32_s["matvecs_per_s"], 1),
-                        "ms_per_step": round(f32_s["ms_per_step"], 5),
-                        "speedup_vs_f64": round(main_s["ms_per_step"] / f32_s["ms_per_step"], 3),
-                        "algorithmic_bytes_per_matvec": int(f32_s["algorithmic_bytes"]),
-                        "roofline": f32_s["roofline"]},
+        "data": "synthetic (seeded sphere points, Laplace kernel, ACA-compressed, nested bases)",
+        "config": {"workload": main_w["workload"], "format": fmt, "n": main_w["n"], "eps": main_w["eps"],
+                   "nrhs": 1, "storage": "f64", "accumulation": "f64", "rotated_copies": f64["copies"]},
+        "matvecs_per_s": f64["matvecs_per_s"],
+        "p10_ms": f64["p10_ms"],
+        "p90_ms": f64["p90_ms"],
+        "wall_ms_per_step": f64["wall_ms_per_step"],
+        "timing": "graph replays, HIP events around each replay (median, p10, p90); roofline from "
+                  "event-timed eager products",
+        "method_bytes_per_matvec": f64["method_bytes_per_matvec"],
+        "overhead_bytes_per_matvec": f64["overhead_bytes_per_matvec"],
+        "roofline": roof,
+        "legs": main_w["legs"],
+        "phases_f64": main_w["phases"]["f64"],
     }
-    if not args.no_cpu:
-        dt, reps, cores, errs = cpu_baseline(fmt, st, vals, x_np, args.cpu_seconds, results, points, eps)
-        out["cpu_baseline"] = {"value": round(main_s["algorithmic_bytes"] / dt / 1e9, 3), "unit": "GB/s",
-                               "matvecs_per_s": round(1.0 / dt, 3), "cores": cores, "kind": "oracle",
-                               "sample": f"{reps} full {fmt.upper()} products (float64 stored values, numpy) "
-                                         f"of the same n={n} matrix"}
-        out["rel_err"] = errs
+    if "cpu" in main_w:
+        c = main_w["cpu"]
+        out["cpu_baseline"] = {
+            "value": round(c["all_cores"]["GBs"], 3), "unit": "GB/s", "cores": c["all_cores"]["threads"],
+            "kind": "oracle", "matvecs_per_s": round(c["all_cores"]["matvecs_per_s"], 3),
+            "one_core": {"GBs": round(c["one_core"]["GBs"], 3),
+                         "matvecs_per_s": round(c["one_core"]["matvecs_per_s"], 3)},
+            "host_triad_GBs": round(c["triad_GBs"], 1), "host_triad_threads": c["triad_threads"],
+            "fraction_of_host_triad": round(c["all_cores"]["GBs"] / c["triad_GBs"], 3),
+            "sample": f"median of 5 full FP64 {fmt.upper()} products of the same n={main_w['n']} matrix "
+                      "(C/OpenMP oracle, oracle/mvm_omp.c), all cores and one core"}
+    if extras:
+        out["extra_workloads"] = {k: {"workload": v["workload"], "legs": v["legs"]} for k, v in extras.items()}
     print(json.dumps(out), flush=True)
 
 

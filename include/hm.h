@@ -197,6 +197,7 @@ typedef struct hm_matrix hm_matrix;
  *                  instead of one stage on a second stream
  *   dense_grid     cap on the workgroups of that second-stream stage (0 = none)
  *   fork_after     initial fork point of that stage (see hm_tune_mvm)
+ *   schedule / dense_after / spin_limit_us: see the fields below
  *   valr_promote   1 = under HM_VALR_AUTO, a format used by fewer columns of
  *                  a factor than one 16-byte tile holds is stored in the
  *                  factor's next more precise format present when that costs
@@ -210,7 +211,15 @@ typedef struct {
     int32_t dense_grid;
     int32_t fork_after;
     int32_t valr_promote;
+    int32_t schedule;       /* HM_SCHED_PERSISTENT (default) or HM_SCHED_STAGED, see hm_mvm */
+    int32_t dense_after;    /* persistent schedule: first boundary between dependent stages from
+                               which the dense near-field tasks are interleaved (see hm_tune_mvm) */
+    int32_t spin_limit_us;  /* persistent schedule: bound of one dependency wait in microseconds
+                               (0 = 2 000 000); a wait past it aborts the launch (hm_matrix_check) */
 } hm_upload_opts;
+
+#define HM_SCHED_PERSISTENT 0
+#define HM_SCHED_STAGED 1
 
 /* Quantise on the host per `prec`, pack into level- and row-cluster-ordered
  * streams and copy to the current HIP device.  opts may be NULL (defaults).
@@ -234,8 +243,12 @@ typedef struct {
     int64_t sum_rank;               /* sum of block ranks (H) or basis ranks (UH/H2) */
     int32_t max_rank;
     int32_t accum;                  /* resolved accumulation (HM_ACC_F32 / HM_ACC_F64) */
-    int32_t nlaunch;                /* kernel launches per hm_mvm */
-    double algorithmic_bytes;       /* bytes one hm_mvm must move: data + scales + vectors + metadata */
+    int32_t nlaunch;                /* kernel launches per hm_mvm (persistent schedule: 2) */
+    double algorithmic_bytes;       /* bytes one hm_mvm moves: stored data (16-byte tiles, padding
+                                       included) + scales + vectors + coefficients + plan metadata */
+    double method_bytes;            /* bytes the product itself needs: every stored entry once at its
+                                       element size, a float32 scale per FP16/FP8 column, x read,
+                                       y read and written, every coefficient written and read once */
 } hm_stats;
 
 hm_status hm_matrix_stats(const hm_matrix* m, hm_stats* s);
@@ -252,9 +265,30 @@ hm_status hm_plan_stats(const hm_layout* layout, int32_t format, const hm_values
 
 /* y := alpha * M * x + y.  x, y: device float64 arrays of length n
  * (caller-owned, e.g. PyTorch tensors), x != y.  Enqueued on `stream`;
- * calls on one matrix must not overlap in time (they share its workspace). */
+ * calls on one matrix must not overlap in time (they share its workspace).
+ *
+ * Schedules (the arithmetic and its order are the same, results are
+ * bitwise identical):
+ *   HM_SCHED_STAGED      one launch per stage of the data flow of Sec. 3
+ *                        (forward transform / upward pass, couplings,
+ *                        downward pass level by level, leaf rows), the
+ *                        dense near field on a second stream, a final
+ *                        reduction of split output rows;
+ *   HM_SCHED_PERSISTENT  a gather launch, then one launch whose wavefronts
+ *                        take the same tasks from a ticket queue in a
+ *                        topological order; each task waits only for the
+ *                        owners whose outputs it reads.  Every wait is
+ *                        bounded (spin_limit_us): past it the launch aborts
+ *                        and records an error for hm_matrix_check. */
 hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double* y, uint32_t flags,
                  hm_stream_t stream);
+
+/* Waits for the device (hipDeviceSynchronize) and reports whether a
+ * persistent-schedule launch of this matrix was aborted since the last call
+ * (a dependency wait exceeded its bound; the products of that launch are
+ * wrong).  Clears the record.  Errors: HM_EINVAL, HM_EDEVICE (aborted, or a
+ * HIP call failed). */
+hm_status hm_matrix_check(hm_matrix* m);
 
 /* Many right-hand sides (the paper's product applied to every column of a
  * block of vectors, eq. 4 per column): for i < nmat,
@@ -302,25 +336,30 @@ typedef struct {
 hm_status hm_tune_batch(hm_matrix* m, int32_t nrhs, int32_t vec_dtype, int32_t reps, hm_stream_t stream,
                         hm_tune_result* out);
 
-/* Autotuner of the single-vector product.  The dependent chain of stages
- * (cluster-basis and coupling passes) runs on the caller's stream and the
- * dense near-field stage, which reads only x, on a second stream.  Its one
- * free parameter is the fork point: how many chain stages complete before
- * the dense stage starts (0 = right after x is gathered).  Starting it later
- * keeps it off the chain's bandwidth-heavy first stages and lets it fill the
- * latency-bound ones.  hm_tune_mvm times every fork point (`reps` replays of
- * a captured graph of the product on a zero vector, allocated and freed
- * here) and keeps the fastest for this matrix.  The fork point changes no
- * arithmetic: products are bitwise identical for every choice.  It
+/* Autotuner of the single-vector product.  Staged schedule: the dependent
+ * chain of stages (cluster-basis and coupling passes) runs on the caller's
+ * stream and the dense near-field stage, which reads only x, on a second
+ * stream; the free parameter is the fork point, how many chain stages
+ * complete before the dense stage starts (0 = right after x is gathered).
+ * Persistent schedule: the free parameter is dense_after, the first boundary
+ * between chain stages from which the dense tasks are interleaved into the
+ * queue.  hm_tune_mvm times every candidate of both schedules (`reps`
+ * replays of a captured graph of the product on a zero vector, allocated and
+ * freed here; a matrix uploaded with HM_SCHED_STAGED has no persistent
+ * candidates) and keeps the fastest for this matrix.  No candidate changes
+ * the arithmetic: products are bitwise identical for every choice.  It
  * allocates and synchronises: call it outside graph capture, before
- * creating graphs of the matrix (graphs keep the fork point they were
- * captured with).  A matrix without a dense stage reports one candidate.
- * Errors: HM_EINVAL, HM_ENOMEM, HM_EDEVICE. */
+ * creating graphs of the matrix (graphs keep the schedule they were
+ * captured with).  Errors: HM_EINVAL, HM_ENOMEM, HM_EDEVICE. */
 typedef struct {
-    int32_t fork_after;     /* chosen: chain stages completed before the dense stage starts */
-    int32_t ncandidates;    /* fork points timed */
-    double ms;              /* mean time per product at the chosen fork point */
-    double ms_first;        /* ... at fork point 0 */
+    int32_t fork_after;     /* staged schedule: chain stages completed before the dense stage starts */
+    int32_t ncandidates;    /* candidates timed */
+    double ms;              /* mean time per product of the chosen candidate */
+    double ms_first;        /* ... of the staged schedule at fork point 0 */
+    int32_t schedule;       /* chosen schedule (HM_SCHED_*) */
+    int32_t dense_after;    /* persistent schedule: chosen interleave point */
+    double ms_staged;       /* best staged candidate */
+    double ms_persistent;   /* best persistent candidate (0 if none) */
 } hm_tune_mvm_result;
 hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream, hm_tune_mvm_result* out);
 
@@ -367,6 +406,7 @@ typedef struct {
     int32_t nrhs;            /* padded block width of the timed launches (1 = single vector);
                                 launches of different widths are not mixed: timing
                                 an hm_mvm_batch call discards pending hm_mvm timings */
+    double method_bytes;     /* algorithmic_bytes without tile padding and task descriptors */
 } hm_phase_timing;
 
 hm_status hm_timing_read(hm_matrix* m, hm_phase_timing* out, int32_t cap, int32_t* nphase);

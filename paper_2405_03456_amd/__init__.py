@@ -144,11 +144,15 @@ def make_precision(eps=0.0, dense="f64", diag=None, factor="f64", coupling=None,
                           DTYPES[coupling or factor], accum)
 
 
+SCHEDULES = {"persistent": _lib.HM_SCHED_PERSISTENT, "staged": _lib.HM_SCHED_STAGED}
+
+
 def make_opts(task_bytes: int = 0, spread_dense: bool = False, dense_grid: int = 0, fork_after: int = 0,
-              valr_promote: bool = False):
+              valr_promote: bool = False, schedule: str = "persistent", dense_after: int = 0,
+              spin_limit_us: int = 0):
     """hm_upload_opts (all zero = the library's defaults)."""
     return _lib.UploadOpts(int(task_bytes), int(bool(spread_dense)), int(dense_grid), int(fork_after),
-                           int(bool(valr_promote)))
+                           int(bool(valr_promote)), SCHEDULES[schedule], int(dense_after), int(spin_limit_us))
 
 
 def _stats_dict(s) -> dict:
@@ -226,10 +230,17 @@ class Matrix:
         return dict(target_bytes=r.target_bytes, nrb=r.nrb, ms=r.ms, ncandidates=r.ncandidates)
 
     def tune_mvm(self, reps: int = 10, stream=None) -> dict:
-        """Pick the single-vector fork point of the dense stage (hm_tune_mvm)."""
+        """Pick the single-vector schedule and its parameter (hm_tune_mvm)."""
         r = _lib.TuneMvmResult()
         _lib.check(_lib.lib().hm_tune_mvm(self._h, int(reps), _stream_ptr(stream), ctypes.byref(r)))
-        return dict(fork_after=r.fork_after, ncandidates=r.ncandidates, ms=r.ms, ms_first=r.ms_first)
+        return dict(fork_after=r.fork_after, ncandidates=r.ncandidates, ms=r.ms, ms_first=r.ms_first,
+                    schedule="persistent" if r.schedule == _lib.HM_SCHED_PERSISTENT else "staged",
+                    dense_after=r.dense_after, ms_staged=r.ms_staged, ms_persistent=r.ms_persistent)
+
+    def check(self):
+        """Wait for the device; raise if a persistent launch of this matrix
+        was aborted since the last check (hm_matrix_check)."""
+        _lib.check(_lib.lib().hm_matrix_check(self._h))
 
     def graph(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None) -> "Graph":
         """Capture one product (fixed x, y, alpha) into a replayable HIP graph."""
@@ -243,7 +254,8 @@ class Matrix:
         _lib.check(_lib.lib().hm_timing_read(self._h, arr, cap, ctypes.byref(n)))
         return [dict(name=arr[i].name.decode(), ms_total=arr[i].ms_total, launches=arr[i].launches,
                      algorithmic_bytes=arr[i].algorithmic_bytes, ntasks=arr[i].ntasks, nowners=arr[i].nowners,
-                     data_bytes=arr[i].data_bytes, data_entries=arr[i].data_entries, nrhs=arr[i].nrhs)
+                     data_bytes=arr[i].data_bytes, data_entries=arr[i].data_entries, nrhs=arr[i].nrhs,
+                     method_bytes=arr[i].method_bytes)
                 for i in range(min(n.value, cap))]
 
     def free(self):

@@ -46,9 +46,13 @@ class LayoutInfo(ctypes.Structure):
                 ("lowrank_area_per_level", c_double * HM_MAX_LEVELS)]
 
 
+HM_SCHED_PERSISTENT, HM_SCHED_STAGED = 0, 1
+
+
 class UploadOpts(ctypes.Structure):
     _fields_ = [("task_bytes", c_int64), ("spread_dense", c_int32), ("dense_grid", c_int32),
-                ("fork_after", c_int32), ("valr_promote", c_int32)]
+                ("fork_after", c_int32), ("valr_promote", c_int32), ("schedule", c_int32),
+                ("dense_after", c_int32), ("spin_limit_us", c_int32)]
 
 
 class Values(ctypes.Structure):
@@ -71,13 +75,14 @@ class Stats(ctypes.Structure):
                 ("bytes_workspace", c_int64), ("bytes_per_dtype", c_int64 * 5),
                 ("entries_per_dtype", c_int64 * 5), ("sum_rank", c_int64),
                 ("max_rank", c_int32), ("accum", c_int32), ("nlaunch", c_int32),
-                ("algorithmic_bytes", c_double)]
+                ("algorithmic_bytes", c_double), ("method_bytes", c_double)]
 
 
 class PhaseTiming(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("ms_total", c_double), ("launches", c_int64),
                 ("algorithmic_bytes", c_double), ("ntasks", c_int32), ("nowners", c_int32),
-                ("data_bytes", c_int64), ("data_entries", c_int64), ("nrhs", c_int32)]
+                ("data_bytes", c_int64), ("data_entries", c_int64), ("nrhs", c_int32),
+                ("method_bytes", c_double)]
 
 
 class TuneResult(ctypes.Structure):
@@ -85,7 +90,9 @@ class TuneResult(ctypes.Structure):
 
 
 class TuneMvmResult(ctypes.Structure):
-    _fields_ = [("fork_after", c_int32), ("ncandidates", c_int32), ("ms", c_double), ("ms_first", c_double)]
+    _fields_ = [("fork_after", c_int32), ("ncandidates", c_int32), ("ms", c_double), ("ms_first", c_double),
+                ("schedule", c_int32), ("dense_after", c_int32), ("ms_staged", c_double),
+                ("ms_persistent", c_double)]
 
 
 class ServeOpts(ctypes.Structure):
@@ -116,6 +123,7 @@ SIGNATURES = {
     "hm_matrix_stats": (c_int32, [c_void_p, P(Stats)]),
     "hm_plan_stats": (c_int32, [c_void_p, c_int32, P(Values), P(Precision), P(UploadOpts), P(Stats)]),
     "hm_mvm": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p]),
+    "hm_matrix_check": (c_int32, [c_void_p]),
     "hm_mvm_batch": (c_int32, [P(c_void_p), c_int32, c_double, P(c_void_p), P(c_int64), P(c_int32),
                                P(c_void_p), P(c_int64), c_int32, c_uint32, c_void_p]),
     "hm_graph_create": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p, P(c_void_p)]),

@@ -103,6 +103,7 @@ struct DevStage {
     int64_t data_bytes;
     int64_t data_entries;
     double alg_bytes;
+    double method_bytes = 0;
     std::string name;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;   // HM_TIMING event pairs
     int32_t timed_nrhs = 1;                                    // block width of the pending pairs
@@ -163,6 +164,24 @@ struct hm_matrix {
     float* wsm32 = nullptr;
     double* ym = nullptr;      // y contributions in cluster order
     double* partm = nullptr;
+    // persistent schedule (hm_persist.hip): the plan's tasks as one ticket
+    // queue, per-owner completion counters, control words
+    int32_t schedule = HM_SCHED_STAGED;
+    int32_t p_nq = 0;            // queue entries
+    int32_t p_mask = 0;          // dtypes of the tasks
+    int32_t p_grid = 0;          // workgroups of the persistent launch
+    int32_t p_dense_after = 0;
+    int64_t p_nowners = 0;
+    uint64_t p_spin = 0;         // bound of a dependency wait, 100 MHz ticks
+    const hm::DTask* p_tasks = nullptr;
+    const int32_t* p_dep_first = nullptr;
+    const int32_t* p_deps = nullptr;
+    const int32_t* p_target = nullptr;
+    int32_t* p_order = nullptr;
+    int32_t* p_done = nullptr;
+    uint32_t* p_ctl = nullptr;   // ticket, abort, error
+    hm::Queue p_queue;           // host copy (the tuner reorders it)
+    std::vector<hm::DevStage> pphases;   // the persistent launch, for HM_TIMING
 };
 
 namespace hm {

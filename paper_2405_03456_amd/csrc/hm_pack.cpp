@@ -1273,14 +1273,18 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
                     const int32_t jb = c - item.col0, je = std::min(item.ncols, t.c1 - item.col0);
                     st.data_bytes += (int64_t)((je + V - 1) / V - jb / V) * ow.nrows * 16;
                     st.data_entries += (int64_t)((je + V - 1) / V - jb / V) * ow.nrows * V;
+                    st.method_bytes += (double)(je - jb) * ow.nrows * dtype_bytes(item.dtype);
                     st.dtype_mask |= 1 << item.dtype;
                     c = item.col0 + je;
                 }
-                st.alg_bytes += 8.0 * ow.nrows * (t.ntasks > 1 ? 1 : (ow.mode == 0 ? 2 : 3)) + sizeof(DTask);
+                const double outb = 8.0 * ow.nrows * (t.ntasks > 1 ? 1 : (ow.mode == 0 ? 2 : 3));
+                st.alg_bytes += outb + sizeof(DTask);
+                st.method_bytes += outb;
             }
             for (int32_t o : st.reduce) {
                 const DOwner& ow = out.owners[o];
                 st.alg_bytes += 8.0 * ow.nrows * (ow.ntasks + (ow.mode == 0 ? 2 : 3));
+                st.method_bytes += 8.0 * ow.nrows * (ow.ntasks + (ow.mode == 0 ? 2 : 3));
             }
             st.alg_bytes += (double)st.data_bytes;
         }
@@ -1320,6 +1324,12 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
     s.algorithmic_bytes = (double)(s.bytes_dense + s.bytes_factors + s.bytes_coupling + s.bytes_transfer +
                                    s.bytes_scales + s.bytes_meta) +
                           24.0 * L.n + 16.0 * (out.ws_elems - L.n);
+    // the method's own bytes: every stored entry once at its element size, a
+    // float32 scale per range-scaled column, x read, y read and written, and
+    // every coefficient entry written and read once (float64)
+    s.method_bytes = 24.0 * L.n + 16.0 * (out.ws_elems - L.n);
+    for (const Source& S : B.src)
+        s.method_bytes += (double)S.m * S.k * dtype_bytes(S.dtype) + (range_scaled(S.dtype) ? 4.0 * S.k : 0.0);
     std::string why;
     if (!validate(out, L.n, why)) {
         set_error("hm_upload: internal plan check failed (" + why + ")");
@@ -1428,10 +1438,16 @@ hm_status pack_options(const hm_upload_opts* o, PackOptions& opt) {
         set_error("hm_upload: task_bytes must be 0 (default) or at least 1024");
         return HM_EINVAL;
     }
-    if (o->dense_grid < 0 || o->fork_after < 0 || (o->spread_dense & ~1) || (o->valr_promote & ~1)) {
-        set_error("hm_upload: negative dense_grid / fork_after, or a flag other than 0 / 1");
+    if (o->dense_grid < 0 || o->fork_after < 0 || (o->spread_dense & ~1) || (o->valr_promote & ~1) ||
+        o->dense_after < 0 || o->spin_limit_us < 0 ||
+        (o->schedule != HM_SCHED_PERSISTENT && o->schedule != HM_SCHED_STAGED)) {
+        set_error("hm_upload: negative dense_grid / fork_after / dense_after / spin_limit_us, a flag other "
+                  "than 0 / 1, or an unknown schedule");
         return HM_EINVAL;
     }
+    opt.schedule = o->schedule;
+    opt.dense_after = o->dense_after;
+    if (o->spin_limit_us) opt.spin_limit_us = o->spin_limit_us;
     if (o->task_bytes) opt.task_bytes = o->task_bytes;
     opt.concurrent_dense = o->spread_dense == 0;
     opt.valr_promote = o->valr_promote != 0;
@@ -1452,6 +1468,14 @@ extern "C" hm_status hm_plan_stats(const hm_layout* layout, int32_t format, cons
     if (st != HM_OK) return st;
     try {
         st = hm::pack(layout->L, format, values, prec, opt, P);
+        if (st == HM_OK && opt.schedule == HM_SCHED_PERSISTENT) {
+            // the persistent queue is built and its progress rule checked as in hm_upload
+            hm::Queue Q;
+            std::vector<int32_t> order;
+            st = hm::build_queue(P, layout->L.n, Q);
+            if (st == HM_OK) st = hm::queue_order(P.owners, Q.tasks, Q, opt.dense_after, order);
+            if (st == HM_OK) P.stats.nlaunch = 2;   // gather + the persistent launch
+        }
     } catch (const std::bad_alloc&) {
         hm::set_error("hm_plan_stats: out of host memory while packing");
         return HM_ENOMEM;

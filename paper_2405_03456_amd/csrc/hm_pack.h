@@ -10,6 +10,9 @@ struct PackOptions {
     int64_t task_bytes = 32768;   // target matrix bytes per task (one wavefront)
     bool concurrent_dense = true; // dense leaves as one independent stage (else spread over the stages)
     bool valr_promote = false;    // VALR: fill the 16-byte tiles of short format runs (see valr_formats)
+    int32_t schedule = HM_SCHED_PERSISTENT;
+    int32_t dense_after = 0;      // persistent schedule: interleave point of the dense tasks
+    int64_t spin_limit_us = 2000000;
 };
 
 // Validated PackOptions from the ABI's hm_upload_opts (NULL = defaults).
@@ -36,6 +39,29 @@ struct Packed {
 
 hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_precision* p,
                const PackOptions& opt, Packed& out);
+
+// Persistent schedule of the single-vector product (hm_queue.cpp): the
+// plan's tasks and split-owner reductions as one ticket queue.  A queue
+// entry e >= 0 is task e, e < 0 the reduction of owner ~e.
+struct Queue {
+    std::vector<DTask> tasks;          // the plan's tasks; mode bit 2 set where inputs are staged
+    std::vector<int32_t> dep_first;    // per task: its producer owners are deps[dep_first[k] .. dep_first[k+1])
+    std::vector<int32_t> deps;
+    std::vector<int32_t> target;       // per owner: completion count once its outputs are final
+    std::vector<std::vector<int32_t>> chain;   // queue entries of each dependent stage, in order
+    std::vector<int32_t> dense;        // the independent (near-field) tasks
+    std::vector<int32_t> final_reduce; // queue entries (~owner) of the reductions after everything
+    int32_t nchain = 0;
+    int32_t dtype_mask = 0;
+};
+
+hm_status build_queue(const Packed& P, int64_t n, Queue& q);
+
+// The queue order with the dense tasks spread evenly over the boundaries
+// between the dependent stages from boundary `dense_after` on (0 = before the
+// first stage); checks that every item follows its producers.
+hm_status queue_order(const std::vector<DOwner>& owners, const std::vector<DTask>& tasks, const Queue& q,
+                      int32_t dense_after, std::vector<int32_t>& order);
 
 // Task table of the many-right-hand-side engine, derived from a packed plan.
 // Consecutive tasks of one owner in one stage (same dtype, adjacent

@@ -83,6 +83,7 @@ struct Stage {
     int64_t data_bytes = 0;      // matrix bytes streamed by its tasks
     int64_t data_entries = 0;    // matrix entries streamed (tile padding included)
     double alg_bytes = 0;        // data + partial/output writes
+    double method_bytes = 0;     // the same without tile padding and task descriptors
     int32_t dtype_mask = 0;      // dtypes of the items its tasks touch
     bool aux = false;            // independent of the other stages: runs on a second stream
     std::vector<int32_t> reduce_launch;   // the owners of `reduce` the single-vector product

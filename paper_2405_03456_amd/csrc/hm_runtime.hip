@@ -24,7 +24,7 @@
 #include <string>
 #include <vector>
 
-#include "hm_device.h"
+#include "hm_stream.h"
 
 namespace hm {
 
@@ -32,319 +32,6 @@ static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 
 namespace dev {
-
-
-// Accumulate one tile row.  WIDE: float64 accumulator with float64 inputs
-// w; otherwise float32 accumulator with the float32 mirror of the inputs.
-template <int DT, bool WIDE, bool SCALED, typename WT>
-__device__ __forceinline__ void tile_acc(const uint4& q, const WT* __restrict__ w, const double* __restrict__ sc,
-                                         double& a64, float& a32) {
-    using TT = Tile<DT>;
-    typename TT::R v[TT::V];
-    TT::decode(q, v);
-#pragma unroll
-    for (int i = 0; i < TT::V; ++i) {
-        if (WIDE) {
-            double wi = (double)w[i];
-            if (SCALED) wi *= sc[i];
-            a64 = fma((double)v[i], wi, a64);
-        } else {
-            float wi = (float)w[i];
-            if (SCALED) wi *= (float)sc[i];
-            a32 = fmaf((float)v[i], wi, a32);
-        }
-    }
-}
-
-// Where the current item sits in the owner's tile stream.
-struct ItemPos {
-    int it, k0, k1, vec, sc;
-};
-
-template <int DT>
-__device__ __forceinline__ ItemPos item_pos(const DItem* __restrict__ items, int it) {
-    const DItem d = items[it];
-    constexpr int V = Tile<DT>::V;
-    return ItemPos{it, d.tile0, d.tile0 + (d.ncols + V - 1) / V, d.vec_off, d.scale_off};
-}
-
-__device__ __forceinline__ void finalize(int mode, int out_off, int r, double v, double* __restrict__ vout,
-                                         float* __restrict__ vout32, double* __restrict__ y,
-                                         const int64_t* __restrict__ perm, double alpha) {
-    if (mode == 0) {
-        vout[out_off + r] = v;
-        vout32[out_off + r] = (float)v;
-    } else if (mode == 1) {
-        y[perm ? perm[out_off + r] : (int64_t)(out_off + r)] += alpha * v;
-    } else {
-        y[out_off + r] += alpha * v;
-    }
-}
-
-// Accumulate one tile row with inputs already in registers/LDS (grouped path).
-template <int DT, bool WIDE>
-__device__ __forceinline__ void tile_acc_w(const uint4& q, const double* wv, double& a64, float& a32) {
-    using TT = Tile<DT>;
-    typename TT::R v[TT::V];
-    TT::decode(q, v);
-#pragma unroll
-    for (int i = 0; i < TT::V; ++i) {
-        if (WIDE)
-            a64 = fma((double)v[i], wv[i], a64);
-        else
-            a32 = fmaf((float)v[i], (float)wv[i], a32);
-    }
-}
-
-// Stage a task's inputs (times their column scales) in this wave's LDS slice
-// in tile order: lw[(t - k0) * V + i] = input of column i of tile t.  With
-// `deferred`, an input that is an unreduced sum (dsrc entry != 0) is formed
-// here from its partial sums, added in task order.  Past an item's last
-// column the values are not needed (its data is zero) but are finite.
-// Each lane takes four entries per pass and loads up to four partial sums of
-// each at once, so the loads of a pass overlap instead of queueing.
-template <int DT>
-__device__ __forceinline__ void stage_inputs(const DTask& tk, const DItem* __restrict__ items, int lane,
-                                             bool deferred, const double* __restrict__ vin,
-                                             const double* __restrict__ scales, const int64_t* __restrict__ dsrc,
-                                             const double* part, double* __restrict__ lw) {
-    constexpr int V = Tile<DT>::V;
-    constexpr int CH = 4;
-    const int k0 = tk.k0;
-    const int nval = (tk.k1 - k0) * V;
-    ItemPos st = item_pos<DT>(items, tk.item_start);
-    for (int base = lane; base < nval; base += 64 * CH) {
-        int e[CH], sc[CH];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int idx = min(base + u * 64, nval - 1);   // a clamped entry is staged twice, same value
-            const int t = k0 + idx / V;
-            while (t >= st.k1) st = item_pos<DT>(items, st.it + 1);
-            const int c = (t - st.k0) * V + idx % V;
-            e[u] = st.vec + c;
-            sc[u] = st.sc >= 0 ? st.sc + c : -1;
-        }
-        int64_t d[CH];
-        double v[CH], f[CH];
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            d[u] = deferred ? dsrc[e[u]] : 0;
-            v[u] = vin[e[u]];
-            f[u] = sc[u] >= 0 ? scales[sc[u]] : 1.0;
-        }
-        if (deferred) {
-#pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                if (d[u] == 0) continue;
-                const double* p = part + (uint32_t)d[u];
-                const int cnt = (int)(((uint64_t)d[u] >> 32) & 0xffff);
-                const int64_t stride = (int64_t)((uint64_t)d[u] >> 48);
-                double acc = 0.0;
-                for (int l = 0; l < cnt; l += 4) {
-                    double q[4];
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) q[w] = l + w < cnt ? p[(l + w) * stride] : 0.0;
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) acc += q[w];
-                }
-                v[u] = acc;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int idx = base + u * 64;
-            if (idx < nval) lw[idx] = v[u] * f[u];
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Wide owners (more than 32 rows): the wave walks the task's tiles together,
-// a prefetched batch of U tiles always in flight; item bookkeeping is
-// uniform and the inputs are scalar loads (lgkmcnt), so waiting for them
-// never drains the data prefetch (vmcnt).
-template <int DT, bool WIDE, bool STAGED>
-__device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __restrict__ items,
-                                               const uint8_t* __restrict__ sb, int64_t rt, int lane,
-                                               const double* __restrict__ vin, const float* __restrict__ vin32,
-                                               const double* __restrict__ scales, const int64_t* __restrict__ dsrc,
-                                               const double* part, double* __restrict__ lw, double& a64,
-                                               float& a32) {
-    constexpr int V = Tile<DT>::V;
-    constexpr int U = Tile<DT>::V <= 4 ? 8 : 4;
-    const int k0 = tk.k0, k1 = tk.k1;
-    ItemPos st = item_pos<DT>(items, tk.item_start);
-    uint4 qa[U], qb[U];
-    auto issue = [&](uint4* q, int kb) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) q[u] = *reinterpret_cast<const uint4*>(sb + (int64_t)min(kb + u, k1 - 1) * rt);
-    };
-    auto consume = [&](const uint4* q, int kb) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int kk = kb + u;
-            if (STAGED) {
-                if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw + (kk - k0) * V, a64, a32);
-                continue;
-            }
-            if (kk < k1) {
-                while (kk >= st.k1) st = item_pos<DT>(items, st.it + 1);
-                const int c = (kk - st.k0) * V;
-                if (WIDE) {
-                    if (st.sc >= 0)
-                        tile_acc<DT, true, true>(q[u], vin + st.vec + c, scales + st.sc + c, a64, a32);
-                    else
-                        tile_acc<DT, true, false>(q[u], vin + st.vec + c, scales, a64, a32);
-                } else {
-                    if (st.sc >= 0)
-                        tile_acc<DT, false, true>(q[u], vin32 + st.vec + c, scales + st.sc + c, a64, a32);
-                    else
-                        tile_acc<DT, false, false>(q[u], vin32 + st.vec + c, scales, a64, a32);
-                }
-            }
-        }
-    };
-    issue(qa, k0);
-    if (STAGED) stage_inputs<DT>(tk, items, lane, true, vin, scales, dsrc, part, lw);
-    for (int k = k0; k < k1; k += 2 * U) {
-        issue(qb, k + U);
-        __builtin_amdgcn_sched_barrier(0);
-        consume(qa, k);
-        issue(qa, k + 2 * U);
-        __builtin_amdgcn_sched_barrier(0);
-        consume(qb, k + U);
-    }
-}
-
-// Narrow owners (at most 32 rows): G = 64/P lane groups take tiles
-// k0+g, k0+g+G, ...  The task's inputs (times their column scales) are first
-// staged in this wave's LDS slice in tile order, so each lane reads its
-// group's inputs from LDS and the data prefetch is never drained.
-template <int DT, bool WIDE>
-__device__ __forceinline__ void stream_grouped(const DTask& tk, const DItem* __restrict__ items,
-                                               const uint8_t* __restrict__ sb, int64_t rt, int g, int G, int lane,
-                                               bool deferred, const double* __restrict__ vin,
-                                               const double* __restrict__ scales, const int64_t* __restrict__ dsrc,
-                                               const double* part, double* __restrict__ lw, double& a64,
-                                               float& a32) {
-    constexpr int V = Tile<DT>::V;
-    constexpr int U = 4;
-    const int k0 = tk.k0, k1 = tk.k1;
-    const int step = U * G;
-    uint4 qa[U], qb[U];
-    auto issue = [&](uint4* q, int kb) {
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            q[u] = *reinterpret_cast<const uint4*>(sb + (int64_t)min(kb + u * G + g, k1 - 1) * rt);
-    };
-    // the first tiles are requested before the inputs are staged, so both
-    // memory latencies overlap
-    issue(qa, k0);
-    stage_inputs<DT>(tk, items, lane, deferred, vin, scales, dsrc, part, lw);
-    auto consume = [&](const uint4* q, int kb) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int kk = kb + u * G + g;
-            if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw + (kk - k0) * V, a64, a32);
-        }
-    };
-    for (int k = k0; k < k1; k += 2 * step) {
-        issue(qb, k + step);
-        __builtin_amdgcn_sched_barrier(0);
-        consume(qa, k);
-        issue(qa, k + 2 * step);
-        __builtin_amdgcn_sched_barrier(0);
-        consume(qb, k + step);
-    }
-}
-
-template <int DT, bool ACC64>
-__device__ __forceinline__ void stream_task(const DTask& tk, const DItem* items, const uint8_t* sb, int64_t rt,
-                                            int g, int G, int lane, bool deferred, const double* vin,
-                                            const float* vin32, const double* scales, const int64_t* dsrc,
-                                            const double* part, double* lw, double& a64, float& a32) {
-    constexpr bool WIDE = ACC64 || DT == HM_F64;
-    if (G == 1) {
-        if (deferred)
-            stream_uniform<DT, WIDE, true>(tk, items, sb, rt, lane, vin, vin32, scales, dsrc, part, lw, a64, a32);
-        else
-            stream_uniform<DT, WIDE, false>(tk, items, sb, rt, lane, vin, vin32, scales, dsrc, part, lw, a64, a32);
-    } else {
-        stream_grouped<DT, WIDE>(tk, items, sb, rt, g, G, lane, deferred, vin, scales, dsrc, part, lw, a64, a32);
-    }
-}
-
-// One wavefront per task.  Lane geometry: P = rows per group (next power of
-// two >= nrows, at most 64), G = 64 / P column groups.  Tasks hold one dtype.
-// MASK: bit d set = tasks of dtype d may occur in the launched stage; the
-// host launches the instantiation whose mask is the stage's dtype set.
-template <bool ACC64, int MASK>
-__global__ __launch_bounds__(256) void k_owner_tasks(
-    const DTask* __restrict__ tasks, int ntasks, const DOwner* __restrict__ owners,
-    const DItem* __restrict__ items, const uint8_t* __restrict__ data, const double* __restrict__ scales,
-    const double* __restrict__ vin, const float* __restrict__ vin32, double* vout, float* vout32,
-    double* __restrict__ part, const int64_t* __restrict__ dsrc, double* __restrict__ y,
-    const int64_t* __restrict__ perm, double alpha) {
-    __shared__ double lds_w[4][MAX_TASK_INPUTS];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    // a grid smaller than the task count makes each wave walk tasks
-    // t, t + stride, ... (used to leave compute units to a concurrent stage)
-    for (int t = blockIdx.x * 4 + wave; t < ntasks; t += gridDim.x * 4) {
-    const DTask tk = tasks[t];
-    const int nrows = tk.nrows;
-    int lp = 0;                         // log2 P
-    while ((1 << lp) < nrows && lp < 6) ++lp;
-    const int P = 1 << lp;
-    const int G = 64 >> lp;
-    const int g = lane >> lp;
-    const int rl = lane & (P - 1);
-    const int dt = tk.dtype;   // in the descriptor: no dependent item load before the tiles
-    const int mode = tk.mode & 3;
-    const bool deferred = (tk.mode & 4) != 0;   // some inputs are unreduced sums
-    for (int r0 = 0; r0 < nrows; r0 += P) {
-        const int r = r0 + rl;
-        const bool act = r < nrows;
-        const int rr = act ? r : nrows - 1;   // idle lanes re-read a valid row
-        double a64 = 0.0;
-        float a32 = 0.0f;
-        const int64_t rt = (int64_t)nrows * 16;
-        const uint8_t* sb = data + tk.stream + (uint32_t)(rr * 16);
-        double* lw = lds_w[wave];
-        if constexpr ((MASK & (1 << HM_F64)) != 0)
-            if (dt == HM_F64)
-                stream_task<HM_F64, ACC64>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
-                                           a64, a32);
-        if constexpr ((MASK & (1 << HM_F32)) != 0)
-            if (dt == HM_F32)
-                stream_task<HM_F32, ACC64>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
-                                           a64, a32);
-        if constexpr ((MASK & (1 << HM_BF16)) != 0)
-            if (dt == HM_BF16)
-                stream_task<HM_BF16, ACC64>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
-                                            a64, a32);
-        if constexpr ((MASK & (1 << HM_F16)) != 0)
-            if (dt == HM_F16)
-                stream_task<HM_F16, ACC64>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
-                                           a64, a32);
-        if constexpr ((MASK & (1 << HM_FP8E4M3)) != 0)
-            if (dt == HM_FP8E4M3)
-                stream_task<HM_FP8E4M3, ACC64>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part,
-                                               lw, a64, a32);
-        double v = a64 + (double)a32;
-        for (int off = P; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);   // across column groups
-        if (act && g == 0) {
-            if (tk.rscale_off >= 0) v *= scales[tk.rscale_off + r];
-            if (tk.ntasks == 1)
-                finalize(mode, tk.out_off, r, v, vout, vout32, y, perm, alpha);
-            else
-                part[tk.part_off + (int64_t)tk.local * nrows + r] = v;
-        }
-    }
-    }
-}
 
 // Sum the partial results of split owners in a fixed order, one wave per owner.
 __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list, int nlist,
@@ -355,47 +42,15 @@ __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= nlist) return;
-    const DOwner ow = owners[list[i]];
-    // P lanes per row group (next power of two >= nrows, at most 64); the
-    // G = 64 / P groups take tasks g, g + G, ... with two independent sums
-    // each, combined across groups by shuffles (a fixed order: deterministic)
-    const int nrows = ow.nrows, nt = ow.ntasks;
-    int lp = 0;
-    while ((1 << lp) < nrows && lp < 6) ++lp;
-    const int P = 1 << lp, G = 64 >> lp, g = lane >> lp, rl = lane & (P - 1);
-    for (int r0 = 0; r0 < nrows; r0 += P) {
-        const int r = r0 + rl;
-        const bool act = r < nrows;
-        // y owners: the destination is read before the partial sums, so
-        // its latency overlaps theirs
-        double* yp = nullptr;
-        double y0 = 0.0;
-        if (act && g == 0 && ow.mode != 0) {
-            yp = y + (ow.mode == 1 && perm ? perm[ow.out_off + r] : (int64_t)(ow.out_off + r));
-            y0 = *yp;
-        }
-        // eight sums, each over every 8G-th partial: the loads of a pass are
-        // independent (missing ones read as zero)
-        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (act) {
-            const double* p = part + ow.part_off + r;
-            for (int l = g; l < nt; l += 8 * G) {
-                double q[8];
-#pragma unroll
-                for (int w = 0; w < 8; ++w) q[w] = l + w * G < nt ? p[(int64_t)(l + w * G) * nrows] : 0.0;
-#pragma unroll
-                for (int w = 0; w < 8; ++w) acc[w] += q[w];
-            }
-        }
-        double v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-        for (int off = P; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-        if (act && g == 0) {
-            if (yp)
-                *yp = y0 + alpha * v;
-            else
-                finalize(ow.mode, ow.out_off, r, v, vout, vout32, y, perm, alpha);
-        }
-    }
+    run_reduce<false>(owners[list[i]], lane, part, vout, vout32, y, perm, alpha);
+}
+
+extern const TaskKernel kTasks32lo[16], kTasks32hi[16], kTasks64lo[16], kTasks64hi[16];
+
+TaskKernel task_kernel(bool acc64, int mask) {
+    mask &= 31;
+    if (acc64) return mask < 16 ? kTasks64lo[mask] : kTasks64hi[mask - 16];
+    return mask < 16 ? kTasks32lo[mask] : kTasks32hi[mask - 16];
 }
 
 // x in cluster order: ws[i] = x[perm[i]]  (or a straight copy)
@@ -409,19 +64,6 @@ __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ x, co
         ws32[i] = (float)v;
     }
 }
-
-using TaskKernel = void (*)(const DTask*, int, const DOwner*, const DItem*, const uint8_t*, const double*,
-                           const double*, const float*, double*, float*, double*, const int64_t*, double*,
-                           const int64_t*, double);
-
-template <bool ACC64, int... M>
-constexpr std::array<TaskKernel, sizeof...(M)> task_kernels(std::integer_sequence<int, M...>) {
-    return {{&k_owner_tasks<ACC64, M>...}};
-}
-
-// [acc64][dtype mask]
-static const std::array<TaskKernel, 32> kTasks[2] = {task_kernels<false>(std::make_integer_sequence<int, 32>{}),
-                                                      task_kernels<true>(std::make_integer_sequence<int, 32>{})};
 
 }  // namespace dev
 
@@ -456,8 +98,23 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         return HM_ENOMEM;
     }
     if (st != HM_OK) return st;
+    // persistent schedule: the plan as one ticket queue
+    hm::Queue Q;
+    std::vector<int32_t> qorder;
+    const bool persist = opt.schedule == HM_SCHED_PERSISTENT;
+    if (persist) {
+        try {
+            st = hm::build_queue(P, layout->L.n, Q);
+            if (st == HM_OK) st = hm::queue_order(P.owners, Q.tasks, Q, opt.dense_after, qorder);
+        } catch (const std::bad_alloc&) {
+            hm::set_error("hm_upload: out of host memory while building the persistent queue");
+            return HM_ENOMEM;
+        }
+        if (st != HM_OK) return st;
+    }
 
     // one device allocation: metadata | perm | data | scales | workspace | partials
+    // | persistent queue tables and counters
     size_t meta = 0;
     const size_t o_owners = meta;
     meta = align256(meta + P.owners.size() * sizeof(hm::DOwner));
@@ -482,7 +139,15 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     size_t o_ws = align256(o_scales + P.scales.size() * sizeof(double));
     size_t o_ws32 = align256(o_ws + (P.ws_elems + hm::TILE_PAD) * sizeof(double));
     size_t o_part = align256(o_ws32 + (P.ws_elems + hm::TILE_PAD) * sizeof(float));
-    size_t total = align256(o_part + std::max<int64_t>(P.part_elems, 1) * sizeof(double));
+    size_t o_pq = align256(o_part + std::max<int64_t>(P.part_elems, 1) * sizeof(double));
+    const size_t o_ptasks = o_pq;
+    const size_t o_pdep0 = align256(o_ptasks + Q.tasks.size() * sizeof(hm::DTask));
+    const size_t o_pdeps = align256(o_pdep0 + Q.dep_first.size() * sizeof(int32_t));
+    const size_t o_ptarget = align256(o_pdeps + Q.deps.size() * sizeof(int32_t));
+    const size_t o_porder = align256(o_ptarget + Q.target.size() * sizeof(int32_t));
+    const size_t o_pdone = align256(o_porder + qorder.size() * sizeof(int32_t));
+    const size_t o_pctl = align256(o_pdone + (persist ? P.owners.size() : 0) * sizeof(int32_t));
+    size_t total = align256(o_pctl + (persist ? 256 : 0));
 
     hm_matrix* m = new (std::nothrow) hm_matrix();
     if (!m) {
@@ -519,6 +184,15 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     if (e == hipSuccess) e = copy(o_perm, layout->L.perm.data(), n * sizeof(int64_t));
     if (e == hipSuccess) e = copy(o_data, P.data.data(), P.data.size());
     if (e == hipSuccess) e = copy(o_scales, P.scales.data(), P.scales.size() * sizeof(double));
+    if (persist) {
+        if (e == hipSuccess) e = copy(o_ptasks, Q.tasks.data(), Q.tasks.size() * sizeof(hm::DTask));
+        if (e == hipSuccess) e = copy(o_pdep0, Q.dep_first.data(), Q.dep_first.size() * sizeof(int32_t));
+        if (e == hipSuccess) e = copy(o_pdeps, Q.deps.data(), Q.deps.size() * sizeof(int32_t));
+        if (e == hipSuccess) e = copy(o_ptarget, Q.target.data(), Q.target.size() * sizeof(int32_t));
+        if (e == hipSuccess) e = copy(o_porder, qorder.data(), qorder.size() * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemset(base + o_pdone, 0, P.owners.size() * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemset(base + o_pctl, 0, 256);
+    }
     // every workspace entry must hold a finite value before the first product:
     // zero-data padding columns multiply whatever they read
     if (e == hipSuccess) e = hipMemset(base + o_ws, 0, (P.ws_elems + hm::TILE_PAD) * sizeof(double));
@@ -559,6 +233,7 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         d.data_bytes = st.data_bytes;
         d.data_entries = st.data_entries;
         d.alg_bytes = st.alg_bytes;
+        d.method_bytes = st.method_bytes;
         d.name = st.name;
         nlaunch += (d.ntasks > 0) + (d.nreduce > 0);
         m->phases.push_back(d);
@@ -585,19 +260,67 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     m->h_stages = P.stages;
     m->ws_elems = P.ws_elems;
     m->part_elems = P.part_elems;
+    if (persist) {
+        m->schedule = HM_SCHED_PERSISTENT;
+        m->p_nq = (int32_t)qorder.size();
+        m->p_mask = Q.dtype_mask ? Q.dtype_mask : 1;
+        m->p_dense_after = opt.dense_after;
+        m->p_nowners = (int64_t)P.owners.size();
+        m->p_spin = (uint64_t)opt.spin_limit_us * 100;   // 100 MHz real-time counter
+        m->p_tasks = (const hm::DTask*)(base + o_ptasks);
+        m->p_dep_first = (const int32_t*)(base + o_pdep0);
+        m->p_deps = (const int32_t*)(base + o_pdeps);
+        m->p_target = (const int32_t*)(base + o_ptarget);
+        m->p_order = (int32_t*)(base + o_porder);
+        m->p_done = (int32_t*)(base + o_pdone);
+        m->p_ctl = (uint32_t*)(base + o_pctl);
+        // grid: as many workgroups as can be resident (the queue does not
+        // rely on it: later workgroups simply find fewer tickets)
+        const hm::dev::PersistKernel pk = hm::dev::persist_kernel(m->acc64 != 0, m->p_mask, nullptr);
+        int per_cu = 0, ncu = 0;
+        if (!pk || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)pk, 256, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess) {
+            hm_matrix_free(m);
+            hm::set_error("hm_upload: occupancy query of the persistent kernel failed");
+            return HM_EDEVICE;
+        }
+        m->p_grid = std::max(1, std::min(std::max(per_cu, 1) * std::max(ncu, 1), (m->p_nq + 3) / 4));
+        hm::DevStage d;
+        d.aux = false;
+        d.t0 = 0;
+        d.ntasks = m->p_nq;
+        d.nreduce = 0;
+        d.nowners = (int32_t)P.owners.size();
+        d.reduce = nullptr;
+        d.dtype_mask = m->p_mask;
+        d.data_bytes = d.data_entries = 0;
+        d.alg_bytes = d.method_bytes = 0.0;
+        for (const auto& st2 : P.stages) {
+            d.data_bytes += st2.data_bytes;
+            d.data_entries += st2.data_entries;
+            d.alg_bytes += st2.alg_bytes;
+            d.method_bytes += st2.method_bytes;
+        }
+        d.name = "persistent";
+        m->pphases.push_back(d);
+        Q.chain.shrink_to_fit();
+        m->p_queue = std::move(Q);
+    }
     if (nlaunch != P.stats.nlaunch) {
         hm_matrix_free(m);
         hm::set_error("hm_upload: launch count mismatch");
         return HM_ELAYOUT;
     }
+    if (persist) m->stats.nlaunch = 2;   // gather + the persistent launch
     *out = m;
     return HM_OK;
 }
 
 extern "C" void hm_matrix_free(hm_matrix* m) {
     if (!m) return;
-    for (auto& ph : m->phases)
-        for (auto& e : ph.pending) m->event_pool.push_back(e);
+    for (auto* list : {&m->phases, &m->pphases})
+        for (auto& ph : *list)
+            for (auto& e : ph.pending) m->event_pool.push_back(e);
     for (auto& e : m->event_pool) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
@@ -639,6 +362,36 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
     }
     const int cluster = (flags & HM_CLUSTER_ORDER) ? 1 : 0;
     const int64_t n = m->n;
+    if (m->schedule == HM_SCHED_PERSISTENT) {
+        const int64_t nth = std::max<int64_t>(n, m->p_nowners);
+        hipLaunchKernelGGL(hm::dev::k_gather_reset, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, stream, x,
+                           m->perm, m->ws, m->ws32, n, cluster, m->p_done, m->p_nowners, m->p_ctl);
+        const hm::dev::PersistKernel pk = hm::dev::persist_kernel(m->acc64 != 0, m->p_mask, nullptr);
+        const int64_t* permp = cluster ? nullptr : m->perm;
+        const dim3 grid((unsigned)m->p_grid), block(256);
+        if (flags & HM_TIMING) {
+            std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+            if (!hm::timing_acquire(m, m->pphases[0], 1, ev)) {
+                hm::set_error("hm_mvm: timing events failed");
+                return HM_EDEVICE;
+            }
+            hipExtLaunchKernelGGL(pk, grid, block, 0, stream, ev.first, ev.second, 0, (const int32_t*)m->p_order,
+                                  m->p_nq, m->p_dep_first, m->p_deps, m->p_target, m->p_done, m->p_ctl, m->p_spin,
+                                  m->p_tasks, m->owners, m->items, (const uint8_t*)m->data, (const double*)m->scales,
+                                  (const double*)m->ws, (const float*)m->ws32, m->ws, m->ws32, m->part,
+                                  (const int64_t*)m->dsrc, y, permp, alpha, (int)n);
+            m->pphases[0].pending.push_back(ev);
+        } else {
+            hipLaunchKernelGGL(pk, grid, block, 0, stream, (const int32_t*)m->p_order, m->p_nq, m->p_dep_first,
+                               m->p_deps, m->p_target, m->p_done, m->p_ctl, m->p_spin, m->p_tasks, m->owners,
+                               m->items, (const uint8_t*)m->data, (const double*)m->scales, (const double*)m->ws,
+                               (const float*)m->ws32, m->ws, m->ws32, m->part, (const int64_t*)m->dsrc, y, permp,
+                               alpha, (int)n);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail("hm_mvm: kernel launch", e);
+        return HM_OK;
+    }
     hipLaunchKernelGGL(hm::dev::k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, x, m->perm,
                        m->ws, m->ws32, n, cluster);
     const int64_t* perm = cluster ? nullptr : m->perm;
@@ -673,7 +426,7 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
             unsigned blocks = (unsigned)((ph.ntasks + 3) / 4);
             if (ph.aux && m->aux_grid > 0) blocks = std::min<unsigned>(blocks, (unsigned)m->aux_grid);
             dim3 grid(blocks);
-            const hm::dev::TaskKernel kern = hm::dev::kTasks[m->acc64 ? 1 : 0][ph.dtype_mask & 31];
+            const hm::dev::TaskKernel kern = hm::dev::task_kernel(m->acc64 != 0, ph.dtype_mask);
             if (timing) {
                 // the event pair is part of the dispatch: it brackets the
                 // kernel's execution, as a kernel trace does
@@ -712,13 +465,34 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
     return HM_OK;
 }
 
+extern "C" hm_status hm_matrix_check(hm_matrix* m) {
+    if (!m) {
+        hm::set_error("hm_matrix_check: null matrix");
+        return HM_EINVAL;
+    }
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail("hm_matrix_check: synchronize", e);
+    if (!m->p_ctl) return HM_OK;
+    uint32_t err = 0;
+    e = hipMemcpy(&err, m->p_ctl + 2, sizeof(err), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail("hm_matrix_check: read", e);
+    if (err != 0) {
+        e = hipMemset(m->p_ctl + 2, 0, sizeof(uint32_t));
+        if (e != hipSuccess) return hip_fail("hm_matrix_check: clear", e);
+        hm::set_error("hm_matrix_check: a persistent launch was aborted (a dependency wait exceeded its bound); "
+                      "its products are invalid");
+        return HM_EDEVICE;
+    }
+    return HM_OK;
+}
+
 extern "C" hm_status hm_timing_read(hm_matrix* m, hm_phase_timing* out, int32_t cap, int32_t* nphase) {
     if (!m || (cap > 0 && !out)) {
         hm::set_error("hm_timing_read: null argument");
         return HM_EINVAL;
     }
     int32_t i = 0;
-    for (auto* list : {&m->phases, &m->mr_phases})
+    for (auto* list : {&m->phases, &m->pphases, &m->mr_phases})
     for (auto& ph : *list) {
         double ms = 0.0;
         int64_t cnt = 0;
@@ -742,6 +516,7 @@ extern "C" hm_status hm_timing_read(hm_matrix* m, hm_phase_timing* out, int32_t 
             out[i].data_bytes = ph.data_bytes;
             out[i].data_entries = ph.data_entries;
             out[i].nrhs = ph.timed_nrhs;
+            out[i].method_bytes = ph.method_bytes;
         }
         ++i;
     }
@@ -808,6 +583,22 @@ extern "C" hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x
     });
 }
 
+// Reorder the persistent queue for another interleave point (host build,
+// then one copy of the order table; synchronous, outside graph capture).
+static hm_status set_dense_after(hm_matrix* m, int32_t dense_after) {
+    std::vector<int32_t> order;
+    hm_status st = hm::queue_order(m->h_owners, m->p_queue.tasks, m->p_queue, dense_after, order);
+    if (st != HM_OK) return st;
+    if ((int32_t)order.size() != m->p_nq) {
+        hm::set_error("hm_tune_mvm: queue size changed");
+        return HM_ELAYOUT;
+    }
+    hipError_t e = hipMemcpy(m->p_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail("hm_tune_mvm: queue copy", e);
+    m->p_dense_after = dense_after;
+    return HM_OK;
+}
+
 extern "C" hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream_, hm_tune_mvm_result* out) {
     if (!m || !out || reps < 1) {
         hm::set_error("hm_tune_mvm: null argument or reps < 1");
@@ -818,7 +609,7 @@ extern "C" hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream_
         hm::set_error("hm_tune_mvm: current device differs from the matrix's device");
         return HM_EINVAL;
     }
-    *out = hm_tune_mvm_result{0, 0, 0.0, 0.0};
+    *out = hm_tune_mvm_result{};
     int32_t nchain = 0;   // main-stream stages with tasks: the possible fork points are 0 ... nchain
     for (auto& ph : m->phases) nchain += !ph.aux && ph.ntasks > 0;
     const int32_t last = m->aux ? nchain : 0;
@@ -839,39 +630,82 @@ extern "C" hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream_
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     hm_status st = e == hipSuccess ? HM_OK : hip_fail("hm_tune_mvm: set-up", e);
-    const int32_t keep = m->fork_after;
-    int32_t best = keep;
+    // time one candidate: `reps` replays of a captured graph of the product
+    auto time_it = [&](double& t) -> hm_status {
+        hm_graph* g = nullptr;
+        hm_status s2 = hm_graph_create(m, 1.0, x, y, 0, stream_, &g);
+        if (s2 != HM_OK) return s2;
+        float ms = 0.0f;
+        hipError_t e2 = hipSuccess;
+        for (int i = 0; i < 2 && e2 == hipSuccess; ++i) e2 = hipGraphLaunch(g->exec, stream);   // warm-up
+        if (e2 == hipSuccess) e2 = hipEventRecord(e0, stream);
+        for (int i = 0; i < reps && e2 == hipSuccess; ++i) e2 = hipGraphLaunch(g->exec, stream);
+        if (e2 == hipSuccess) e2 = hipEventRecord(e1, stream);
+        if (e2 == hipSuccess) e2 = hipEventSynchronize(e1);
+        if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, e0, e1);
+        hm_graph_free(g);
+        if (e2 != hipSuccess) return hip_fail("hm_tune_mvm: timing", e2);
+        t = (double)ms / reps;
+        return HM_OK;
+    };
+    const int32_t keep_sched = m->schedule, keep_fork = m->fork_after, keep_da = m->p_dense_after;
+    int32_t best_sched = keep_sched, best_fork = keep_fork, best_da = keep_da;
     double best_ms = 0.0;
+    bool have = false;
+    // staged schedule: every fork point of the dense stage
+    m->schedule = HM_SCHED_STAGED;
     for (int32_t f = 0; f <= last && st == HM_OK; ++f) {
         m->fork_after = f;
-        hm_graph* g = nullptr;
-        st = hm_graph_create(m, 1.0, x, y, 0, stream_, &g);
+        double t = 0.0;
+        st = time_it(t);
         if (st != HM_OK) break;
-        float ms = 0.0f;
-        e = hipSuccess;
-        for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipGraphLaunch(g->exec, stream);   // warm-up
-        if (e == hipSuccess) e = hipEventRecord(e0, stream);
-        for (int i = 0; i < reps && e == hipSuccess; ++i) e = hipGraphLaunch(g->exec, stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        hm_graph_free(g);
-        if (e != hipSuccess) {
-            st = hip_fail("hm_tune_mvm: timing", e);
-            break;
-        }
-        const double t = (double)ms / reps;
         ++out->ncandidates;
         if (f == 0) out->ms_first = t;
-        if (f == 0 || t < best_ms) {
-            best = f;
+        if (out->ms_staged == 0.0 || t < out->ms_staged) out->ms_staged = t;
+        if (!have || t < best_ms) {
+            best_sched = HM_SCHED_STAGED;
+            best_fork = f;
             best_ms = t;
+            have = true;
         }
     }
-    m->fork_after = st == HM_OK ? best : keep;
+    m->fork_after = best_sched == HM_SCHED_STAGED ? best_fork : keep_fork;
+    // persistent schedule: interleave points of the dense tasks (at most 17,
+    // spread over 0 ... nchain of the queue)
+    if (m->p_ctl && st == HM_OK) {
+        m->schedule = HM_SCHED_PERSISTENT;
+        const int32_t nc = m->p_queue.nchain;
+        std::vector<int32_t> cand;
+        for (int32_t i = 0; i <= std::min(nc, 16); ++i) {
+            const int32_t v = nc <= 16 ? i : (int32_t)((int64_t)i * nc / 16);
+            if (cand.empty() || cand.back() != v) cand.push_back(v);
+        }
+        for (int32_t da : cand) {
+            st = set_dense_after(m, da);
+            double t = 0.0;
+            if (st == HM_OK) st = time_it(t);
+            if (st == HM_OK) st = hm_matrix_check(m);   // an aborted launch must not be chosen
+            if (st != HM_OK) break;
+            ++out->ncandidates;
+            if (out->ms_persistent == 0.0 || t < out->ms_persistent) out->ms_persistent = t;
+            if (!have || t < best_ms) {
+                best_sched = HM_SCHED_PERSISTENT;
+                best_da = da;
+                best_ms = t;
+                have = true;
+            }
+        }
+        if (st == HM_OK) st = set_dense_after(m, best_sched == HM_SCHED_PERSISTENT ? best_da : keep_da);
+    }
     if (st == HM_OK) {
-        out->fork_after = best;
+        m->schedule = best_sched;
+        out->schedule = best_sched;
+        out->fork_after = m->fork_after;
+        out->dense_after = m->p_dense_after;
         out->ms = best_ms;
+    } else {
+        m->schedule = keep_sched;
+        m->fork_after = keep_fork;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

@@ -158,7 +158,7 @@ def test_plan_launch_counts():
     counts = {}
     for tb in ("32768", "2000"):
         for fmt, v in vals.items():
-            counts[(tb, fmt)] = hm.plan_stats(lay, fmt, v, eps=1e-8, task_bytes=int(tb))["nlaunch"]
+            counts[(tb, fmt)] = hm.plan_stats(lay, fmt, v, eps=1e-8, task_bytes=int(tb), schedule="staged")["nlaunch"]
     assert counts[("32768", "uh")] == 1 + uh_stages + 1
     for fmt in vals:
         assert counts[("2000", fmt)] > counts[("32768", fmt)], fmt
@@ -212,3 +212,26 @@ def test_upload_options_are_validated():
     assert _lib.lib().hm_plan_stats(lay.handle, 0, ctypes.byref(v), ctypes.byref(prec), None,
                                     ctypes.byref(s)) == _lib.HM_OK
     assert s.nlaunch == hm.plan_stats(lay, "h", h, eps=1e-6)["nlaunch"]
+
+
+@pytest.mark.parametrize("tb", [0, 2000])
+def test_persistent_queue_plans(tb):
+    """hm_plan_stats builds the persistent queue exactly as hm_upload does and
+    checks its progress rule (every item after its producers); one product
+    is then two launches.  Every interleave point of the dense tasks gives a
+    valid order, for every format and storage policy."""
+    from synth import KERNEL_LAPLACE, compress_h, to_h2, to_uh
+    n = 2048
+    p = sphere_points(n, 1001)
+    st = trees.build_structure(p)
+    lay = hm.Layout(p)
+    h = compress_h(p, KERNEL_LAPLACE, st, 1e-6, method="svd")
+    vals = {"h": h, "uh": to_uh(h, st), "h2": to_h2(h, st)}
+    for fmt, v in vals.items():
+        for pol in (dict(), dict(dense="valr", diag="valr", factor="valr")):
+            staged = hm.plan_stats(lay, fmt, v, eps=1e-6, task_bytes=tb, schedule="staged", **pol)
+            for da in (0, 1, 3, 50):
+                s = hm.plan_stats(lay, fmt, v, eps=1e-6, task_bytes=tb, dense_after=da, **pol)
+                assert s["nlaunch"] == 2
+                assert s["method_bytes"] == staged["method_bytes"]
+                assert staged["nlaunch"] > 2

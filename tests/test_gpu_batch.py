@@ -258,3 +258,40 @@ def test_batch_maximum_width_and_beyond():
         with pytest.raises(hm.HMError):
             M.mvm_many(Xb, Yb)
         M.free()
+
+
+def test_stale_batch_graph_is_refused():
+    """A batch graph holds device addresses of its matrix's many-RHS
+    workspace: after a wider product regrows that workspace the graph is
+    refused (HM_EINVAL) before anything is launched, and a graph captured
+    afterwards replays correctly."""
+    import torch
+    import paper_2405_03456_amd as hm
+    from paper_2405_03456_amd import _lib
+    st, lay, vals = case()
+    print("case stale batch graph h n=2048 r=16 -> 64", flush=True)
+    pol, tol = POLICIES["f32"]
+    M = hm.Matrix(lay, "h", vals["h"], **pol)
+    X = gaussian_matrix(st.n, 64, 77)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda().T
+    Y16 = torch.zeros((16, st.n), dtype=torch.float64, device="cuda").T
+    g = hm.BatchGraph([M], [Xd[:, :16]], [Y16])
+    g.launch()
+    Y64 = torch.zeros((64, st.n), dtype=torch.float64, device="cuda").T
+    hm.mvm_batch([M], [Xd], [Y64])              # grows the workspace to 64 columns
+    torch.cuda.synchronize()
+    before = Y16.clone()
+    with pytest.raises(hm.HMError) as ex:
+        g.launch()
+    assert ex.value.status == _lib.HM_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(before, Y16)              # nothing ran
+    g.free()
+    g2 = hm.BatchGraph([M], [Xd[:, :16]], [Y16])
+    g2.launch()
+    torch.cuda.synchronize()
+    sv = stored.stored_values(st, "h", vals["h"], dense=pol["dense"], factor=pol["factor"], eps=pol["eps"])
+    ref = stored.product_many(st, "h", sv, 1.0, X[:, :16], np.zeros((st.n, 16)))
+    assert colerr(Y16.cpu().numpy() / 2.0, ref, 0.0) <= tol
+    g2.free()
+    M.free()

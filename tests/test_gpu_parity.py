@@ -172,3 +172,27 @@ def test_parity_small_tasks(fmt, pol):
     out = run_gpu(lay, fmt, vals[fmt], x, y, 0.75, task_bytes=2000, **pp)
     tol = TOL64 if pol in ACC64 else TOL32
     assert rel(out, ref, y) <= tol
+
+
+@pytest.mark.parametrize("fmt", ["h", "uh", "h2"])
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_valr_tile_promotion_within_budget(fmt, eps):
+    """The library's optional tile promotion (valr_promote) stores some
+    columns more precisely than Sec. 4.2 asks.  Its product is checked
+    against the oracle's paper rule (every column in its own cheapest
+    format): the two stored matrices differ by at most the VALR budgets, so
+    the products agree within a small multiple of eps (eq. 6 / eq. 7), as
+    does the promoted product and the float64 product."""
+    n = 2048
+    p, st, lay, vals = make(n, 1e-8)
+    print(f"case valr promotion {fmt} eps={eps:g}", flush=True)
+    x, y = gaussian_vector(n, 2201), gaussian_vector(n, 3201)
+    pol = dict(dense="valr", diag="valr", factor="valr", eps=eps)
+    sv = stored.stored_values(st, fmt, vals[fmt], **pol)
+    ref = stored.product(st, fmt, sv, 1.0, x, y)
+    exact = stored.product(st, fmt, vals[fmt], 1.0, x, y)
+    out = run_gpu(lay, fmt, vals[fmt], x, y, 1.0, valr_promote=True, **pol)
+    plain = run_gpu(lay, fmt, vals[fmt], x, y, 1.0, **pol)
+    assert rel(plain, ref, y) <= TOL32                       # paper rule: parity
+    assert rel(out, ref, y) <= 3.0 * eps                     # promotion: within the budget
+    assert rel(out, exact, y) <= 3.0 * eps                   # ... of the float64 product too
