@@ -128,9 +128,11 @@ def test_identity_kernel_rank_zero_blocks():
 
 @pytest.mark.parametrize("fmt", ["uh", "h2"])
 def test_tune_mvm_keeps_results_bitwise(fmt):
-    """hm_tune_mvm times every fork point of the dense stage and keeps the
-    fastest; the fork point moves work in time only, so eager products and
-    graph replays after tuning equal the untuned product bit for bit."""
+    """hm_tune_mvm times every fork point of the dense stage (staged
+    schedule) and a spread of interleave points of the dense tasks
+    (persistent schedule) and keeps the fastest; both move work in time
+    only, so eager products and graph replays after tuning equal the untuned
+    product bit for bit."""
     import paper_2405_03456_amd as hm
     torch = torch_cuda()
     n = 2048
@@ -141,10 +143,13 @@ def test_tune_mvm_keeps_results_bitwise(fmt):
     y0 = torch.from_numpy(y.copy()).cuda()
     M.mvm(xd, y0, alpha=0.5)
     r = M.tune_mvm(reps=3)
-    # one candidate per fork point 0 ... number of chain stages with tasks
-    nchain = sum(1 for ph in M.timing() if ph["ntasks"] > 0 and ph["name"] != "dense")
-    assert r["ncandidates"] == nchain + 1 and 0 <= r["fork_after"] < r["ncandidates"]
-    assert r["ms"] > 0 and r["ms"] <= r["ms_first"]
+    # staged: one candidate per fork point 0 ... number of chain stages with
+    # tasks; persistent: at most 17 interleave points
+    nchain = sum(1 for ph in M.timing() if ph["ntasks"] > 0 and ph["name"] not in ("dense", "persistent"))
+    assert nchain + 2 <= r["ncandidates"] <= nchain + 1 + 17 and 0 <= r["fork_after"] <= nchain
+    assert r["ms"] > 0 and r["ms"] <= r["ms_first"] and r["ms"] == min(r["ms_staged"], r["ms_persistent"])
+    assert r["schedule"] == ("staged" if r["ms"] == r["ms_staged"] else "persistent")
+    M.check()
     y1 = torch.from_numpy(y.copy()).cuda()
     M.mvm(xd, y1, alpha=0.5)
     y2 = torch.from_numpy(y.copy()).cuda()
