@@ -314,6 +314,32 @@ hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double alpha, const
                        const int64_t* ldx, const int32_t* nrhs, void* const* Y, const int64_t* ldy,
                        int32_t vec_dtype, uint32_t flags, hm_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * products as hm_mvm_batch, bitwise, with every many-RHS workspace taken
+ * from one library-owned device array of HM_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * instead of the matrices' own workspaces.  The call allocates nothing: no
+ * hipMalloc, hipFree or allocating library routine.
+ *   - Limit: the workspaces of one call (for matrix i, about
+ *     (12 * (coefficient entries + n_i) + 8 * (n_i + partial sums)) * R_i
+ *     bytes, R_i = nrhs[i] rounded up to 16 or a multiple of 32) must fit the
+ *     array together; a larger call fails with HM_EINVAL before launching.
+ *   - Every matrix with more than one column (or float32 vectors) needs its
+ *     many-RHS plan already built (hm_tune_batch, or one earlier
+ *     hm_mvm_batch call), else HM_EINVAL.  Single float64 columns run the
+ *     hm_mvm kernels on the matrix's own workspace, as in hm_mvm_batch.
+ *   - HM_TIMING is not accepted (timing events are allocated).
+ *   - Each GPU has one array, shared by every call on it and holding the
+ *     last call's contents; each call clears the part it uses before its
+ *     products.  Calls that overlap in time on one GPU (on different streams
+ *     or from different threads) race on the array and give wrong results:
+ *     serialise them.
+ * Arguments, layouts and the other errors are those of hm_mvm_batch. */
+#define HM_NOALLOC_SCRATCH_BYTES (64ll << 20)
+hm_status hm_mvm_batch_noalloc(hm_matrix* const* mats, int32_t nmat, double alpha, const void* const* X,
+                               const int64_t* ldx, const int32_t* nrhs, void* const* Y, const int64_t* ldy,
+                               int32_t vec_dtype, uint32_t flags, hm_stream_t stream);
+
 /* Autotuner of the many-right-hand-side path.  The engine's two free
  * parameters are the column-chunk size of a task (bytes of stored data per
  * 64-row group: 64 KiB ... 1 MiB) and the number of 16-wide right-hand-side

@@ -314,6 +314,15 @@ def mvm_batch(mats, X, Y, alpha: float = 1.0, cluster_order: bool = False, strea
                                        _stream_ptr(stream)))
 
 
+def mvm_batch_noalloc(mats, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None):
+    """hm_mvm_batch_noalloc: the products of mvm_batch with the workspaces
+    taken from the library's fixed device array (nothing is allocated)."""
+    k, hs, xs, ldx, nr, ys, ldy, vdt = _marshal_batch(mats, X, Y)
+    flags = HM_CLUSTER_ORDER if cluster_order else 0
+    _lib.check(_lib.lib().hm_mvm_batch_noalloc(hs, k, float(alpha), xs, ldx, nr, ys, ldy, vdt, flags,
+                                               _stream_ptr(stream)))
+
+
 class BatchGraph:
     """hm_graph_create_batch: one captured hm_mvm_batch call, replayed with launch()."""
 

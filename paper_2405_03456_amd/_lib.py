@@ -126,6 +126,8 @@ SIGNATURES = {
     "hm_matrix_check": (c_int32, [c_void_p]),
     "hm_mvm_batch": (c_int32, [P(c_void_p), c_int32, c_double, P(c_void_p), P(c_int64), P(c_int32),
                                P(c_void_p), P(c_int64), c_int32, c_uint32, c_void_p]),
+    "hm_mvm_batch_noalloc": (c_int32, [P(c_void_p), c_int32, c_double, P(c_void_p), P(c_int64), P(c_int32),
+                                       P(c_void_p), P(c_int64), c_int32, c_uint32, c_void_p]),
     "hm_graph_create": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p, P(c_void_p)]),
     "hm_tune_batch": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, P(TuneResult)]),
     "hm_tune_mvm": (c_int32, [c_void_p, c_int32, c_void_p, P(TuneMvmResult)]),

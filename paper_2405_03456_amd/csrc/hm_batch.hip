@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -636,6 +637,16 @@ static hm_status ensure_mr_plan(hm_matrix* m, int64_t target) {
     return HM_OK;
 }
 
+// Byte layout of a many-RHS workspace of R values per entry:
+// wsm | wsm32 | ym | partm, each 256-byte aligned; returns the total.
+static size_t mr_ws_layout(const hm_matrix* m, int R, size_t& o_wsm32, size_t& o_ym, size_t& o_part) {
+    const size_t ent = (size_t)(m->ws_elems + TILE_PAD);
+    o_wsm32 = align256(ent * R * sizeof(double));
+    o_ym = align256(o_wsm32 + ent * R * sizeof(float));
+    o_part = align256(o_ym + (size_t)m->n * R * sizeof(double));
+    return align256(o_part + (size_t)std::max<int64_t>(m->mr_part_elems, 1) * R * sizeof(double));
+}
+
 // Grow the matrix's many-RHS workspace to R values per entry.
 static hm_status ensure_mr(hm_matrix* m, int R) {
     hm_status st = ensure_mr_plan(m, m->mr_target ? m->mr_target : kDefaultMrTarget);
@@ -648,12 +659,9 @@ static hm_status ensure_mr(hm_matrix* m, int R) {
         m->mr_arena = nullptr;
         m->mr_cap = 0;
     }
-    const size_t ent = (size_t)(m->ws_elems + TILE_PAD);
+    size_t o_wsm32, o_ym, o_part;
+    const size_t total = mr_ws_layout(m, R, o_wsm32, o_ym, o_part);
     const size_t o_wsm = 0;
-    const size_t o_wsm32 = align256(o_wsm + ent * R * sizeof(double));
-    const size_t o_ym = align256(o_wsm32 + ent * R * sizeof(float));
-    const size_t o_part = align256(o_ym + (size_t)m->n * R * sizeof(double));
-    const size_t total = align256(o_part + (size_t)std::max<int64_t>(m->mr_part_elems, 1) * R * sizeof(double));
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, total);
     if (e != hipSuccess) {
@@ -687,21 +695,38 @@ static int stage_nrb(const hm_matrix* m, const DevStage& ph, int R) {
     return (R >= 32 && want == 2) ? 2 : 1;
 }
 
+// The many-RHS workspace one call uses: the matrix's own (grown on demand)
+// or a caller-provided region of the same layout.
+struct MrWs {
+    double* wsm;
+    float* wsm32;
+    double* ym;
+    double* partm;
+};
+
+static hm_status mvm_many_ws(hm_matrix* m, const MrWs& ws, double alpha, const void* X, int64_t ldx, int nrhs,
+                             void* Y, int64_t ldy, int32_t vdt, uint32_t flags, hipStream_t stream);
+
 static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx, int nrhs, void* Y, int64_t ldy,
                           int32_t vdt, uint32_t flags, hipStream_t stream) {
-    const int R = padded_width(nrhs);
-    hm_status st = ensure_mr(m, R);
+    hm_status st = ensure_mr(m, padded_width(nrhs));
     if (st != HM_OK) return st;
+    return mvm_many_ws(m, MrWs{m->wsm, m->wsm32, m->ym, m->partm}, alpha, X, ldx, nrhs, Y, ldy, vdt, flags, stream);
+}
+
+static hm_status mvm_many_ws(hm_matrix* m, const MrWs& ws, double alpha, const void* X, int64_t ldx, int nrhs,
+                             void* Y, int64_t ldy, int32_t vdt, uint32_t flags, hipStream_t stream) {
+    const int R = padded_width(nrhs);
     const int64_t n = m->n;
     const int64_t* perm = (flags & HM_CLUSTER_ORDER) ? nullptr : m->mr_iperm;
     const bool timing = (flags & HM_TIMING) != 0;
     dim3 tgrid((unsigned)((n + 63) / 64), (unsigned)((R + 63) / 64));
     if (vdt == HM_F64)
         hipLaunchKernelGGL(mr::k_gather<double>, tgrid, dim3(256), 0, stream, (const double*)X, ldx, nrhs, perm, n, R,
-                           m->wsm, m->wsm32, m->ym);
+                           ws.wsm, ws.wsm32, ws.ym);
     else
         hipLaunchKernelGGL(mr::k_gather<float>, tgrid, dim3(256), 0, stream, (const float*)X, ldx, nrhs, perm, n, R,
-                           m->wsm, m->wsm32, m->ym);
+                           ws.wsm, ws.wsm32, ws.ym);
     const hipStream_t main_stream = stream;
     if (m->aux) {
         (void)hipEventRecord(m->ev_fork, main_stream);
@@ -731,14 +756,14 @@ static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx
                 const int64_t w = (int64_t)sb.ntasks * nblk;
                 hipLaunchKernelGGL(mr::kTasks[m->acc64 ? 1 : 0][nrb - 1][var], dim3((unsigned)((w + 3) / 4)),
                                    dim3(256), 0, s, m->mr_tasks + ph.t0 + sb.t0, sb.ntasks, nblk, m->items, m->data,
-                                   m->scales, m->wsm, m->wsm32, m->ym, m->partm, R, n);
+                                   m->scales, ws.wsm, ws.wsm32, ws.ym, ws.partm, R, n);
             }
             if (timing) timing_end(ph, s, ev);
         }
         if (ph.nreduce > 0)
             hipLaunchKernelGGL(mr::k_reduce,
                                dim3((unsigned)ph.nreduce, (unsigned)(((int64_t)ph.reduce_rows * R + 255) / 256)),
-                               dim3(256), 0, s, ph.reduce, m->mr_owners, m->partm, m->wsm, m->wsm32, m->ym, R,
+                               dim3(256), 0, s, ph.reduce, m->mr_owners, ws.partm, ws.wsm, ws.wsm32, ws.ym, R,
                                m->acc64 ? 1 : 0);
     }
     if (!joined) {
@@ -747,10 +772,10 @@ static hm_status mvm_many(hm_matrix* m, double alpha, const void* X, int64_t ldx
     }
     if (vdt == HM_F64)
         hipLaunchKernelGGL(mr::k_scatter<double>, tgrid, dim3(256), 0, main_stream, (double*)Y, ldy, nrhs, perm, n, R,
-                           m->ym, alpha);
+                           ws.ym, alpha);
     else
         hipLaunchKernelGGL(mr::k_scatter<float>, tgrid, dim3(256), 0, main_stream, (float*)Y, ldy, nrhs, perm, n, R,
-                           m->ym, alpha);
+                           ws.ym, alpha);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail("hm_mvm_batch: kernel launch", e);
     return HM_OK;
@@ -1098,5 +1123,130 @@ extern "C" hm_status hm_tune_batch(hm_matrix* m, int32_t nrhs, int32_t vec_dtype
     if (st != HM_OK) return st;
     for (size_t i = 0; i < m->mr_phases.size() && i < best_nrb.size(); ++i) m->mr_phases[i].mr_nrb = best_nrb[i];
     if (out) *out = best;
+    return HM_OK;
+}
+
+// ------------------------------------------------- no-allocation variant
+//
+// hm_mvm_batch_noalloc: the many-RHS products of hm_mvm_batch with their
+// workspaces carved out of one file-scope device array instead of the
+// matrices' own (grown by hipMalloc).  Each GPU holds its own copy of the
+// array for the life of the process; host code addresses it only through
+// the device address hipGetSymbolAddress returns for the current device.
+
+static __device__ __align__(256) uint8_t scratch[HM_NOALLOC_SCRATCH_BYTES];
+
+namespace hm {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+hm_status scratch_address(int dev, uint8_t** out) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("hm_mvm_batch_noalloc: device index out of range");
+        return HM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail("hm_mvm_batch_noalloc: hipGetSymbolAddress(scratch)", e);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (uint8_t*)g_scratch_ptr[dev];
+    return HM_OK;
+}
+
+// Zero n16 16-byte words (the workspace of one call starts from zeros).
+__global__ __launch_bounds__(256) void k_zero16(uint4* __restrict__ p, int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+}  // namespace
+}  // namespace hm
+
+extern "C" hm_status hm_mvm_batch_noalloc(hm_matrix* const* mats, int32_t nmat, double alpha, const void* const* X,
+                                          const int64_t* ldx, const int32_t* nrhs, void* const* Y,
+                                          const int64_t* ldy, int32_t vec_dtype, uint32_t flags,
+                                          hm_stream_t stream) {
+    if (nmat < 0 || (nmat > 0 && (!mats || !X || !ldx || !nrhs || !Y || !ldy))) {
+        hm::set_error("hm_mvm_batch_noalloc: null argument");
+        return HM_EINVAL;
+    }
+    if (vec_dtype != HM_F64 && vec_dtype != HM_F32) {
+        hm::set_error("hm_mvm_batch_noalloc: vec_dtype must be HM_F64 or HM_F32");
+        return HM_EINVAL;
+    }
+    if (flags & ~(uint32_t)HM_CLUSTER_ORDER) {
+        hm::set_error("hm_mvm_batch_noalloc: unsupported flags (HM_TIMING allocates events)");
+        return HM_EINVAL;
+    }
+    if (nmat == 0) return HM_OK;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        hm::set_error("hm_mvm_batch_noalloc: no current device");
+        return HM_EDEVICE;
+    }
+    // validate everything and lay the workspaces out before any launch
+    std::vector<size_t> off((size_t)nmat, 0);
+    size_t total = 0;
+    for (int32_t i = 0; i < nmat; ++i) {
+        const hm_matrix* m = mats[i];
+        if (!m || nrhs[i] < 0 || nrhs[i] > HM_MAX_NRHS) {
+            hm::set_error("hm_mvm_batch_noalloc: null matrix or nrhs out of [0, HM_MAX_NRHS] at index " +
+                          std::to_string(i));
+            return HM_EINVAL;
+        }
+        if (nrhs[i] == 0) continue;
+        if (!X[i] || !Y[i] || X[i] == Y[i] || ldx[i] < m->n || ldy[i] < m->n || m->device != dev) {
+            hm::set_error("hm_mvm_batch_noalloc: bad X/Y, leading dimension or device at index " + std::to_string(i));
+            return HM_EINVAL;
+        }
+        for (int32_t k = 0; k < i; ++k)
+            if (mats[k] == m && nrhs[k] > 0) {
+                hm::set_error("hm_mvm_batch_noalloc: a matrix appears twice");
+                return HM_EINVAL;
+            }
+        if (nrhs[i] == 1 && vec_dtype == HM_F64) continue;   // single-vector kernels: the matrix's own workspace
+        if (!m->mr_meta) {
+            hm::set_error("hm_mvm_batch_noalloc: the many-RHS plan of matrix " + std::to_string(i) +
+                          " is not built (call hm_tune_batch or hm_mvm_batch once beforehand)");
+            return HM_EINVAL;
+        }
+        size_t o1, o2, o3;
+        off[(size_t)i] = total;
+        total += hm::mr_ws_layout(m, hm::padded_width(nrhs[i]), o1, o2, o3);
+    }
+    if (total > (size_t)HM_NOALLOC_SCRATCH_BYTES) {
+        hm::set_error("hm_mvm_batch_noalloc: the workspaces need " + std::to_string(total) +
+                      " bytes, more than HM_NOALLOC_SCRATCH_BYTES = " + std::to_string((long long)HM_NOALLOC_SCRATCH_BYTES));
+        return HM_EINVAL;
+    }
+    uint8_t* base = nullptr;
+    hm_status st = hm::scratch_address(dev, &base);
+    if (st != HM_OK) return st;
+    const hipStream_t s = (hipStream_t)stream;
+    if (total > 0) {
+        const int64_t n16 = (int64_t)(total / 16);
+        hipLaunchKernelGGL(hm::k_zero16, dim3((unsigned)std::min<int64_t>((n16 + 255) / 256, 4096)), dim3(256), 0, s,
+                           (uint4*)base, n16);
+    }
+    for (int32_t i = 0; i < nmat; ++i) {
+        if (nrhs[i] == 0) continue;
+        if (nrhs[i] == 1 && vec_dtype == HM_F64) {
+            st = hm_mvm(mats[i], alpha, (const double*)X[i], (double*)Y[i], flags, stream);
+        } else {
+            size_t o_wsm32, o_ym, o_part;
+            (void)hm::mr_ws_layout(mats[i], hm::padded_width(nrhs[i]), o_wsm32, o_ym, o_part);
+            uint8_t* b = base + off[(size_t)i];
+            const hm::MrWs ws{(double*)b, (float*)(b + o_wsm32), (double*)(b + o_ym), (double*)(b + o_part)};
+            st = hm::mvm_many_ws(mats[i], ws, alpha, X[i], ldx[i], nrhs[i], Y[i], ldy[i], vec_dtype, flags, s);
+        }
+        if (st != HM_OK) return st;
+    }
     return HM_OK;
 }
