@@ -211,15 +211,18 @@ typedef struct {
     int32_t dense_grid;
     int32_t fork_after;
     int32_t valr_promote;
-    int32_t schedule;       /* HM_SCHED_PERSISTENT (default) or HM_SCHED_STAGED, see hm_mvm */
+    int32_t schedule;       /* HM_SCHED_STAGED (default) or HM_SCHED_PERSISTENT (also builds the
+                               persistent queue, so hm_tune_mvm can time both), see hm_mvm */
     int32_t dense_after;    /* persistent schedule: first boundary between dependent stages from
                                which the dense near-field tasks are interleaved (see hm_tune_mvm) */
     int32_t spin_limit_us;  /* persistent schedule: bound of one dependency wait in microseconds
                                (0 = 2 000 000); a wait past it aborts the launch (hm_matrix_check) */
+    int32_t tickets_per_grab; /* persistent schedule: queue items a wavefront takes per atomic
+                                 (0 = 4, at most 256) */
 } hm_upload_opts;
 
-#define HM_SCHED_PERSISTENT 0
-#define HM_SCHED_STAGED 1
+#define HM_SCHED_STAGED 0
+#define HM_SCHED_PERSISTENT 1
 
 /* Quantise on the host per `prec`, pack into level- and row-cluster-ordered
  * streams and copy to the current HIP device.  opts may be NULL (defaults).
@@ -394,6 +397,14 @@ hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream, hm_tune_mv
  * Replays read x and update y in place exactly like hm_mvm; results are
  * bitwise identical to the eager call.  The matrix must outlive the graph.
  * The graph records no memset nodes.  Errors: HM_EINVAL, HM_EDEVICE. */
+/* Sets the single-vector schedule of a matrix without timing anything:
+ * HM_SCHED_STAGED with param = fork point (0 ... number of dependent
+ * stages), or HM_SCHED_PERSISTENT with param = dense_after (any value >= 0;
+ * a matrix uploaded with HM_SCHED_STAGED has no persistent queue).  Changes
+ * no arithmetic.  Synchronous (the queue order is copied); not inside graph
+ * capture.  Errors: HM_EINVAL, HM_ELAYOUT, HM_EDEVICE. */
+hm_status hm_set_schedule(hm_matrix* m, int32_t schedule, int32_t param);
+
 typedef struct hm_graph hm_graph;
 hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x, double* y, uint32_t flags,
                           hm_stream_t stream, hm_graph** out);

@@ -148,11 +148,12 @@ SCHEDULES = {"persistent": _lib.HM_SCHED_PERSISTENT, "staged": _lib.HM_SCHED_STA
 
 
 def make_opts(task_bytes: int = 0, spread_dense: bool = False, dense_grid: int = 0, fork_after: int = 0,
-              valr_promote: bool = False, schedule: str = "persistent", dense_after: int = 0,
-              spin_limit_us: int = 0):
+              valr_promote: bool = False, schedule: str = "staged", dense_after: int = 0,
+              spin_limit_us: int = 0, tickets_per_grab: int = 0):
     """hm_upload_opts (all zero = the library's defaults)."""
     return _lib.UploadOpts(int(task_bytes), int(bool(spread_dense)), int(dense_grid), int(fork_after),
-                           int(bool(valr_promote)), SCHEDULES[schedule], int(dense_after), int(spin_limit_us))
+                           int(bool(valr_promote)), SCHEDULES[schedule], int(dense_after), int(spin_limit_us),
+                           int(tickets_per_grab))
 
 
 def _stats_dict(s) -> dict:
@@ -236,6 +237,11 @@ class Matrix:
         return dict(fork_after=r.fork_after, ncandidates=r.ncandidates, ms=r.ms, ms_first=r.ms_first,
                     schedule="persistent" if r.schedule == _lib.HM_SCHED_PERSISTENT else "staged",
                     dense_after=r.dense_after, ms_staged=r.ms_staged, ms_persistent=r.ms_persistent)
+
+    def set_schedule(self, schedule: str, param: int = 0):
+        """hm_set_schedule: "staged" (param = fork point) or "persistent"
+        (param = dense_after)."""
+        _lib.check(_lib.lib().hm_set_schedule(self._h, SCHEDULES[schedule], int(param)))
 
     def check(self):
         """Wait for the device; raise if a persistent launch of this matrix

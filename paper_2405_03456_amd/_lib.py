@@ -46,13 +46,13 @@ class LayoutInfo(ctypes.Structure):
                 ("lowrank_area_per_level", c_double * HM_MAX_LEVELS)]
 
 
-HM_SCHED_PERSISTENT, HM_SCHED_STAGED = 0, 1
+HM_SCHED_STAGED, HM_SCHED_PERSISTENT = 0, 1
 
 
 class UploadOpts(ctypes.Structure):
     _fields_ = [("task_bytes", c_int64), ("spread_dense", c_int32), ("dense_grid", c_int32),
                 ("fork_after", c_int32), ("valr_promote", c_int32), ("schedule", c_int32),
-                ("dense_after", c_int32), ("spin_limit_us", c_int32)]
+                ("dense_after", c_int32), ("spin_limit_us", c_int32), ("tickets_per_grab", c_int32)]
 
 
 class Values(ctypes.Structure):
@@ -124,6 +124,7 @@ SIGNATURES = {
     "hm_plan_stats": (c_int32, [c_void_p, c_int32, P(Values), P(Precision), P(UploadOpts), P(Stats)]),
     "hm_mvm": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_uint32, c_void_p]),
     "hm_matrix_check": (c_int32, [c_void_p]),
+    "hm_set_schedule": (c_int32, [c_void_p, c_int32, c_int32]),
     "hm_mvm_batch": (c_int32, [P(c_void_p), c_int32, c_double, P(c_void_p), P(c_int64), P(c_int32),
                                P(c_void_p), P(c_int64), c_int32, c_uint32, c_void_p]),
     "hm_mvm_batch_noalloc": (c_int32, [P(c_void_p), c_int32, c_double, P(c_void_p), P(c_int64), P(c_int32),

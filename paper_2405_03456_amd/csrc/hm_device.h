@@ -74,15 +74,25 @@ template <> struct Tile<HM_F16> {
         }
     }
 };
+// gfx950 widens OCP E4M3 pairs in hardware (v_cvt_pk_f32_fp8: the low or
+// high 16-bit half of a word), exact for every finite code.
+__device__ __forceinline__ void fp8x4_to_f32(uint32_t w, float* o) {
+    const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+    const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+    o[0] = lo[0];
+    o[1] = lo[1];
+    o[2] = hi[0];
+    o[3] = hi[1];
+}
+
 template <> struct Tile<HM_FP8E4M3> {
     static constexpr int V = 16;
     using R = float;
     __device__ static void decode(const uint4& q, R* o) {
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) o[4 * i + b] = fp8_to_f32((uint8_t)(w[i] >> (8 * b)));
+        fp8x4_to_f32(q.x, o);
+        fp8x4_to_f32(q.y, o + 4);
+        fp8x4_to_f32(q.z, o + 8);
+        fp8x4_to_f32(q.w, o + 12);
     }
 };
 
@@ -171,6 +181,7 @@ struct hm_matrix {
     int32_t p_mask = 0;          // dtypes of the tasks
     int32_t p_grid = 0;          // workgroups of the persistent launch
     int32_t p_dense_after = 0;
+    int32_t p_grab = 1;          // tickets a wave takes per atomic
     int64_t p_nowners = 0;
     uint64_t p_spin = 0;         // bound of a dependency wait, 100 MHz ticks
     const hm::DTask* p_tasks = nullptr;

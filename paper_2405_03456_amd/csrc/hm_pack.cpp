@@ -1445,6 +1445,11 @@ hm_status pack_options(const hm_upload_opts* o, PackOptions& opt) {
                   "than 0 / 1, or an unknown schedule");
         return HM_EINVAL;
     }
+    if (o->tickets_per_grab < 0 || o->tickets_per_grab > 256) {
+        set_error("hm_upload: tickets_per_grab must be in [0, 256]");
+        return HM_EINVAL;
+    }
+    if (o->tickets_per_grab) opt.tickets_per_grab = o->tickets_per_grab;
     opt.schedule = o->schedule;
     opt.dense_after = o->dense_after;
     if (o->spin_limit_us) opt.spin_limit_us = o->spin_limit_us;

@@ -10,9 +10,10 @@ struct PackOptions {
     int64_t task_bytes = 32768;   // target matrix bytes per task (one wavefront)
     bool concurrent_dense = true; // dense leaves as one independent stage (else spread over the stages)
     bool valr_promote = false;    // VALR: fill the 16-byte tiles of short format runs (see valr_formats)
-    int32_t schedule = HM_SCHED_PERSISTENT;
+    int32_t schedule = HM_SCHED_STAGED;
     int32_t dense_after = 0;      // persistent schedule: interleave point of the dense tasks
     int64_t spin_limit_us = 2000000;
+    int32_t tickets_per_grab = 4;
 };
 
 // Validated PackOptions from the ABI's hm_upload_opts (NULL = defaults).

@@ -63,7 +63,13 @@ __device__ __forceinline__ bool wait_owners(OwnerOf owner_of, int nlist, const i
                 }
                 return false;
             }
-            __builtin_amdgcn_s_sleep(2);
+            // back off: waiting waves keep polling traffic low
+            if (spin < 8)
+                __builtin_amdgcn_s_sleep(2);
+            else if (spin < 64)
+                __builtin_amdgcn_s_sleep(16);
+            else
+                __builtin_amdgcn_s_sleep(127);
         }
     }
     return true;
@@ -77,14 +83,22 @@ __global__ __launch_bounds__(256) void k_persistent(
     const DItem* __restrict__ items, const uint8_t* __restrict__ data, const double* __restrict__ scales,
     const double* __restrict__ vin, const float* __restrict__ vin32, double* vout, float* vout32,
     double* __restrict__ part, const int64_t* __restrict__ dsrc, double* __restrict__ y,
-    const int64_t* __restrict__ perm, double alpha, int nx) {
+    const int64_t* __restrict__ perm, double alpha, int nx, int grab) {
     __shared__ double lds_w[4][MAX_TASK_INPUTS];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    for (;;) {
-        uint32_t tk_ = 0;
-        if (lane == 0) tk_ = __hip_atomic_fetch_add(ctl + kCtlTicket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int q = (int)__builtin_amdgcn_readfirstlane(tk_);
+    // a wave takes `grab` consecutive tickets per atomic and runs them in
+    // order (the smallest unfinished ticket is still never waiting)
+    int q = 0, qend = 0;
+    for (;; ++q) {
+        if (q >= qend) {
+            uint32_t tk_ = 0;
+            if (lane == 0)
+                tk_ = __hip_atomic_fetch_add(ctl + kCtlTicket, (uint32_t)grab, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+            q = (int)__builtin_amdgcn_readfirstlane(tk_);
+            qend = q + grab;
+        }
         if (q >= nq) break;
         const int32_t e = queue[q];
         int32_t owner;

@@ -265,6 +265,7 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         m->p_nq = (int32_t)qorder.size();
         m->p_mask = Q.dtype_mask ? Q.dtype_mask : 1;
         m->p_dense_after = opt.dense_after;
+        m->p_grab = opt.tickets_per_grab;
         m->p_nowners = (int64_t)P.owners.size();
         m->p_spin = (uint64_t)opt.spin_limit_us * 100;   // 100 MHz real-time counter
         m->p_tasks = (const hm::DTask*)(base + o_ptasks);
@@ -379,14 +380,14 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
                                   m->p_nq, m->p_dep_first, m->p_deps, m->p_target, m->p_done, m->p_ctl, m->p_spin,
                                   m->p_tasks, m->owners, m->items, (const uint8_t*)m->data, (const double*)m->scales,
                                   (const double*)m->ws, (const float*)m->ws32, m->ws, m->ws32, m->part,
-                                  (const int64_t*)m->dsrc, y, permp, alpha, (int)n);
+                                  (const int64_t*)m->dsrc, y, permp, alpha, (int)n, m->p_grab);
             m->pphases[0].pending.push_back(ev);
         } else {
             hipLaunchKernelGGL(pk, grid, block, 0, stream, (const int32_t*)m->p_order, m->p_nq, m->p_dep_first,
                                m->p_deps, m->p_target, m->p_done, m->p_ctl, m->p_spin, m->p_tasks, m->owners,
                                m->items, (const uint8_t*)m->data, (const double*)m->scales, (const double*)m->ws,
                                (const float*)m->ws32, m->ws, m->ws32, m->part, (const int64_t*)m->dsrc, y, permp,
-                               alpha, (int)n);
+                               alpha, (int)n, m->p_grab);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail("hm_mvm: kernel launch", e);
@@ -586,6 +587,7 @@ extern "C" hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x
 // Reorder the persistent queue for another interleave point (host build,
 // then one copy of the order table; synchronous, outside graph capture).
 static hm_status set_dense_after(hm_matrix* m, int32_t dense_after) {
+    if (m->p_dense_after == dense_after) return HM_OK;
     std::vector<int32_t> order;
     hm_status st = hm::queue_order(m->h_owners, m->p_queue.tasks, m->p_queue, dense_after, order);
     if (st != HM_OK) return st;
@@ -596,6 +598,24 @@ static hm_status set_dense_after(hm_matrix* m, int32_t dense_after) {
     hipError_t e = hipMemcpy(m->p_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail("hm_tune_mvm: queue copy", e);
     m->p_dense_after = dense_after;
+    return HM_OK;
+}
+
+extern "C" hm_status hm_set_schedule(hm_matrix* m, int32_t schedule, int32_t param) {
+    if (!m || param < 0 || (schedule != HM_SCHED_STAGED && schedule != HM_SCHED_PERSISTENT) ||
+        (schedule == HM_SCHED_PERSISTENT && !m->p_ctl)) {
+        hm::set_error("hm_set_schedule: null matrix, negative parameter, unknown schedule, or no persistent queue");
+        return HM_EINVAL;
+    }
+    if (schedule == HM_SCHED_STAGED) {
+        m->fork_after = param;
+    } else {
+        hipError_t e = hipDeviceSynchronize();   // no product may be reading the queue being replaced
+        if (e != hipSuccess) return hip_fail("hm_set_schedule: synchronize", e);
+        hm_status st = set_dense_after(m, param);
+        if (st != HM_OK) return st;
+    }
+    m->schedule = schedule;
     return HM_OK;
 }
 

@@ -437,7 +437,7 @@ TaskKernel task_kernel(bool acc64, int mask);
 using PersistKernel = void (*)(const int32_t*, int, const int32_t*, const int32_t*, const int32_t*, int32_t*,
                                uint32_t*, uint64_t, const DTask*, const DOwner*, const DItem*, const uint8_t*,
                                const double*, const double*, const float*, double*, float*, double*,
-                               const int64_t*, double*, const int64_t*, double, int);
+                               const int64_t*, double*, const int64_t*, double, int, int);
 PersistKernel persist_kernel(bool acc64, int mask, int* launched_mask);
 __global__ void k_gather_reset(const double* __restrict__ x, const int64_t* __restrict__ perm,
                                double* __restrict__ ws, float* __restrict__ ws32, int64_t n, int cluster_order,

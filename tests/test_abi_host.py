@@ -229,9 +229,9 @@ def test_persistent_queue_plans(tb):
     vals = {"h": h, "uh": to_uh(h, st), "h2": to_h2(h, st)}
     for fmt, v in vals.items():
         for pol in (dict(), dict(dense="valr", diag="valr", factor="valr")):
-            staged = hm.plan_stats(lay, fmt, v, eps=1e-6, task_bytes=tb, schedule="staged", **pol)
+            staged = hm.plan_stats(lay, fmt, v, eps=1e-6, task_bytes=tb, **pol)
             for da in (0, 1, 3, 50):
-                s = hm.plan_stats(lay, fmt, v, eps=1e-6, task_bytes=tb, dense_after=da, **pol)
+                s = hm.plan_stats(lay, fmt, v, eps=1e-6, task_bytes=tb, dense_after=da, schedule="persistent", **pol)
                 assert s["nlaunch"] == 2
                 assert s["method_bytes"] == staged["method_bytes"]
                 assert staged["nlaunch"] > 2

@@ -138,7 +138,7 @@ def test_tune_mvm_keeps_results_bitwise(fmt):
     n = 2048
     p, st, lay, vals = make(n, 1e-8)
     x, y = gaussian_vector(n, 12), gaussian_vector(n, 13)
-    M = hm.Matrix(lay, fmt, vals[fmt], dense="valr", diag="valr", factor="valr", eps=1e-6)
+    M = hm.Matrix(lay, fmt, vals[fmt], dense="valr", diag="valr", factor="valr", eps=1e-6, schedule="persistent")
     xd = torch.from_numpy(x).cuda()
     y0 = torch.from_numpy(y.copy()).cuda()
     M.mvm(xd, y0, alpha=0.5)

@@ -56,9 +56,10 @@ def test_persistent_equals_staged(fmt, pol, tb):
     pp, tol = POLICIES[pol]
     print(f"case persistent vs staged {fmt} {pol} task_bytes={tb}", flush=True)
     x, y = gaussian_vector(st.n, 2301), gaussian_vector(st.n, 3301)
-    Mp = hm.Matrix(lay, fmt, vals[fmt], task_bytes=tb, **pp)
+    Mp = hm.Matrix(lay, fmt, vals[fmt], task_bytes=tb, schedule="persistent", **pp)
     Ms = hm.Matrix(lay, fmt, vals[fmt], task_bytes=tb, schedule="staged", **pp)
     assert Mp.stats()["nlaunch"] == 2 and Ms.stats()["nlaunch"] > 2
+    assert hm.Matrix(lay, fmt, vals[fmt], task_bytes=tb, **pp).stats()["nlaunch"] > 2   # staged by default
     a = product(Mp, x, y)
     b = product(Ms, x, y)
     Mp.check()
@@ -82,7 +83,7 @@ def test_persistent_repeatable_graphs_and_interleave(fmt):
     pp, _ = POLICIES["valr6"]
     print(f"case persistent repeat/graph/interleave {fmt}", flush=True)
     x, y = gaussian_vector(st.n, 2401), gaussian_vector(st.n, 3401)
-    M = hm.Matrix(lay, fmt, vals[fmt], task_bytes=4000, **pp)
+    M = hm.Matrix(lay, fmt, vals[fmt], task_bytes=4000, schedule="persistent", **pp)
     first = product(M, x, y)
     for _ in range(10):
         assert np.array_equal(product(M, x, y), first)
@@ -97,7 +98,7 @@ def test_persistent_repeatable_graphs_and_interleave(fmt):
     g.free()
     M.check()
     for da in (1, 2, 5, 100):
-        Md = hm.Matrix(lay, fmt, vals[fmt], task_bytes=4000, dense_after=da, **pp)
+        Md = hm.Matrix(lay, fmt, vals[fmt], task_bytes=4000, dense_after=da, schedule="persistent", **pp)
         assert np.array_equal(product(Md, x, y), first), da
         Md.check()
         Md.free()
@@ -119,7 +120,7 @@ def test_wait_bound_ends_the_launch():
     pp, tol = POLICIES["f64"]
     print("case persistent wait bound 1 us (h2, 2000-byte tasks)", flush=True)
     x, y = gaussian_vector(st.n, 2501), gaussian_vector(st.n, 3501)
-    M = hm.Matrix(lay, "h2", vals["h2"], task_bytes=2000, spin_limit_us=1, **pp)
+    M = hm.Matrix(lay, "h2", vals["h2"], task_bytes=2000, spin_limit_us=1, schedule="persistent", **pp)
     aborted = 0
     for _ in range(5):
         out = product(M, x, y)
@@ -132,7 +133,7 @@ def test_wait_bound_ends_the_launch():
         assert np.all(np.isfinite(out))
     print(f"  {aborted} of 5 launches aborted", flush=True)
     M.free()
-    M2 = hm.Matrix(lay, "h2", vals["h2"], task_bytes=2000, **pp)
+    M2 = hm.Matrix(lay, "h2", vals["h2"], task_bytes=2000, schedule="persistent", **pp)
     out = product(M2, x, y)
     M2.check()
     ref = stored.product(st, "h2", vals["h2"], 0.75, x, y)
