@@ -65,15 +65,24 @@ typedef enum { HM_ACC_AUTO = 0, HM_ACC_F32 = 1, HM_ACC_F64 = 2 } hm_accum;
 
 /* ---------------------------------------------------------------- layout */
 
+/* Partitions (Sec. 2.2; its remark names BLR and HODLR as members of the
+ * same set of matrices, obtained by the choice of clustering and
+ * admissibility alone). */
+#define HM_PART_STANDARD 0   /* geometric bisection, standard admissibility */
+#define HM_PART_HODLR 1      /* balanced bisection, off-diagonal admissibility: t != s */
+#define HM_PART_BLR 2        /* balanced bisection, one level: all pairs of leaf clusters,
+                                low rank where the standard condition holds */
+
 typedef struct {
     int32_t leaf_size;   /* a cluster with at most leaf_size points is a leaf (default 64) */
     double eta;          /* admissibility min(diam) <= eta * dist (default 2) */
+    int32_t partition;   /* HM_PART_* (default HM_PART_STANDARD) */
 } hm_layout_opts;
 
 typedef struct hm_layout hm_layout;
 
 /* Cluster tree by geometric bisection and block tree with standard
- * admissibility (Def. 2.1, 2.2):
+ * admissibility (Def. 2.1, 2.2), for HM_PART_STANDARD:
  *   - a cluster's box is the tight axis-aligned box of its points;
  *   - clusters larger than leaf_size split along the axis of largest extent
  *     (lowest axis on ties) at 0.5*(lo+hi); points with coordinate < mid go
@@ -81,9 +90,18 @@ typedef struct hm_layout hm_layout;
  *   - a block (t,s) is low rank if min(diam_t^2, diam_s^2) <= eta^2 dist^2
  *     and dist^2 > 0 (squared box diameters/distance, summed x,y,z), else a
  *     dense leaf if t or s is a leaf, else it recurses over son pairs.
+ * HM_PART_HODLR and HM_PART_BLR use a balanced tree instead: every cluster
+ * above level d splits (along its box's axis of largest extent, lowest axis
+ * on ties) into the first floor(m/2) of its points ordered by that
+ * coordinate (stable) and the rest, d being the smallest depth with
+ * ceil(n / 2^d) <= leaf_size (a single point is always a leaf).  HODLR then
+ * makes every block (t, s) with t != s low rank; BLR recurses down to the
+ * pairs of leaf clusters and makes a pair low rank where the standard
+ * condition holds, dense otherwise.
  * points: n x 3 row-major float64, caller-owned, n >= 1.  opts may be NULL.
  * Deterministic: the same points give bit-identical layouts.
- * Errors: HM_EINVAL (n < 1, null, non-finite point, leaf_size < 1, eta <= 0). */
+ * Errors: HM_EINVAL (n < 1, null, non-finite point, leaf_size < 1, eta <= 0,
+ * unknown partition). */
 hm_status hm_build_layout(const double* points, int64_t n, const hm_layout_opts* opts,
                           hm_layout** out);
 

@@ -26,6 +26,19 @@ on squared quantities with dist > 0:
     adm    = min(diam_t^2, diam_s^2) <= 4 dist^2  and  dist^2 > 0.
 
 Sums run over x, y, z in that order in plain float64.
+
+Other partitions (the remark after Def. 2.3: BLR and HODLR belong to the same
+set of matrices through the choice of clustering and admissibility alone):
+
+* balanced clustering, used by both: every cluster above a fixed depth d
+  splits along the axis of largest box extent (lowest axis on ties) into the
+  first floor(m/2) of its points ordered by that coordinate (stable order on
+  ties) and the rest; d is the smallest depth with ceil(n / 2^d) <= leaf_size,
+  and a single point is always a leaf;
+* HODLR: off-diagonal admissibility, every block (tau, sigma) with
+  tau != sigma is low rank;
+* BLR: a single hierarchy level, the block tree recurses to the pairs of leaf
+  clusters, which are low rank where the standard condition holds.
 """
 from __future__ import annotations
 
@@ -34,9 +47,20 @@ import numpy as np
 from synth.inputs import Structure
 
 
-def cluster_tree(points: np.ndarray, leaf_size: int = 64):
+STANDARD, HODLR, BLR = "standard", "hodlr", "blr"
+
+
+def balanced_depth(n: int, leaf_size: int) -> int:
+    d = 0
+    while -(-n // (1 << d)) > leaf_size:
+        d += 1
+    return d
+
+
+def cluster_tree(points: np.ndarray, leaf_size: int = 64, balanced: bool = False):
     """Returns (perm, begin, end, level, parent, son0, son1, lo, hi)."""
     n = points.shape[0]
+    depth = balanced_depth(n, leaf_size) if balanced else None
     P = np.asarray(points, dtype=np.float64)
     perm = np.empty(n, dtype=np.int64)
     begin, end, level, parent, son0, son1, lo_l, hi_l = [], [], [], [], [], [], [], []
@@ -57,7 +81,8 @@ def cluster_tree(points: np.ndarray, leaf_size: int = 64):
         lo = pts.min(axis=0) if len(idx) else np.zeros(3)
         hi = pts.max(axis=0) if len(idx) else np.zeros(3)
         lo_l[v], hi_l[v] = lo, hi
-        if len(idx) <= leaf_size:
+        leaf = (level[v] >= depth or len(idx) < 2) if balanced else len(idx) <= leaf_size
+        if leaf:
             begin[v] = pos[0]
             perm[pos[0]:pos[0] + len(idx)] = idx
             pos[0] += len(idx)
@@ -65,12 +90,17 @@ def cluster_tree(points: np.ndarray, leaf_size: int = 64):
             continue
         ext = hi - lo
         axis = int(np.argmax(ext))          # first maximum on ties
-        mid = 0.5 * (lo[axis] + hi[axis])
-        mask = pts[:, axis] < mid
-        a, b = idx[mask], idx[~mask]
-        if len(a) == 0 or len(b) == 0:
+        if balanced:
+            srt = idx[np.argsort(pts[:, axis], kind="stable")]
             h = len(idx) // 2
-            a, b = idx[:h], idx[h:]
+            a, b = srt[:h], srt[h:]
+        else:
+            mid = 0.5 * (lo[axis] + hi[axis])
+            mask = pts[:, axis] < mid
+            a, b = idx[mask], idx[~mask]
+            if len(a) == 0 or len(b) == 0:
+                h = len(idx) // 2
+                a, b = idx[:h], idx[h:]
         c0 = new_node(level[v] + 1, v)
         c1 = new_node(level[v] + 1, v)
         son0[v], son1[v] = c0, c1
@@ -129,13 +159,22 @@ def admissible(lo_t, hi_t, lo_s, hi_s) -> bool:
     return (min(dt, ds) <= 4.0 * dd) and dd > 0.0
 
 
-def block_tree(son0, son1, lo, hi):
+def partition_admissible(kind, t, s, son0, lo, hi) -> bool:
+    """The admissibility of the chosen partition kind."""
+    if kind == HODLR:
+        return t != s
+    if kind == BLR:
+        return son0[t] < 0 and son0[s] < 0 and admissible(lo[t], hi[t], lo[s], hi[s])
+    return admissible(lo[t], hi[t], lo[s], hi[s])
+
+
+def block_tree(son0, son1, lo, hi, kind=STANDARD):
     """Leaves of the block tree in depth-first order: (tau, sigma, adm)."""
     taus, sigs, adms = [], [], []
     stack = [(0, 0)]
     while stack:
         t, s = stack.pop()
-        if admissible(lo[t], hi[t], lo[s], hi[s]):
+        if partition_admissible(kind, t, s, son0, lo, hi):
             taus.append(t); sigs.append(s); adms.append(True)
         elif son0[t] < 0 or son0[s] < 0:
             taus.append(t); sigs.append(s); adms.append(False)
@@ -148,11 +187,12 @@ def block_tree(son0, son1, lo, hi):
             np.array(adms, dtype=bool))
 
 
-def build_structure(points: np.ndarray, leaf_size: int = 64) -> Structure:
-    perm, beg, end, lev, par, s0, s1, lo, hi = cluster_tree(points, leaf_size)
-    bt, bs, ba = block_tree(s0, s1, lo, hi)
+def build_structure(points: np.ndarray, leaf_size: int = 64, kind: str = STANDARD) -> Structure:
+    perm, beg, end, lev, par, s0, s1, lo, hi = cluster_tree(points, leaf_size, balanced=kind != STANDARD)
+    bt, bs, ba = block_tree(s0, s1, lo, hi, kind)
     st = Structure(points.shape[0], perm, beg, end, lev, par, s0, s1, bt, bs, ba)
     st._cache["bbox"] = (lo, hi)
+    st._cache["partition"] = kind
     return st
 
 
@@ -162,6 +202,7 @@ def validate_partition(st: Structure, leaf_size: int = 64) -> None:
     cluster, blocks pair clusters of equal level, and sons partition their
     parent (Def. 2.1, 2.2)."""
     n = st.n
+    kind = st._cache.get("partition", STANDARD)
     assert sorted(st.perm.tolist()) == list(range(n)), "perm is not a permutation"
     for v in range(st.nnodes):
         if st.son0[v] >= 0:
@@ -171,13 +212,16 @@ def validate_partition(st: Structure, leaf_size: int = 64) -> None:
             assert st.end[a] > st.begin[a] and st.end[b] > st.begin[b]
         else:
             assert 0 < st.end[v] - st.begin[v] <= leaf_size or n == 0
+            if kind != STANDARD and st.end[v] - st.begin[v] > 1:
+                assert st.level[v] == balanced_depth(n, leaf_size)
     lo, hi = st._cache.get("bbox", (None, None))
+    kind = st._cache.get("partition", STANDARD)
     for b in range(st.nblocks):
         t, s = int(st.blk_tau[b]), int(st.blk_sigma[b])
         assert st.level[t] == st.level[s]
         if st.blk_adm[b]:
             if lo is not None:
-                assert admissible(lo[t], hi[t], lo[s], hi[s])
+                assert partition_admissible(kind, t, s, st.son0, lo, hi)
         else:
             assert st.son0[t] < 0 or st.son0[s] < 0
     # exact cover: per leaf row cluster, the column intervals of every block

@@ -16,6 +16,7 @@ from ._lib import (HM_ACC_AUTO, HM_ACC_F32, HM_ACC_F64, HM_BF16, HM_CLUSTER_ORDE
                    HMError)
 
 FORMATS = {"h": HM_FMT_H, "uh": HM_FMT_UH, "h2": HM_FMT_H2}
+PARTITIONS = {"standard": _lib.HM_PART_STANDARD, "hodlr": _lib.HM_PART_HODLR, "blr": _lib.HM_PART_BLR}
 DTYPES = {"f64": HM_F64, "f32": HM_F32, "bf16": HM_BF16, "f16": HM_F16, "fp8": HM_FP8E4M3,
           "valr": HM_VALR_AUTO}
 
@@ -27,12 +28,12 @@ def _dptr(a):
 class Layout:
     """Cluster tree + block tree built by the library (hm_build_layout)."""
 
-    def __init__(self, points, leaf_size: int = 64, eta: float = 2.0):
+    def __init__(self, points, leaf_size: int = 64, eta: float = 2.0, partition: str = "standard"):
         L = _lib.lib()
         self._pts = np.ascontiguousarray(points, dtype=np.float64)
         if self._pts.ndim != 2 or self._pts.shape[1] != 3:
             raise ValueError("points must be n x 3")
-        opts = _lib.LayoutOpts(leaf_size, eta)
+        opts = _lib.LayoutOpts(leaf_size, eta, PARTITIONS[partition])
         h = ctypes.c_void_p()
         _lib.check(L.hm_build_layout(_dptr(self._pts), self._pts.shape[0], ctypes.byref(opts),
                                      ctypes.byref(h)))

@@ -21,8 +21,11 @@ HM_ACC_AUTO, HM_ACC_F32, HM_ACC_F64 = 0, 1, 2
 HM_CLUSTER_ORDER = 1
 
 
+HM_PART_STANDARD, HM_PART_HODLR, HM_PART_BLR = 0, 1, 2
+
+
 class LayoutOpts(ctypes.Structure):
-    _fields_ = [("leaf_size", c_int32), ("eta", c_double)]
+    _fields_ = [("leaf_size", c_int32), ("eta", c_double), ("partition", c_int32)]
 
 
 class LayoutView(ctypes.Structure):

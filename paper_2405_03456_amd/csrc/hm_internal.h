@@ -16,6 +16,8 @@ struct Layout {
     int64_t n = 0;
     int32_t leaf_size = 64;
     double eta = 2.0;
+    int32_t partition = 0;   // HM_PART_*
+    int32_t blr_depth = 0;   // balanced trees: level of every leaf
     int32_t depth = 0;
     std::vector<int64_t> perm;
     // nodes, depth-first pre-order

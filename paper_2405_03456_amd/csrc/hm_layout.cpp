@@ -60,7 +60,8 @@ struct Builder {
             L.node_hi[3 * v + d] = hi[d];
         }
         if (level > L.depth) L.depth = level;
-        if (m <= L.leaf_size) {
+        const bool balanced = L.partition != HM_PART_STANDARD;
+        if (balanced ? (level >= L.blr_depth || m < 2) : m <= L.leaf_size) {
             L.node_begin[v] = pos;
             for (int64_t i = 0; i < m; ++i) L.perm[pos + i] = idx[i];
             pos += m;
@@ -76,19 +77,29 @@ struct Builder {
                 axis = d;
             }
         }
-        const double mid = 0.5 * (lo[axis] + hi[axis]);
         std::vector<int64_t> a, b;
-        a.reserve(m);
-        b.reserve(m);
-        for (int64_t i = 0; i < m; ++i) {
-            if (P[3 * idx[i] + axis] < mid)
-                a.push_back(idx[i]);
-            else
-                b.push_back(idx[i]);
-        }
-        if (a.empty() || b.empty()) {
+        if (balanced) {
+            // cardinality bisection: the points ordered by the axis
+            // coordinate (stable), son 0 takes the first half (rounded down)
+            const double* PP = P;
+            std::stable_sort(idx.begin(), idx.end(),
+                             [PP, axis](int64_t u, int64_t w) { return PP[3 * u + axis] < PP[3 * w + axis]; });
             a.assign(idx.begin(), idx.begin() + m / 2);
             b.assign(idx.begin() + m / 2, idx.end());
+        } else {
+            const double mid = 0.5 * (lo[axis] + hi[axis]);
+            a.reserve(m);
+            b.reserve(m);
+            for (int64_t i = 0; i < m; ++i) {
+                if (P[3 * idx[i] + axis] < mid)
+                    a.push_back(idx[i]);
+                else
+                    b.push_back(idx[i]);
+            }
+            if (a.empty() || b.empty()) {
+                a.assign(idx.begin(), idx.begin() + m / 2);
+                b.assign(idx.begin() + m / 2, idx.end());
+            }
         }
         std::vector<int64_t>().swap(idx);   // release before recursing
         int32_t s0 = (int32_t)L.node_begin.size();
@@ -124,13 +135,23 @@ bool admissible(const Layout& L, int32_t t, int32_t s) {
     return mn <= (L.eta * L.eta) * dd && dd > 0.0;
 }
 
+// The admissibility of the chosen partition (Sec. 2.2 and its remark on
+// BLR and HODLR): standard; off-diagonal (weak) for HODLR, every pair of
+// distinct clusters; for BLR the standard condition between leaf clusters
+// only, so the block tree reaches all pairs of leaves (one level).
+bool block_admissible(const Layout& L, int32_t t, int32_t s) {
+    if (L.partition == HM_PART_HODLR) return t != s;
+    if (L.partition == HM_PART_BLR) return L.leaf(t) && L.leaf(s) && admissible(L, t, s);
+    return admissible(L, t, s);
+}
+
 void block_tree(Layout& L) {
     std::vector<std::pair<int32_t, int32_t>> stack;
     stack.push_back({0, 0});
     while (!stack.empty()) {
         auto [t, s] = stack.back();
         stack.pop_back();
-        if (admissible(L, t, s)) {
+        if (block_admissible(L, t, s)) {
             L.blk_tau.push_back(t);
             L.blk_sigma.push_back(s);
             L.blk_adm.push_back(1);
@@ -163,8 +184,10 @@ extern "C" hm_status hm_build_layout(const double* points, int64_t n, const hm_l
     *out = nullptr;
     int32_t leaf = opts ? opts->leaf_size : 64;
     double eta = opts ? opts->eta : 2.0;
-    if (leaf < 1 || !(eta > 0.0) || !std::isfinite(eta)) {
-        hm::set_error("hm_build_layout: leaf_size must be >= 1 and eta > 0");
+    const int32_t part = opts ? opts->partition : HM_PART_STANDARD;
+    if (leaf < 1 || !(eta > 0.0) || !std::isfinite(eta) ||
+        (part != HM_PART_STANDARD && part != HM_PART_HODLR && part != HM_PART_BLR)) {
+        hm::set_error("hm_build_layout: leaf_size must be >= 1, eta > 0 and partition one of HM_PART_*");
         return HM_EINVAL;
     }
     for (int64_t i = 0; i < 3 * n; ++i)
@@ -182,6 +205,9 @@ extern "C" hm_status hm_build_layout(const double* points, int64_t n, const hm_l
         L.n = n;
         L.leaf_size = leaf;
         L.eta = eta;
+        L.partition = part;
+        // balanced trees: the smallest depth d with ceil(n / 2^d) <= leaf_size
+        while (L.blr_depth < 62 && ((n + (int64_t(1) << L.blr_depth) - 1) >> L.blr_depth) > leaf) ++L.blr_depth;
         L.perm.assign(n, -1);
         std::vector<int64_t> idx(n);
         for (int64_t i = 0; i < n; ++i) idx[i] = i;
