@@ -62,6 +62,7 @@ typedef enum { HM_ACC_AUTO = 0, HM_ACC_F32 = 1, HM_ACC_F64 = 2 } hm_accum;
 /* hm_mvm flags */
 #define HM_CLUSTER_ORDER 1u   /* x and y are already in cluster order */
 #define HM_TIMING 2u          /* record HIP events around every phase kernel (hm_timing_read) */
+#define HM_ADJOINT 4u         /* y := alpha * M^T * x + y (needs hm_upload_opts.adjoint) */
 
 /* ---------------------------------------------------------------- layout */
 
@@ -237,6 +238,10 @@ typedef struct {
                                (0 = 2 000 000); a wait past it aborts the launch (hm_matrix_check) */
     int32_t tickets_per_grab; /* persistent schedule: queue items a wavefront takes per atomic
                                  (0 = 4, at most 256) */
+    int32_t adjoint;        /* 1 = also upload the adjoint M^T (the remark after Alg. 3: the
+                               product over block columns) for HM_ADJOINT products: every block
+                               transposed, stored under the same precision policy; doubles the
+                               device memory of the matrix */
 } hm_upload_opts;
 
 #define HM_SCHED_STAGED 0
@@ -284,9 +289,14 @@ hm_status hm_plan_stats(const hm_layout* layout, int32_t format, const hm_values
 
 /* ------------------------------------------------------------- products */
 
-/* y := alpha * M * x + y.  x, y: device float64 arrays of length n
- * (caller-owned, e.g. PyTorch tensors), x != y.  Enqueued on `stream`;
- * calls on one matrix must not overlap in time (they share its workspace).
+/* y := alpha * M * x + y, or with HM_ADJOINT y := alpha * M^T * x + y (the
+ * transposed matrix uploaded with hm_upload_opts.adjoint; its blocks are
+ * the transposes of M's, stored under the same policy: for FP64, FP32 and
+ * BF16 storage exactly the transpose of M as stored; FP16/FP8 columns take
+ * the range scales of the transposed columns).  x, y: device float64 arrays
+ * of length n (caller-owned, e.g. PyTorch tensors), x != y.  Enqueued on
+ * `stream`; calls on one matrix must not overlap in time (they share its
+ * workspace).
  *
  * Schedules (the arithmetic and its order are the same, results are
  * bitwise identical):

@@ -150,11 +150,11 @@ SCHEDULES = {"persistent": _lib.HM_SCHED_PERSISTENT, "staged": _lib.HM_SCHED_STA
 
 def make_opts(task_bytes: int = 0, spread_dense: bool = False, dense_grid: int = 0, fork_after: int = 0,
               valr_promote: bool = False, schedule: str = "staged", dense_after: int = 0,
-              spin_limit_us: int = 0, tickets_per_grab: int = 0):
+              spin_limit_us: int = 0, tickets_per_grab: int = 0, adjoint: bool = False):
     """hm_upload_opts (all zero = the library's defaults)."""
     return _lib.UploadOpts(int(task_bytes), int(bool(spread_dense)), int(dense_grid), int(fork_after),
                            int(bool(valr_promote)), SCHEDULES[schedule], int(dense_after), int(spin_limit_us),
-                           int(tickets_per_grab))
+                           int(tickets_per_grab), int(bool(adjoint)))
 
 
 def _stats_dict(s) -> dict:
@@ -214,10 +214,13 @@ class Matrix:
         _lib.check(_lib.lib().hm_matrix_stats(self._h, ctypes.byref(s)))
         return _stats_dict(s)
 
-    def mvm(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None, timing: bool = False):
-        """y += alpha * M * x for device float64 tensors (enqueued, asynchronous)."""
+    def mvm(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None, timing: bool = False,
+            adjoint: bool = False):
+        """y += alpha * M * x (or M^T x with adjoint=True) for device float64
+        tensors (enqueued, asynchronous)."""
         xp, yp = _dev_ptr(x, self.layout.n), _dev_ptr(y, self.layout.n)
-        flags = (HM_CLUSTER_ORDER if cluster_order else 0) | (_lib.HM_TIMING if timing else 0)
+        flags = (HM_CLUSTER_ORDER if cluster_order else 0) | (_lib.HM_TIMING if timing else 0) | \
+            (_lib.HM_ADJOINT if adjoint else 0)
         _lib.check(_lib.lib().hm_mvm(self._h, float(alpha), xp, yp, flags, _stream_ptr(stream)))
 
     def mvm_many(self, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None, timing: bool = False):
@@ -249,9 +252,10 @@ class Matrix:
         was aborted since the last check (hm_matrix_check)."""
         _lib.check(_lib.lib().hm_matrix_check(self._h))
 
-    def graph(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None) -> "Graph":
+    def graph(self, x, y, alpha: float = 1.0, cluster_order: bool = False, stream=None,
+              adjoint: bool = False) -> "Graph":
         """Capture one product (fixed x, y, alpha) into a replayable HIP graph."""
-        return Graph(self, x, y, alpha, cluster_order, stream)
+        return Graph(self, x, y, alpha, cluster_order, stream, adjoint)
 
     def timing(self) -> list:
         """Per-phase kernel times of the calls made with timing=True (and clears them)."""
@@ -311,12 +315,14 @@ def _marshal_batch(mats, X, Y):
     return k, hs, xs, ldx, nr, ys, ldy, HM_F64 if vdt is None else vdt
 
 
-def mvm_batch(mats, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None, timing: bool = False):
-    """Y[i] += alpha * mats[i] * X[i] for every i (hm_mvm_batch).  X[i], Y[i]:
-    device tensors of n_i x r_i values (column-major) or vectors of length
-    n_i, all float64 or all float32."""
+def mvm_batch(mats, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None, timing: bool = False,
+              adjoint: bool = False):
+    """Y[i] += alpha * mats[i] * X[i] for every i (hm_mvm_batch; mats[i]^T
+    with adjoint=True).  X[i], Y[i]: device tensors of n_i x r_i values
+    (column-major) or vectors of length n_i, all float64 or all float32."""
     k, hs, xs, ldx, nr, ys, ldy, vdt = _marshal_batch(mats, X, Y)
-    flags = (HM_CLUSTER_ORDER if cluster_order else 0) | (_lib.HM_TIMING if timing else 0)
+    flags = (HM_CLUSTER_ORDER if cluster_order else 0) | (_lib.HM_TIMING if timing else 0) | \
+        (_lib.HM_ADJOINT if adjoint else 0)
     _lib.check(_lib.lib().hm_mvm_batch(hs, k, float(alpha), xs, ldx, nr, ys, ldy, vdt, flags,
                                        _stream_ptr(stream)))
 
@@ -333,11 +339,12 @@ def mvm_batch_noalloc(mats, X, Y, alpha: float = 1.0, cluster_order: bool = Fals
 class BatchGraph:
     """hm_graph_create_batch: one captured hm_mvm_batch call, replayed with launch()."""
 
-    def __init__(self, mats, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None):
+    def __init__(self, mats, X, Y, alpha: float = 1.0, cluster_order: bool = False, stream=None,
+                 adjoint: bool = False):
         self._keep = (list(mats), list(X), list(Y))
         k, hs, xs, ldx, nr, ys, ldy, vdt = _marshal_batch(mats, X, Y)
         h = ctypes.c_void_p()
-        flags = HM_CLUSTER_ORDER if cluster_order else 0
+        flags = (HM_CLUSTER_ORDER if cluster_order else 0) | (_lib.HM_ADJOINT if adjoint else 0)
         _lib.check(_lib.lib().hm_graph_create_batch(hs, k, float(alpha), xs, ldx, nr, ys, ldy, vdt, flags,
                                                     _stream_ptr(stream), ctypes.byref(h)))
         self._h = h
@@ -358,11 +365,11 @@ class BatchGraph:
 class Graph:
     """hm_graph: a captured product, replayed with launch()."""
 
-    def __init__(self, M: Matrix, x, y, alpha, cluster_order, stream):
+    def __init__(self, M: Matrix, x, y, alpha, cluster_order, stream, adjoint=False):
         self.matrix = M           # keeps the matrix alive
         self._xy = (x, y)         # keeps the vectors alive
         h = ctypes.c_void_p()
-        flags = HM_CLUSTER_ORDER if cluster_order else 0
+        flags = (HM_CLUSTER_ORDER if cluster_order else 0) | (_lib.HM_ADJOINT if adjoint else 0)
         _lib.check(_lib.lib().hm_graph_create(M.handle, float(alpha), _dev_ptr(x, M.layout.n),
                                               _dev_ptr(y, M.layout.n), flags, _stream_ptr(stream),
                                               ctypes.byref(h)))

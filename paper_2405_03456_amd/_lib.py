@@ -19,6 +19,7 @@ HM_FMT_H, HM_FMT_UH, HM_FMT_H2 = 0, 1, 2
 HM_F64, HM_F32, HM_BF16, HM_F16, HM_FP8E4M3, HM_VALR_AUTO = 0, 1, 2, 3, 4, 5
 HM_ACC_AUTO, HM_ACC_F32, HM_ACC_F64 = 0, 1, 2
 HM_CLUSTER_ORDER = 1
+HM_ADJOINT = 4
 
 
 HM_PART_STANDARD, HM_PART_HODLR, HM_PART_BLR = 0, 1, 2
@@ -55,7 +56,8 @@ HM_SCHED_STAGED, HM_SCHED_PERSISTENT = 0, 1
 class UploadOpts(ctypes.Structure):
     _fields_ = [("task_bytes", c_int64), ("spread_dense", c_int32), ("dense_grid", c_int32),
                 ("fork_after", c_int32), ("valr_promote", c_int32), ("schedule", c_int32),
-                ("dense_after", c_int32), ("spin_limit_us", c_int32), ("tickets_per_grab", c_int32)]
+                ("dense_after", c_int32), ("spin_limit_us", c_int32), ("tickets_per_grab", c_int32),
+                ("adjoint", c_int32)]
 
 
 class Values(ctypes.Structure):

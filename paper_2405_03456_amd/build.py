@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhm.so")
 ARCH = os.environ.get("HM_OFFLOAD_ARCH", "gfx950")
 
-HOST_SRCS = ["hm_layout.cpp", "hm_quant.cpp", "hm_pack.cpp", "hm_queue.cpp"]
+HOST_SRCS = ["hm_layout.cpp", "hm_quant.cpp", "hm_pack.cpp", "hm_queue.cpp", "hm_adjoint.cpp"]
 DEVICE_SRCS = ["hm_runtime.hip", "hm_tasks_a32_lo.hip", "hm_tasks_a32_hi.hip", "hm_tasks_a64_lo.hip",
                "hm_tasks_a64_hi.hip", "hm_batch.hip", "hm_serve.hip"]
 HEADERS = ["hm_internal.h", "hm_plan.h", "hm_pack.h", "hm_device.h", "hm_stream.h"]

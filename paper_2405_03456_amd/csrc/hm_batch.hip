@@ -968,9 +968,35 @@ hm_status batch_prepare(hm_matrix* const* mats, int32_t nmat, const int32_t* nrh
 
 }  // namespace hm
 
+namespace hm {
+// HM_ADJOINT: the same call on the matrices' adjoints (uploaded with
+// hm_upload_opts.adjoint); false with the error set if one has none.
+bool adjoint_mats(hm_matrix* const* mats, int32_t nmat, const int32_t* nrhs, std::vector<hm_matrix*>& out,
+                  const char* who) {
+    out.assign((size_t)std::max(nmat, 0), nullptr);
+    for (int32_t i = 0; i < nmat; ++i) {
+        if (!mats[i] || nrhs[i] == 0) {
+            out[(size_t)i] = mats[i];
+            continue;
+        }
+        if (!mats[i]->adj) {
+            set_error(std::string(who) + ": HM_ADJOINT needs matrices uploaded with hm_upload_opts.adjoint = 1");
+            return false;
+        }
+        out[(size_t)i] = mats[i]->adj;
+    }
+    return true;
+}
+}  // namespace hm
+
 extern "C" hm_status hm_mvm_batch(hm_matrix* const* mats, int32_t nmat, double alpha, const void* const* X,
                                   const int64_t* ldx, const int32_t* nrhs, void* const* Y, const int64_t* ldy,
                                   int32_t vec_dtype, uint32_t flags, hm_stream_t stream) {
+    if ((flags & HM_ADJOINT) && nmat > 0 && mats && nrhs) {
+        std::vector<hm_matrix*> adj;
+        if (!hm::adjoint_mats(mats, nmat, nrhs, adj, "hm_mvm_batch")) return HM_EINVAL;
+        return hm_mvm_batch(adj.data(), nmat, alpha, X, ldx, nrhs, Y, ldy, vec_dtype, flags & ~HM_ADJOINT, stream);
+    }
     if (nmat < 0 || (nmat > 0 && (!mats || !X || !ldx || !nrhs || !Y || !ldy))) {
         hm::set_error("hm_mvm_batch: null argument");
         return HM_EINVAL;
@@ -1052,6 +1078,11 @@ extern "C" hm_status hm_tune_batch(hm_matrix* m, int32_t nrhs, int32_t vec_dtype
     if (!m || nrhs < 2 || nrhs > HM_MAX_NRHS || (vec_dtype != HM_F64 && vec_dtype != HM_F32) || reps < 1) {
         hm::set_error("hm_tune_batch: bad argument (nrhs in [2, HM_MAX_NRHS], vec_dtype F64/F32, reps >= 1)");
         return HM_EINVAL;
+    }
+    if (m->adj) {   // the adjoint's plan is tuned (and built) as well
+        hm_tune_result ra{};
+        hm_status sa = hm_tune_batch(m->adj, nrhs, vec_dtype, reps, stream, &ra);
+        if (sa != HM_OK) return sa;
     }
     const size_t esz = vec_dtype == HM_F64 ? 8 : 4;
     const size_t bytes = (size_t)m->n * nrhs * esz;
@@ -1180,6 +1211,12 @@ extern "C" hm_status hm_mvm_batch_noalloc(hm_matrix* const* mats, int32_t nmat, 
     if (vec_dtype != HM_F64 && vec_dtype != HM_F32) {
         hm::set_error("hm_mvm_batch_noalloc: vec_dtype must be HM_F64 or HM_F32");
         return HM_EINVAL;
+    }
+    if ((flags & HM_ADJOINT) && nmat > 0 && mats && nrhs) {
+        std::vector<hm_matrix*> adj;
+        if (!hm::adjoint_mats(mats, nmat, nrhs, adj, "hm_mvm_batch_noalloc")) return HM_EINVAL;
+        return hm_mvm_batch_noalloc(adj.data(), nmat, alpha, X, ldx, nrhs, Y, ldy, vec_dtype, flags & ~HM_ADJOINT,
+                                    stream);
     }
     if (flags & ~(uint32_t)HM_CLUSTER_ORDER) {
         hm::set_error("hm_mvm_batch_noalloc: unsupported flags (HM_TIMING allocates events)");

@@ -192,6 +192,9 @@ struct hm_matrix {
     int32_t* p_done = nullptr;
     uint32_t* p_ctl = nullptr;   // ticket, abort, error
     hm::Queue p_queue;           // host copy (the tuner reorders it)
+    // the adjoint M^T (HM_ADJOINT), uploaded with its own transposed layout
+    hm_matrix* adj = nullptr;
+    hm_layout* adj_layout = nullptr;
     std::vector<hm::DevStage> pphases;   // the persistent launch, for HM_TIMING
 };
 
@@ -212,6 +215,11 @@ struct BlockCall {
 // Run blocks of distinct matrices through the many-right-hand-side engine
 // (any width >= 1, including single columns), merged as in hm_mvm_batch.
 hm_status mvm_blocks(const BlockCall* calls, int ncalls, hipStream_t stream);
+
+// HM_ADJOINT: the adjoints of a batch's matrices (error set and false if one
+// was uploaded without).
+bool adjoint_mats(hm_matrix* const* mats, int32_t nmat, const int32_t* nrhs, std::vector<hm_matrix*>& out,
+                  const char* who);
 
 // Size the many-RHS workspaces of a batch (see hm_mvm_batch) ahead of a call.
 hm_status batch_prepare(hm_matrix* const* mats, int32_t nmat, const int32_t* nrhs, int32_t vec_dtype);

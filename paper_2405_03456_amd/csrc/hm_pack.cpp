@@ -1450,6 +1450,11 @@ hm_status pack_options(const hm_upload_opts* o, PackOptions& opt) {
         return HM_EINVAL;
     }
     if (o->tickets_per_grab) opt.tickets_per_grab = o->tickets_per_grab;
+    if (o->adjoint & ~1) {
+        set_error("hm_upload: adjoint must be 0 or 1");
+        return HM_EINVAL;
+    }
+    opt.adjoint = o->adjoint != 0;
     opt.schedule = o->schedule;
     opt.dense_after = o->dense_after;
     if (o->spin_limit_us) opt.spin_limit_us = o->spin_limit_us;

@@ -14,6 +14,7 @@ struct PackOptions {
     int32_t dense_after = 0;      // persistent schedule: interleave point of the dense tasks
     int64_t spin_limit_us = 2000000;
     int32_t tickets_per_grab = 4;
+    bool adjoint = false;         // also upload M^T for HM_ADJOINT products
 };
 
 // Validated PackOptions from the ABI's hm_upload_opts (NULL = defaults).
@@ -63,6 +64,19 @@ hm_status build_queue(const Packed& P, int64_t n, Queue& q);
 // first stage); checks that every item follows its producers.
 hm_status queue_order(const std::vector<DOwner>& owners, const std::vector<DTask>& tasks, const Queue& q,
                       int32_t dense_after, std::vector<int32_t>& order);
+
+// The adjoint M^T as a matrix of the same form over the transposed block
+// tree (hm_adjoint.cpp): the layout with every block (t, s) turned into
+// (s, t), and a value set whose pointers refer to the caller's arrays or to
+// transposed copies held here.
+struct Transposed {
+    hm_layout layout;
+    std::vector<std::vector<double>> store;
+    std::vector<const double*> dense, coupling;
+    hm_values v{};
+};
+
+hm_status transpose_matrix(const Layout& L, int32_t format, const hm_values* v, Transposed& T);
 
 // Task table of the many-right-hand-side engine, derived from a packed plan.
 // Consecutive tasks of one owner in one stage (same dtype, adjacent

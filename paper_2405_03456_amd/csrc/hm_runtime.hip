@@ -313,12 +313,37 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         return HM_ELAYOUT;
     }
     if (persist) m->stats.nlaunch = 2;   // gather + the persistent launch
+    if (opt.adjoint) {
+        // M^T over the transposed block tree, uploaded as a matrix of its own
+        hm::Transposed T;
+        hm_status sa;
+        try {
+            sa = hm::transpose_matrix(layout->L, format, values, T);
+        } catch (const std::bad_alloc&) {
+            hm_matrix_free(m);
+            hm::set_error("hm_upload: out of host memory while transposing for the adjoint");
+            return HM_ENOMEM;
+        }
+        hm_layout* tl = sa == HM_OK ? new (std::nothrow) hm_layout(std::move(T.layout)) : nullptr;
+        if (sa == HM_OK && !tl) sa = HM_ENOMEM;
+        hm_upload_opts o2 = opts ? *opts : hm_upload_opts{};
+        o2.adjoint = 0;
+        if (sa == HM_OK) sa = hm_upload(tl, format, &T.v, prec, &o2, stream, &m->adj);
+        if (sa != HM_OK) {
+            delete tl;
+            hm_matrix_free(m);
+            return sa;
+        }
+        m->adj_layout = tl;
+    }
     *out = m;
     return HM_OK;
 }
 
 extern "C" void hm_matrix_free(hm_matrix* m) {
     if (!m) return;
+    if (m->adj) hm_matrix_free(m->adj);
+    delete m->adj_layout;
     for (auto* list : {&m->phases, &m->pphases})
         for (auto& ph : *list)
             for (auto& e : ph.pending) m->event_pool.push_back(e);
@@ -354,6 +379,13 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
     if (!m || !x || !y || x == y) {
         hm::set_error("hm_mvm: null matrix/vector or x == y");
         return HM_EINVAL;
+    }
+    if (flags & HM_ADJOINT) {
+        if (!m->adj) {
+            hm::set_error("hm_mvm: HM_ADJOINT needs a matrix uploaded with hm_upload_opts.adjoint = 1");
+            return HM_EINVAL;
+        }
+        return hm_mvm(m->adj, alpha, x, y, flags & ~HM_ADJOINT, stream_);
     }
     hipStream_t stream = (hipStream_t)stream_;
     int dev = -1;
@@ -624,6 +656,11 @@ extern "C" hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream_
         hm::set_error("hm_tune_mvm: null argument or reps < 1");
         return HM_EINVAL;
     }
+    if (m->adj) {   // the adjoint's schedule is tuned as well (its result is not reported)
+        hm_tune_mvm_result ra{};
+        hm_status sa = hm_tune_mvm(m->adj, reps, stream_, &ra);
+        if (sa != HM_OK) return sa;
+    }
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != m->device) {
         hm::set_error("hm_tune_mvm: current device differs from the matrix's device");
@@ -741,6 +778,12 @@ extern "C" hm_status hm_graph_create_batch(hm_matrix* const* mats, int32_t nmat,
     if (!out || (flags & HM_TIMING)) {
         hm::set_error("hm_graph_create_batch: null argument or HM_TIMING requested");
         return HM_EINVAL;
+    }
+    std::vector<hm_matrix*> adj;
+    if ((flags & HM_ADJOINT) && nmat > 0 && mats && nrhs) {
+        if (!hm::adjoint_mats(mats, nmat, nrhs, adj, "hm_graph_create_batch")) return HM_EINVAL;
+        mats = adj.data();
+        flags &= ~HM_ADJOINT;
     }
     // workspaces are sized (allocated) before the capture starts
     hm_status st = hm::batch_prepare(mats, nmat, nrhs, vec_dtype);
