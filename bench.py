@@ -67,8 +67,13 @@ POLICIES = {
     "fp8_nearfield_f64": dict(dense="f64", diag="f64", factor="fp8", coupling="fp8"),
     # uniform FP32 storage of every block (the UH config's FP32 variant)
     "f32_all": dict(dense="f32", diag="f32", factor="f32", coupling="f32"),
+    # synchronisation variants of Sec. 3.1 (FP64 storage): atomic updates of
+    # shared rows, and thread-local (here: eight private) copies of y
+    "f64_sync_atomic": dict(dense="f64", diag="f64", factor="f64", coupling="f64", sync="atomic"),
+    "f64_sync_private": dict(dense="f64", diag="f64", factor="f64", coupling="f64", sync="private"),
 }
-DEFAULT_LEGS = {"h2": "f64,f32,bf16,fp8,valr,fp8_nearfield_f64", "uh": "f64,f32_all,valr", "h": "f64,f32_all,valr"}
+DEFAULT_LEGS = {"h2": "f64,f32,bf16,fp8,valr,fp8_nearfield_f64,f64_sync_atomic,f64_sync_private",
+                "uh": "f64,f32_all,valr", "h": "f64,f32_all,valr"}
 
 
 def log(*a):
@@ -245,9 +250,9 @@ def parity(fmt, st, vals, pol, eps, x, y_gpu, points, rows):
     from oracle import dense as odense
     from oracle import omp, stored
     y0 = np.zeros(len(x))
-    sv = vals if pol == POLICIES["f64"] else stored.stored_values(
-        st, fmt, vals, dense=pol["dense"], diag=pol.get("diag"), factor=pol["factor"],
-        coupling=pol["coupling"], eps=eps)
+    sv = vals if pol["factor"] == "f64" and pol["dense"] == "f64" and pol["coupling"] == "f64" else \
+        stored.stored_values(st, fmt, vals, dense=pol["dense"], diag=pol.get("diag"), factor=pol["factor"],
+                             coupling=pol["coupling"], eps=eps)
     ref = omp.product(st, fmt, sv, 1.0, x, y0)
     del sv
     yd = odense.dense_product(0, points, 1.0, x, y0, rows=rows)

@@ -238,6 +238,15 @@ typedef struct {
                                (0 = 2 000 000); a wait past it aborts the launch (hm_matrix_check) */
     int32_t tickets_per_grab; /* persistent schedule: queue items a wavefront takes per atomic
                                  (0 = 4, at most 256) */
+    int32_t sync;           /* how tasks that share output rows combine them (Sec. 3.1 discusses
+                               the collision problem and three remedies), for comparison:
+                               HM_SYNC_OWNER (default) one owner per row cluster, split owners'
+                               partial sums added in a fixed order (deterministic);
+                               HM_SYNC_ATOMIC every task adds its rows with float64 atomic adds
+                               (no partial sums, no reduction launches; summation order varies);
+                               HM_SYNC_PRIVATE y rows are added atomically into eight private
+                               copies of y, summed by one final launch (the paper's thread-local
+                               copies).  Staged schedule only. */
     int32_t adjoint;        /* 1 = also upload the adjoint M^T (the remark after Alg. 3: the
                                product over block columns) for HM_ADJOINT products: every block
                                transposed, stored under the same precision policy; doubles the
@@ -246,6 +255,9 @@ typedef struct {
 
 #define HM_SCHED_STAGED 0
 #define HM_SCHED_PERSISTENT 1
+#define HM_SYNC_OWNER 0
+#define HM_SYNC_ATOMIC 1
+#define HM_SYNC_PRIVATE 2
 
 /* Quantise on the host per `prec`, pack into level- and row-cluster-ordered
  * streams and copy to the current HIP device.  opts may be NULL (defaults).

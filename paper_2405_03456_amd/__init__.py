@@ -146,15 +146,16 @@ def make_precision(eps=0.0, dense="f64", diag=None, factor="f64", coupling=None,
 
 
 SCHEDULES = {"persistent": _lib.HM_SCHED_PERSISTENT, "staged": _lib.HM_SCHED_STAGED}
+SYNCS = {"owner": 0, "atomic": 1, "private": 2}
 
 
 def make_opts(task_bytes: int = 0, spread_dense: bool = False, dense_grid: int = 0, fork_after: int = 0,
               valr_promote: bool = False, schedule: str = "staged", dense_after: int = 0,
-              spin_limit_us: int = 0, tickets_per_grab: int = 0, adjoint: bool = False):
+              spin_limit_us: int = 0, tickets_per_grab: int = 0, adjoint: bool = False, sync: str = "owner"):
     """hm_upload_opts (all zero = the library's defaults)."""
     return _lib.UploadOpts(int(task_bytes), int(bool(spread_dense)), int(dense_grid), int(fork_after),
                            int(bool(valr_promote)), SCHEDULES[schedule], int(dense_after), int(spin_limit_us),
-                           int(tickets_per_grab), int(bool(adjoint)))
+                           int(tickets_per_grab), SYNCS[sync], int(bool(adjoint)))
 
 
 def _stats_dict(s) -> dict:

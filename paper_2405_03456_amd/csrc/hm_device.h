@@ -192,6 +192,8 @@ struct hm_matrix {
     int32_t* p_done = nullptr;
     uint32_t* p_ctl = nullptr;   // ticket, abort, error
     hm::Queue p_queue;           // host copy (the tuner reorders it)
+    int32_t sync = HM_SYNC_OWNER;
+    double* ypriv = nullptr;     // HM_SYNC_PRIVATE: eight copies of y in cluster order
     // the adjoint M^T (HM_ADJOINT), uploaded with its own transposed layout
     hm_matrix* adj = nullptr;
     hm_layout* adj_layout = nullptr;

@@ -1455,6 +1455,13 @@ hm_status pack_options(const hm_upload_opts* o, PackOptions& opt) {
         return HM_EINVAL;
     }
     opt.adjoint = o->adjoint != 0;
+    if (o->sync < HM_SYNC_OWNER || o->sync > HM_SYNC_PRIVATE ||
+        (o->sync != HM_SYNC_OWNER && o->schedule == HM_SCHED_PERSISTENT)) {
+        set_error("hm_upload: sync must be HM_SYNC_OWNER, HM_SYNC_ATOMIC or HM_SYNC_PRIVATE (the last two with "
+                  "the staged schedule)");
+        return HM_EINVAL;
+    }
+    opt.sync = o->sync;
     opt.schedule = o->schedule;
     opt.dense_after = o->dense_after;
     if (o->spin_limit_us) opt.spin_limit_us = o->spin_limit_us;

@@ -15,6 +15,7 @@ struct PackOptions {
     int64_t spin_limit_us = 2000000;
     int32_t tickets_per_grab = 4;
     bool adjoint = false;         // also upload M^T for HM_ADJOINT products
+    int32_t sync = HM_SYNC_OWNER; // how tasks sharing output rows combine them
 };
 
 // Validated PackOptions from the ABI's hm_upload_opts (NULL = defaults).

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_persistent(
                                         [&](int32_t o) { return target[o]; }))
                 break;
             run_task<ACC64, MASK, true>(tk, lane, lds_w[wave], items, data, scales, vin, vin32, vout, vout32, part,
-                                        dsrc, y, perm, alpha, nx);
+                                        dsrc, y, perm, alpha, nx, nullptr, 0);
         } else {
             owner = ~e;
             const DOwner ow = owners[owner];

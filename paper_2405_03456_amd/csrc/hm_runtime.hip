@@ -53,16 +53,33 @@ TaskKernel task_kernel(bool acc64, int mask) {
     return mask < 16 ? kTasks32lo[mask] : kTasks32hi[mask - 16];
 }
 
-// x in cluster order: ws[i] = x[perm[i]]  (or a straight copy)
+// x in cluster order: ws[i] = x[perm[i]]  (or a straight copy); the
+// coefficient entries [n, zero_to) are cleared for atomic accumulation
 __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ x, const int64_t* __restrict__ perm,
                                                 double* __restrict__ ws, float* __restrict__ ws32, int64_t n,
-                                                int cluster_order) {
+                                                int cluster_order, int64_t zero_to) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) {
         const double v = cluster_order ? x[i] : x[perm[i]];
         ws[i] = v;
         ws32[i] = (float)v;
+    } else if (i < zero_to) {
+        ws[i] = 0.0;
     }
+}
+
+// HM_SYNC_PRIVATE: y[perm[i]] += alpha * (sum of the eight private copies
+// of row i, in copy order), and the copies cleared for the next product
+__global__ __launch_bounds__(256) void k_private_sum(double* __restrict__ y, const int64_t* __restrict__ perm,
+                                                     double* __restrict__ priv, int64_t n, double alpha) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double v = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        v += priv[c * n + i];
+        priv[c * n + i] = 0.0;
+    }
+    y[perm ? perm[i] : i] += alpha * v;
 }
 
 }  // namespace dev
@@ -147,7 +164,8 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     const size_t o_porder = align256(o_ptarget + Q.target.size() * sizeof(int32_t));
     const size_t o_pdone = align256(o_porder + qorder.size() * sizeof(int32_t));
     const size_t o_pctl = align256(o_pdone + (persist ? P.owners.size() : 0) * sizeof(int32_t));
-    size_t total = align256(o_pctl + (persist ? 256 : 0));
+    const size_t o_priv = align256(o_pctl + (persist ? 256 : 0));
+    size_t total = align256(o_priv + (opt.sync == HM_SYNC_PRIVATE ? 8 * (size_t)layout->L.n * sizeof(double) : 0));
 
     hm_matrix* m = new (std::nothrow) hm_matrix();
     if (!m) {
@@ -175,6 +193,29 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     std::vector<hm::DTask> dtasks = P.tasks;
     for (size_t k = 0; k < dtasks.size(); ++k)
         if (P.staged[k]) dtasks[k].mode = (int16_t)(dtasks[k].mode | 4);
+    if (opt.sync != HM_SYNC_OWNER) {
+        // atomic variants: no partial sums to defer or reduce; every task adds
+        // its rows atomically (mode bit 8; bit 16 = into the private copies of
+        // y), and a task reading coefficients reads them in float64 (staged,
+        // bit 2: the float32 mirror is not kept)
+        std::vector<uint8_t> coef((size_t)(P.ws_elems + hm::TILE_PAD), 0);
+        for (const auto& ow : P.owners)
+            if (ow.mode == 0)
+                for (int32_t r = 0; r < ow.nrows; ++r) coef[(size_t)(ow.out_off + r)] = 1;
+        for (auto& t : dtasks) {
+            t.mode = (int16_t)(t.mode | 8 | ((opt.sync == HM_SYNC_PRIVATE && (t.mode & 3) != 0) ? 16 : 0));
+            const hm::DOwner& ow = P.owners[t.owner];
+            int32_t c = t.c0;
+            for (int32_t it = t.item_start; c < t.c1 && it < ow.item0 + ow.nitems; ++it) {
+                const hm::DItem& item = P.items[it];
+                const int32_t jb = c - item.col0, je = std::min(item.ncols, t.c1 - item.col0);
+                for (int32_t j = jb; j < je; ++j)
+                    if (coef[(size_t)(item.vec_off + j)]) t.mode = (int16_t)(t.mode | 4);
+                c = item.col0 + je;
+            }
+        }
+        std::fill(P.dsrc.begin(), P.dsrc.end(), 0);
+    }
     e = copy(o_owners, P.owners.data(), P.owners.size() * sizeof(hm::DOwner));
     if (e == hipSuccess) e = copy(o_items, P.items.data(), P.items.size() * sizeof(hm::DItem));
     if (e == hipSuccess) e = copy(o_tasks, dtasks.data(), dtasks.size() * sizeof(hm::DTask));
@@ -193,6 +234,8 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         if (e == hipSuccess) e = hipMemset(base + o_pdone, 0, P.owners.size() * sizeof(int32_t));
         if (e == hipSuccess) e = hipMemset(base + o_pctl, 0, 256);
     }
+    if (e == hipSuccess && opt.sync == HM_SYNC_PRIVATE)
+        e = hipMemset(base + o_priv, 0, 8 * (size_t)layout->L.n * sizeof(double));
     // every workspace entry must hold a finite value before the first product:
     // zero-data padding columns multiply whatever they read
     if (e == hipSuccess) e = hipMemset(base + o_ws, 0, (P.ws_elems + hm::TILE_PAD) * sizeof(double));
@@ -227,7 +270,7 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         d.t0 = st.t0;
         d.ntasks = (int32_t)(st.t1 - st.t0);
         d.reduce = (const int32_t*)(base + o_red[i]);
-        d.nreduce = (int32_t)st.reduce_launch.size();
+        d.nreduce = opt.sync == HM_SYNC_OWNER ? (int32_t)st.reduce_launch.size() : 0;
         d.nowners = 0;
         d.dtype_mask = st.dtype_mask;
         d.data_bytes = st.data_bytes;
@@ -260,6 +303,9 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
     m->h_stages = P.stages;
     m->ws_elems = P.ws_elems;
     m->part_elems = P.part_elems;
+    m->sync = opt.sync;
+    if (opt.sync == HM_SYNC_PRIVATE) m->ypriv = (double*)(base + o_priv);
+    if (opt.sync != HM_SYNC_OWNER) P.stats.nlaunch = nlaunch;   // the plan's launches without reductions
     if (persist) {
         m->schedule = HM_SCHED_PERSISTENT;
         m->p_nq = (int32_t)qorder.size();
@@ -312,7 +358,7 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         hm::set_error("hm_upload: launch count mismatch");
         return HM_ELAYOUT;
     }
-    if (persist) m->stats.nlaunch = 2;   // gather + the persistent launch
+    m->stats.nlaunch = persist ? 2 : nlaunch + (opt.sync == HM_SYNC_PRIVATE ? 1 : 0);   // (+ the private sum)
     if (opt.adjoint) {
         // M^T over the transposed block tree, uploaded as a matrix of its own
         hm::Transposed T;
@@ -425,8 +471,9 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
         if (e != hipSuccess) return hip_fail("hm_mvm: kernel launch", e);
         return HM_OK;
     }
-    hipLaunchKernelGGL(hm::dev::k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, x, m->perm,
-                       m->ws, m->ws32, n, cluster);
+    const int64_t zero_to = m->sync != HM_SYNC_OWNER ? m->ws_elems : n;
+    hipLaunchKernelGGL(hm::dev::k_gather, dim3((unsigned)((zero_to + 255) / 256)), dim3(256), 0, stream, x, m->perm,
+                       m->ws, m->ws32, n, cluster, zero_to);
     const int64_t* perm = cluster ? nullptr : m->perm;
     const bool timing = (flags & HM_TIMING) != 0;
     const hipStream_t main_stream = stream;
@@ -471,12 +518,12 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
                 hipExtLaunchKernelGGL(kern, grid, dim3(256), 0, stream, ev.first, ev.second, 0, m->tasks + ph.t0,
                                       ph.ntasks, m->owners, m->items, m->data, m->scales, (const double*)m->ws,
                                       (const float*)m->ws32, m->ws, m->ws32, m->part, (const int64_t*)m->dsrc, y,
-                                      perm, alpha);
+                                      perm, alpha, m->ypriv, n);
                 ph.pending.push_back(ev);
             } else {
                 hipLaunchKernelGGL(kern, grid, dim3(256), 0, stream, m->tasks + ph.t0, ph.ntasks, m->owners,
                                    m->items, m->data, m->scales, m->ws, m->ws32, m->ws, m->ws32, m->part, m->dsrc, y,
-                                   perm, alpha);
+                                   perm, alpha, m->ypriv, n);
             }
         }
         if (ph.nreduce > 0) {
@@ -493,6 +540,9 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
         (void)hipEventRecord(m->ev_join, m->aux);
         (void)hipStreamWaitEvent(main_stream, m->ev_join, 0);
     }
+    if (m->sync == HM_SYNC_PRIVATE)
+        hipLaunchKernelGGL(hm::dev::k_private_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, main_stream, y,
+                           perm, m->ypriv, n, alpha);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail("hm_mvm: kernel launch", e);
     return HM_OK;

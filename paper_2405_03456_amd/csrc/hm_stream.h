@@ -306,7 +306,7 @@ __device__ __forceinline__ void run_task(const DTask& tk, int lane, double* __re
                                          const float* __restrict__ vin32, double* vout, float* vout32,
                                          double* __restrict__ part, const int64_t* __restrict__ dsrc,
                                          double* __restrict__ y, const int64_t* __restrict__ perm, double alpha,
-                                         int nx) {
+                                         int nx, double* ypriv, int64_t npriv) {
     const int nrows = tk.nrows;
     int lp = 0;                         // log2 P
     while ((1 << lp) < nrows && lp < 6) ++lp;
@@ -349,10 +349,24 @@ __device__ __forceinline__ void run_task(const DTask& tk, int lane, double* __re
         for (int off = P; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);   // across column groups
         if (act && g == 0) {
             if (tk.rscale_off >= 0) v *= scales[tk.rscale_off + r];
-            if (tk.ntasks == 1)
+            if (tk.mode & 8) {
+                // atomic synchronisation (Sec. 3.1's alternative to row
+                // ownership): every task adds its rows with float64 atomics,
+                // into y, into the coefficient vector (zeroed at the start),
+                // or (mode bit 16) into one of eight private copies of y
+                // (cluster order) that a final launch sums
+                if (mode == 0)
+                    atomicAdd(vout + tk.out_off + r, v);
+                else if (tk.mode & 16)
+                    atomicAdd(ypriv + (int64_t)(blockIdx.x & 7) * npriv + tk.out_off + r, v);
+                else
+                    atomicAdd(y + (mode == 1 && perm ? perm[tk.out_off + r] : (int64_t)(tk.out_off + r)),
+                              alpha * v);
+            } else if (tk.ntasks == 1) {
                 finalize<COH>(mode, tk.out_off, r, v, vout, vout32, y, perm, alpha);
-            else
+            } else {
                 st_dev<COH>(part + tk.part_off + (int64_t)tk.local * nrows + r, v);
+            }
         }
     }
 }
@@ -413,7 +427,7 @@ __global__ __launch_bounds__(256) void k_owner_tasks(
     const DItem* __restrict__ items, const uint8_t* __restrict__ data, const double* __restrict__ scales,
     const double* __restrict__ vin, const float* __restrict__ vin32, double* vout, float* vout32,
     double* __restrict__ part, const int64_t* __restrict__ dsrc, double* __restrict__ y,
-    const int64_t* __restrict__ perm, double alpha) {
+    const int64_t* __restrict__ perm, double alpha, double* ypriv, int64_t npriv) {
     __shared__ double lds_w[4][MAX_TASK_INPUTS];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -422,12 +436,12 @@ __global__ __launch_bounds__(256) void k_owner_tasks(
     // t, t + stride, ... (used to leave compute units to a concurrent stage)
     for (int t = blockIdx.x * 4 + wave; t < ntasks; t += gridDim.x * 4)
         run_task<ACC64, MASK, false>(tasks[t], lane, lds_w[wave], items, data, scales, vin, vin32, vout, vout32,
-                                     part, dsrc, y, perm, alpha, 0);
+                                     part, dsrc, y, perm, alpha, 0, ypriv, npriv);
 }
 
 using TaskKernel = void (*)(const DTask*, int, const DOwner*, const DItem*, const uint8_t*, const double*,
                             const double*, const float*, double*, float*, double*, const int64_t*, double*,
-                            const int64_t*, double);
+                            const int64_t*, double, double*, int64_t);
 
 // k_owner_tasks<acc64, mask> (instantiated in hm_tasks_*.hip)
 TaskKernel task_kernel(bool acc64, int mask);
