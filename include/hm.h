@@ -210,8 +210,9 @@ typedef struct hm_matrix hm_matrix;
 /* Engine options of hm_upload (NULL, or every field 0, gives the defaults).
  * None of them changes what is computed; they change how the work is cut
  * into tasks and launches, and valr_promote the storage choice.
- *   task_bytes     target stored bytes per task (one wavefront); 0 = 32768,
- *                  else at least 1024
+ *   task_bytes     target stored bytes per task (one wavefront); 0 = 32768 for
+ *                  float64 data and 16384 for the narrower formats, else at
+ *                  least 1024 (for every format)
  *   spread_dense   1 = spread the dense leaves over the dependent stages
  *                  instead of one stage on a second stream
  *   dense_grid     cap on the workgroups of that second-stream stage (0 = none)

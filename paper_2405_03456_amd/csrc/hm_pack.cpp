@@ -387,7 +387,10 @@ struct Builder {
             // ones when they read unreduced sums): at most MAX_TASK_INPUTS
             // input values (tiles * V) per task
             const int64_t cap = (int64_t)(MAX_TASK_INPUTS / V) * bpt;
-            const int64_t target = std::min<int64_t>(opt.task_bytes, cap);
+            // default task size by storage format (measured on the single-
+            // vector product): 32 KiB of float64 tiles, 16 KiB of narrower ones
+            const int64_t tb = opt.task_bytes ? opt.task_bytes : (it.dtype == HM_F64 ? 32768 : 16384);
+            const int64_t target = std::min<int64_t>(tb, cap);
             int32_t j = 0;
             while (j < it.ncols) {
                 int64_t room = target - acc;
