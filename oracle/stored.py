@@ -11,7 +11,12 @@ coupling and transfer matrices (direct compression, Sec. 4.1).  For the H^2
 column transfers F the scaled axis is a row of F.  Under VALR (Sec. 4.2)
 each column of a low-rank factor or cluster basis gets the cheapest format
 that meets its own error budget, and the other classes the cheapest format
-whose unit roundoff is at most eps.  The result is a copy of
+whose unit roundoff is at most eps.  The policies "aflp" and "fpx" do the
+same with the paper's own codecs (oracle.codecs): direct compression of the
+dense, coupling and transfer classes at eps, VALR over the codec's widths
+for factors and bases (one AFLP exponent width per stored matrix).  Fixed
+codec widths ("fpx24", "aflp24", ...) store a class in that format.  The
+result is a copy of
 the values with every stored matrix replaced by its dequantised version, so
 the products in oracle.mvm give the exact product of the stored matrix.
 """
@@ -21,10 +26,13 @@ import copy
 
 import numpy as np
 
-from . import quant
+from . import codecs, quant
 
 DT = {"f64": quant.F64, "f32": quant.F32, "bf16": quant.BF16, "f16": quant.F16, "fp8": quant.FP8,
-      "valr": quant.VALR}
+      "valr": quant.VALR, "aflp": codecs.AFLP_AUTO, "fpx": codecs.FPX_AUTO,
+      **{name: code for code, name in codecs.NAMES.items()}}
+ADAPTIVE = (quant.VALR, codecs.AFLP_AUTO, codecs.FPX_AUTO)
+NCODES = 19
 
 
 def direct_format(eps: float) -> int:
@@ -105,11 +113,36 @@ class _Store:
         if A is None:
             return None
         f = DT[fmt]
+        A = np.asarray(A, dtype=np.float64)
         if f == quant.VALR:
             f = direct_format(self.eps)
-        A = np.asarray(A, dtype=np.float64)
+        elif f == codecs.FPX_AUTO:
+            f = codecs.fpx_code_for_eps(self.eps)
+        elif f == codecs.AFLP_AUTO or codecs.is_aflp(f):
+            return self._aflp_direct(A, f)
         self._count(f, A.size)
+        if codecs.is_fpx(f):
+            return np.asfortranarray(codecs.fpx_stored(A, f))
         return quant.stored(A, f)
+
+    def _aflp_direct(self, A, f):
+        """AFLP over a whole stored matrix: one exponent width e; the width
+        from eps (policy) or at least the requested one (fixed)."""
+        if A.size == 0:
+            return A.copy()
+        e = codecs.aflp_ebits(A)
+        if f == codecs.AFLP_AUTO:
+            B = codecs.aflp_direct_width(e, self.eps)
+        else:
+            B = codecs.AFLP_WIDTH[f]
+            while B <= 7 and not codecs.aflp_feasible(B, e):
+                B += 1
+            B = B if B <= 7 else None
+        if B is None:
+            self._count(quant.F64, A.size)
+            return np.asfortranarray(A.copy())
+        self._count(codecs.AFLP[B], A.size)
+        return codecs.aflp_stored(A, e, B)
 
     def direct_rows(self, A, fmt):
         """Direct compression with the scaled axis along the rows of A."""
@@ -123,31 +156,47 @@ class _Store:
         if A is None:
             return None
         f = DT[fmt]
-        if f != quant.VALR:
+        if f not in ADAPTIVE:
             return self.direct(A, fmt)
         A = np.asarray(A, dtype=np.float64)
         out = np.zeros_like(A, order="F")
-        for j, fj in enumerate(valr_factor_formats(A, deltas)):
-            self._count(fj, A.shape[0])
-            out[:, j] = quant.stored(A[:, j:j + 1], fj)[:, 0]
+        if f == quant.VALR:
+            for j, fj in enumerate(valr_factor_formats(A, deltas)):
+                self._count(fj, A.shape[0])
+                out[:, j] = quant.stored(A[:, j:j + 1], fj)[:, 0]
+        elif f == codecs.FPX_AUTO:
+            for j, fj in enumerate(codecs.valr_fpx_codes(A, deltas)):
+                self._count(fj, A.shape[0])
+                out[:, j] = codecs.fpx_stored(A[:, j], fj)
+        else:
+            e = codecs.aflp_ebits(A)
+            for j, B in enumerate(codecs.valr_aflp_widths(A, deltas, e)):
+                if B is None:
+                    self._count(quant.F64, A.shape[0])
+                    out[:, j] = A[:, j]
+                else:
+                    self._count(codecs.AFLP[B], A.shape[0])
+                    out[:, j] = codecs.aflp_stored_column(A[:, j], e, B)
         return out
 
 
 def stored_values(st, fmt: str, values, dense="f64", diag=None, factor="f64", coupling=None,
                   eps: float = 0.0, counts=None):
-    """The values as stored.  `counts` (length >= 5, optional) accumulates
+    """The values as stored.  `counts` (length >= 19, optional) accumulates
     the stored entries per format code.  Under "valr" the dense and
     coupling/transfer classes are direct-compressed at eps, the diagonal
     dense blocks stay FP64, and factors/bases take VALR per column, which
-    needs the singular values (H: sigma; UH/H2: row_sv/col_sv)."""
+    needs the singular values (H: sigma; UH/H2: row_sv/col_sv).  Under
+    "aflp" / "fpx" every class given that policy, the diagonal blocks
+    included, is compressed with the codec (Sec. 4.1-4.2)."""
     diag = diag or dense
     coupling = coupling or factor
     if DT[diag] == quant.VALR:
         diag = "f64"
-    if quant.VALR in (DT[dense], DT[factor], DT[coupling]) and not eps > 0:
-        raise ValueError("VALR storage needs eps > 0")
+    if any(DT[c] in ADAPTIVE for c in (dense, diag, factor, coupling)) and not eps > 0:
+        raise ValueError("adaptive storage needs eps > 0")
     S = _Store(eps, counts)
-    valr = DT[factor] == quant.VALR
+    valr = DT[factor] in ADAPTIVE
     out = copy.copy(values)
     out.dense = [None if values.dense[b] is None else
                  S.direct(values.dense[b], diag if st.blk_tau[b] == st.blk_sigma[b] else dense)
