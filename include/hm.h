@@ -50,12 +50,44 @@ typedef enum {
 
 typedef enum { HM_FMT_H = 0, HM_FMT_UH = 1, HM_FMT_H2 = 2 } hm_format;
 
-/* Storage formats (Table 1).  FP8 is OCP E4M3 (no infinities, max 448).
- * HM_VALR_AUTO picks per column the cheapest format whose measured error
- * meets delta_i = delta / sigma_i (Sec. 4.2, eq. 6-7). */
+/* Storage formats.  Hardware formats (Table 1): FP8 is OCP E4M3 (no
+ * infinities, max 448).  HM_VALR_AUTO picks per column the cheapest of them
+ * whose measured error meets delta_i = delta / sigma_i (Sec. 4.2, eq. 6-7).
+ *
+ * Byte-aligned codecs of Sec. 4.1 (a stored value of B bytes; a 16-byte
+ * tile row holds floor(16 / B) of them at byte offsets 0, B, 2B, ..., each
+ * least significant byte first, the rest of the row zero):
+ *   FPX (the table of Sec. 4.1): the leading B bytes of the FP32 (8 exponent
+ *   bits) or FP64 (11 bits) encoding, rounded to nearest, ties to even:
+ *   HM_FPX24 = (8, 15), HM_FPX40 = (11, 28), HM_FPX48 = (11, 36),
+ *   HM_FPX56 = (11, 44) (exponent, mantissa bits); the other rows are
+ *   HM_BF16 = (8, 7), HM_F32 = (8, 23) and HM_F64 = (11, 52).
+ *   AFLP (HM_AFLP8 ... HM_AFLP56, B = 1 ... 7): code = sign | z (e bits) |
+ *   M (m' = 8B - 1 - e bits), value = sign * 2^k * 2^(z-1) * (1 + M/2^m'),
+ *   z = 0 (with M = 0) is zero.  k (per column, a power-of-two scale) is
+ *   floor(log2) of the column's smallest nonzero magnitude; e (per stored
+ *   matrix) is the bit length of the largest code z = floor(log2(vmax/2^k))
+ *   + 1 over its columns.  M is rounded to nearest (ties to even, a carry
+ *   moves to z + 1); codes beyond the largest saturate.  Widths up to 3
+ *   bytes need e <= 7, wider ones e <= 10.
+ * Policies (not storage formats), valid in every hm_precision field:
+ *   HM_AFLP_AUTO / HM_FPX_AUTO: direct compression at eps (AFLP: width
+ *   B = ceil((1 + e + m_eps) / 8), m_eps = ceil(-log2 eps); FPX: the first
+ *   row with m >= m_eps) for dense, coupling and transfer matrices, and VALR
+ *   over the codec's widths (the narrowest whose measured column error meets
+ *   delta_i) for low-rank factors and cluster bases.  A fixed AFLP width is
+ *   raised to the first width that holds the matrix's e; past 7 bytes, and
+ *   for eps below 2^-52, FP64 is stored. */
 typedef enum {
-    HM_F64 = 0, HM_F32 = 1, HM_BF16 = 2, HM_F16 = 3, HM_FP8E4M3 = 4, HM_VALR_AUTO = 5
+    HM_F64 = 0, HM_F32 = 1, HM_BF16 = 2, HM_F16 = 3, HM_FP8E4M3 = 4, HM_VALR_AUTO = 5,
+    HM_FPX24 = 6, HM_FPX40 = 7, HM_FPX48 = 8, HM_FPX56 = 9,
+    HM_AFLP8 = 10, HM_AFLP16 = 11, HM_AFLP24 = 12, HM_AFLP32 = 13, HM_AFLP40 = 14, HM_AFLP48 = 15,
+    HM_AFLP56 = 16,
+    HM_AFLP_AUTO = 17, HM_FPX_AUTO = 18
 } hm_dtype;
+
+/* number of storage dtype codes (arrays indexed by dtype; code 5 is unused) */
+#define HM_NDTYPES 17
 
 typedef enum { HM_ACC_AUTO = 0, HM_ACC_F32 = 1, HM_ACC_F64 = 2 } hm_accum;
 
@@ -276,9 +308,9 @@ typedef struct {
     int64_t n, nblocks, ndense, nlowrank;
     int64_t bytes_dense, bytes_factors, bytes_coupling, bytes_transfer, bytes_scales;
     int64_t bytes_meta, bytes_workspace;
-    int64_t bytes_per_dtype[5];     /* stored matrix data by dtype (HM_F64..HM_FP8E4M3) */
-    int64_t entries_per_dtype[5];   /* stored matrix entries by dtype, each source matrix once,
-                                       without tile padding */
+    int64_t bytes_per_dtype[HM_NDTYPES];     /* stored matrix data by dtype (16-byte tiles) */
+    int64_t entries_per_dtype[HM_NDTYPES];   /* stored matrix entries by dtype, each source matrix
+                                                once, without tile padding */
     int64_t sum_rank;               /* sum of block ranks (H) or basis ranks (UH/H2) */
     int32_t max_rank;
     int32_t accum;                  /* resolved accumulation (HM_ACC_F32 / HM_ACC_F64) */
@@ -286,7 +318,8 @@ typedef struct {
     double algorithmic_bytes;       /* bytes one hm_mvm moves: stored data (16-byte tiles, padding
                                        included) + scales + vectors + coefficients + plan metadata */
     double method_bytes;            /* bytes the product itself needs: every stored entry once at its
-                                       element size, a float32 scale per FP16/FP8 column, x read,
+                                       element size (codecs: B bytes), a float32 scale per FP16/FP8/
+                                       AFLP column, x read,
                                        y read and written, every coefficient written and read once */
 } hm_stats;
 
@@ -560,8 +593,21 @@ hm_status hm_serve_stats_read(hm_server* s, hm_serve_stats* out);
 void hm_serve_destroy(hm_server* s);
 
 /* Host-side helper used by tests: round float64 values to `dtype` exactly as
- * hm_upload does (scale already applied); writes float64 results. */
+ * hm_upload does (scale already applied); writes float64 results.  Hardware
+ * formats and FPX codes only (AFLP needs a whole column: hm_codec_column). */
 hm_status hm_round_host(int32_t dtype, const double* in, double* out, int64_t count);
+
+/* Host-side codec of one column exactly as hm_upload stores it (Sec. 4.1).
+ * dtype: a storage format, or HM_AFLP_AUTO / HM_FPX_AUTO with eps > 0 (direct
+ * compression).  ebits: the AFLP exponent width to use (<= 0: the column's
+ * own).  col: m float64 values (host).  On return stored[i] is the value the
+ * product multiplies, codes[i] (may be NULL) the B-byte code word (FP64 and
+ * the hardware formats: their bit pattern), and info[0..3] = stored dtype,
+ * bytes per value, AFLP e (0 otherwise), AFLP scale exponent k (0 otherwise).
+ * HM_EINVAL: bad dtype, null pointers, non-finite data, an AFLP width that
+ * cannot hold the requested e. */
+hm_status hm_codec_column(int32_t dtype, double eps, int32_t ebits, const double* col, int64_t m, double* stored,
+                          uint64_t* codes, int32_t* info);
 
 const char* hm_last_error(void);
 const char* hm_version(void);

@@ -81,8 +81,11 @@ def nbytes(code: int) -> int:
 
 
 def m_eps(eps: float) -> int:
-    """m_eps = ceil(-log2 eps) (Sec. 4.1), at least 0."""
-    return max(0, math.ceil(-math.log2(eps)))
+    """m_eps = ceil(-log2 eps) (Sec. 4.1), at least 0, evaluated exactly:
+    with eps = g 2^E, g in [0.5, 1), -log2 eps = -E - log2 g and
+    -log2 g lies in (0, 1], so the ceiling is 1 - E."""
+    _, E = math.frexp(eps)
+    return max(0, 1 - E)
 
 
 # ---------------------------------------------------------------- FPX
@@ -190,41 +193,34 @@ def aflp_encode_column(col, e: int, B: int):
     col = np.asarray(col, dtype=np.float64)
     mp = 8 * B - 1 - e
     k = aflp_scale_exp(col)
-    sign = (np.signbit(col)).astype(np.int64)
+    a = np.ldexp(np.abs(col), -k)                # exact: a power-of-two scale
+    nz = a > 0
+    sign = (np.signbit(col) & nz).astype(np.int64)
     z = np.zeros(col.shape, dtype=np.int64)
     M = np.zeros(col.shape, dtype=np.int64)
-    zlim = (1 << e) - 1
-    for i, v in enumerate(col):
-        a = math.ldexp(abs(float(v)), -k)        # exact: a power-of-two scale
-        if a == 0.0:
-            sign[i] = 0
-            continue
-        f, E = math.frexp(a)                     # a = f 2^E, f in [0.5, 1)
-        E -= 1                                   # a = 2^E (1 + frac)
-        frac = 2.0 * f - 1.0                     # exact
-        t = math.ldexp(frac, mp)                 # exact: frac has <= 52 bits
-        Mi = round(t)                            # Python round: ties to even
-        if Mi == (1 << mp):
-            Mi = 0
-            E += 1
-        zi = E + 1
-        if zi > zlim:                            # saturate at the largest code
-            zi, Mi = zlim, (1 << mp) - 1
-        z[i] = zi
-        M[i] = Mi
+    f, E = np.frexp(a[nz])                       # a = f 2^E, f in [0.5, 1)
+    E = E.astype(np.int64) - 1                   # a = 2^E (1 + frac)
+    frac = 2.0 * f - 1.0                         # exact
+    Mi = np.round(np.ldexp(frac, mp)).astype(np.int64)   # exact scaling; ties to even
+    carry = Mi == (1 << mp)
+    Mi[carry] = 0
+    E[carry] += 1
+    zi = E + 1
+    sat = zi > (1 << e) - 1                      # saturate at the largest code
+    zi[sat] = (1 << e) - 1
+    Mi[sat] = (1 << mp) - 1
+    z[nz] = zi
+    M[nz] = Mi
     return sign, z, M, k
 
 
 def aflp_decode(sign, z, M, k: int, e: int, B: int) -> np.ndarray:
     """sign * 2^k * 2^(z-1) * (1 + M / 2^m'); z = 0 is zero."""
     mp = 8 * B - 1 - e
-    out = np.zeros(len(z), dtype=np.float64)
-    for i in range(len(z)):
-        if z[i] == 0:
-            continue
-        mag = math.ldexp(1.0 + math.ldexp(float(M[i]), -mp), int(z[i]) - 1 + k)
-        out[i] = -mag if sign[i] else mag
-    return out
+    z = np.asarray(z, dtype=np.int64)
+    mag = np.ldexp(1.0 + np.ldexp(np.asarray(M, dtype=np.float64), -mp), z - 1 + k)
+    mag[z == 0] = 0.0
+    return np.where(np.asarray(sign) != 0, -mag, mag)
 
 
 def aflp_code_word(s: int, z: int, M: int, e: int, B: int) -> int:

@@ -18,7 +18,13 @@ from ._lib import (HM_ACC_AUTO, HM_ACC_F32, HM_ACC_F64, HM_BF16, HM_CLUSTER_ORDE
 FORMATS = {"h": HM_FMT_H, "uh": HM_FMT_UH, "h2": HM_FMT_H2}
 PARTITIONS = {"standard": _lib.HM_PART_STANDARD, "hodlr": _lib.HM_PART_HODLR, "blr": _lib.HM_PART_BLR}
 DTYPES = {"f64": HM_F64, "f32": HM_F32, "bf16": HM_BF16, "f16": HM_F16, "fp8": HM_FP8E4M3,
-          "valr": HM_VALR_AUTO}
+          "valr": HM_VALR_AUTO,
+          # byte-aligned codecs (Sec. 4.1): fixed formats and the adaptive policies
+          "fpx24": _lib.HM_FPX24, "fpx40": _lib.HM_FPX40, "fpx48": _lib.HM_FPX48, "fpx56": _lib.HM_FPX56,
+          "aflp8": _lib.HM_AFLP8, "aflp16": _lib.HM_AFLP16, "aflp24": _lib.HM_AFLP24,
+          "aflp32": _lib.HM_AFLP32, "aflp40": _lib.HM_AFLP40, "aflp48": _lib.HM_AFLP48,
+          "aflp56": _lib.HM_AFLP56, "aflp": _lib.HM_AFLP_AUTO, "fpx": _lib.HM_FPX_AUTO}
+DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
 
 
 def _dptr(a):
@@ -494,6 +500,18 @@ def round_host(dtype: str, values) -> np.ndarray:
     out = np.empty_like(a)
     _lib.check(_lib.lib().hm_round_host(DTYPES[dtype], _dptr(a), _dptr(out), a.size))
     return out
+
+
+def codec_column(dtype: str, values, eps: float = 0.0, ebits: int = 0):
+    """The library's storage of one column (host, for tests): (stored values,
+    code words, {"dtype", "bytes", "ebits", "k"})."""
+    a = np.ascontiguousarray(values, dtype=np.float64)
+    out = np.empty_like(a)
+    codes = np.zeros(a.size, dtype=np.uint64)
+    info = (ctypes.c_int32 * 4)()
+    _lib.check(_lib.lib().hm_codec_column(DTYPES[dtype], float(eps), int(ebits), _dptr(a), a.size, _dptr(out),
+                                          codes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), info))
+    return out, codes, {"dtype": DTYPE_NAMES[info[0]], "bytes": info[1], "ebits": info[2], "k": info[3]}
 
 
 def version() -> str:

@@ -17,6 +17,10 @@ P = ctypes.POINTER
 HM_OK, HM_EINVAL, HM_ENOMEM, HM_EDEVICE, HM_ELAYOUT, HM_EBUSY, HM_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
 HM_FMT_H, HM_FMT_UH, HM_FMT_H2 = 0, 1, 2
 HM_F64, HM_F32, HM_BF16, HM_F16, HM_FP8E4M3, HM_VALR_AUTO = 0, 1, 2, 3, 4, 5
+HM_FPX24, HM_FPX40, HM_FPX48, HM_FPX56 = 6, 7, 8, 9
+HM_AFLP8, HM_AFLP16, HM_AFLP24, HM_AFLP32, HM_AFLP40, HM_AFLP48, HM_AFLP56 = 10, 11, 12, 13, 14, 15, 16
+HM_AFLP_AUTO, HM_FPX_AUTO = 17, 18
+HM_NDTYPES = 17
 HM_ACC_AUTO, HM_ACC_F32, HM_ACC_F64 = 0, 1, 2
 HM_CLUSTER_ORDER = 1
 HM_ADJOINT = 4
@@ -77,8 +81,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("n", c_int64), ("nblocks", c_int64), ("ndense", c_int64), ("nlowrank", c_int64),
                 ("bytes_dense", c_int64), ("bytes_factors", c_int64), ("bytes_coupling", c_int64),
                 ("bytes_transfer", c_int64), ("bytes_scales", c_int64), ("bytes_meta", c_int64),
-                ("bytes_workspace", c_int64), ("bytes_per_dtype", c_int64 * 5),
-                ("entries_per_dtype", c_int64 * 5), ("sum_rank", c_int64),
+                ("bytes_workspace", c_int64), ("bytes_per_dtype", c_int64 * HM_NDTYPES),
+                ("entries_per_dtype", c_int64 * HM_NDTYPES), ("sum_rank", c_int64),
                 ("max_rank", c_int32), ("accum", c_int32), ("nlaunch", c_int32),
                 ("algorithmic_bytes", c_double), ("method_bytes", c_double)]
 
@@ -150,6 +154,8 @@ SIGNATURES = {
     "hm_serve_stats_read": (c_int32, [c_void_p, P(ServeStats)]),
     "hm_serve_destroy": (None, [c_void_p]),
     "hm_round_host": (c_int32, [c_int32, P(c_double), P(c_double), c_int64]),
+    "hm_codec_column": (c_int32, [c_int32, c_double, c_int32, P(c_double), c_int64, P(c_double), P(ctypes.c_uint64),
+                                  P(c_int32)]),
     "hm_last_error": (ctypes.c_char_p, []),
     "hm_version": (ctypes.c_char_p, []),
 }

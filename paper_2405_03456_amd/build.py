@@ -16,10 +16,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhm.so")
 ARCH = os.environ.get("HM_OFFLOAD_ARCH", "gfx950")
 
-HOST_SRCS = ["hm_layout.cpp", "hm_quant.cpp", "hm_pack.cpp", "hm_queue.cpp", "hm_adjoint.cpp"]
-DEVICE_SRCS = ["hm_runtime.hip", "hm_tasks_a32_lo.hip", "hm_tasks_a32_hi.hip", "hm_tasks_a64_lo.hip",
-               "hm_tasks_a64_hi.hip", "hm_batch.hip", "hm_serve.hip"]
-HEADERS = ["hm_internal.h", "hm_plan.h", "hm_pack.h", "hm_device.h", "hm_stream.h"]
+# every translation unit of csrc/: host C++ (*.cpp) and device code (*.hip)
+HOST_SRCS = sorted(f for f in os.listdir(CSRC) if f.endswith(".cpp"))
+DEVICE_SRCS = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-ffp-contract=off"]
 DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -42,21 +42,18 @@ namespace mr {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <int DT> struct Bytes;
-template <> struct Bytes<HM_F64> { static constexpr int v = 8; };
-template <> struct Bytes<HM_F32> { static constexpr int v = 4; };
-template <> struct Bytes<HM_BF16> { static constexpr int v = 2; };
-template <> struct Bytes<HM_F16> { static constexpr int v = 2; };
-template <> struct Bytes<HM_FP8E4M3> { static constexpr int v = 1; };
-
 __device__ __forceinline__ uint32_t word(const uint4& q, int i) {
     return i == 0 ? q.x : i == 1 ? q.y : i == 2 ? q.z : q.w;
 }
 
 // element c (compile-time after unrolling) of a tile row, widened to T
+// (e: the task's AFLP exponent width)
 template <int DT, typename T>
-__device__ __forceinline__ T elem(const uint4& q, int c) {
-    if constexpr (DT == HM_F64) {
+__device__ __forceinline__ T elem(const uint4& q, int c, int e) {
+    if constexpr (DT >= HM_FPX24) {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        return (T)dev::Tile<DT>::elem(w, c, e);
+    } else if constexpr (DT == HM_F64) {
         return (T)(c == 0 ? __hiloint2double((int)q.y, (int)q.x) : __hiloint2double((int)q.w, (int)q.z));
     } else if constexpr (DT == HM_F32) {
         return (T)__uint_as_float(word(q, c));
@@ -118,7 +115,7 @@ __device__ __forceinline__ void put(const DTask& tk, const Outs& o, int row, int
     if (tk.rscale_off >= 0) v *= o.scales[tk.rscale_off + row];
     if (tk.ntasks > 1) {
         o.partm[((int64_t)tk.part_off + (int64_t)tk.local * tk.nrows + row) * o.R + j] = v;
-    } else if (tk.mode == 0) {
+    } else if ((tk.mode & 3) == 0) {
         const int64_t i = (int64_t)(tk.out_off + row) * o.R + j;
         if (o.mat64)
             o.wsm[i] = v;
@@ -140,7 +137,8 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
                                           const float* __restrict__ wsm32, int j0, int lane, const Outs& o) {
     using M = Mfma<ACC64>;
     using T = typename M::T;
-    constexpr int V = 16 / Bytes<DT>::v;
+    constexpr int V = dev::Tile<DT>::V;
+    const int ebits = dev::task_ebits(tk.mode);
     const int rl = lane & 15, kq = lane >> 4;
     const int nrows = tk.nrows, r0 = tk.pad;
     const int nrg = min(4, (nrows - r0 + 15) / 16);
@@ -216,7 +214,7 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
 #pragma unroll
             for (int g = 0; g < 4; ++g)
                 if (g < nrg) {
-                    const T a = elem<DT, T>(f.q[g], c);
+                    const T a = elem<DT, T>(f.q[g], c, ebits);
 #pragma unroll
                     for (int b = 0; b < NRB; ++b) acc[g][b] = M::step(a, f.b[c][b], acc[g][b]);
                 }
@@ -313,6 +311,23 @@ __device__ __forceinline__ void task_wave(const DTask* __restrict__ tasks, int64
             if constexpr ((MASK & (1 << HM_FP8E4M3)) != 0)
                 task_rows<HM_FP8E4M3, ACC64, NRB>(tk, items, data, wsm, wsm32, j0, lane, o);
             break;
+#define HM_MR_CASE(D)                                                                                    \
+    case D:                                                                                             \
+        if constexpr ((MASK & (1 << D)) != 0)                                                           \
+            task_rows<D, ACC64 || dev::kWide<D>, NRB>(tk, items, data, wsm, wsm32, j0, lane, o);         \
+        break;
+            HM_MR_CASE(HM_FPX24)
+            HM_MR_CASE(HM_FPX40)
+            HM_MR_CASE(HM_FPX48)
+            HM_MR_CASE(HM_FPX56)
+            HM_MR_CASE(HM_AFLP8)
+            HM_MR_CASE(HM_AFLP16)
+            HM_MR_CASE(HM_AFLP24)
+            HM_MR_CASE(HM_AFLP32)
+            HM_MR_CASE(HM_AFLP40)
+            HM_MR_CASE(HM_AFLP48)
+            HM_MR_CASE(HM_AFLP56)
+#undef HM_MR_CASE
         default: {
             // a task without columns contributes zero
             for (int idx = lane; idx < 64 * 16 * NRB; idx += 64) {
@@ -501,33 +516,25 @@ __global__ __launch_bounds__(256) void k_scatter(YT* __restrict__ Y, int64_t ldy
 using TaskKernel = void (*)(const DTask*, int, int, const DItem*, const uint8_t*, const double*, double*, float*,
                             double*, double*, int, int64_t);
 
-// [acc64][NRB - 1][dtype of a single-dtype stage, or 5 = several]
-#define HM_MR_ROW(A, N)                                                                                  \
+// [acc64][NRB - 1][dtype of a single-dtype run of tasks; entry 5 = all
+// hardware formats]
+#define HM_MR_ROW(K, A, N)                                                                               \
     {                                                                                                   \
-        &k_tasks<A, N, 1 << HM_F64>, &k_tasks<A, N, 1 << HM_F32>, &k_tasks<A, N, 1 << HM_BF16>,         \
-            &k_tasks<A, N, 1 << HM_F16>, &k_tasks<A, N, 1 << HM_FP8E4M3>, &k_tasks<A, N, 31>              \
+        &K<A, N, 1 << 0>, &K<A, N, 1 << 1>, &K<A, N, 1 << 2>, &K<A, N, 1 << 3>, &K<A, N, 1 << 4>,       \
+            &K<A, N, 31>, &K<A, N, 1 << 6>, &K<A, N, 1 << 7>, &K<A, N, 1 << 8>, &K<A, N, 1 << 9>,        \
+            &K<A, N, 1 << 10>, &K<A, N, 1 << 11>, &K<A, N, 1 << 12>, &K<A, N, 1 << 13>,                 \
+            &K<A, N, 1 << 14>, &K<A, N, 1 << 15>, &K<A, N, 1 << 16>                                     \
     }
-static const TaskKernel kTasks[2][2][6] = {{HM_MR_ROW(false, 1), HM_MR_ROW(false, 2)},
-                                           {HM_MR_ROW(true, 1), HM_MR_ROW(true, 2)}};
-#undef HM_MR_ROW
+static const TaskKernel kTasks[2][2][HM_NDTYPES] = {
+    {HM_MR_ROW(k_tasks, false, 1), HM_MR_ROW(k_tasks, false, 2)},
+    {HM_MR_ROW(k_tasks, true, 1), HM_MR_ROW(k_tasks, true, 2)}};
 
 using MultiKernel = void (*)(const Jobs);
-#define HM_MR_ROW(A, N)                                                                                  \
-    {                                                                                                   \
-        &k_tasks_multi<A, N, 1 << HM_F64>, &k_tasks_multi<A, N, 1 << HM_F32>,                           \
-            &k_tasks_multi<A, N, 1 << HM_BF16>, &k_tasks_multi<A, N, 1 << HM_F16>,                      \
-            &k_tasks_multi<A, N, 1 << HM_FP8E4M3>, &k_tasks_multi<A, N, 31>                               \
-    }
-static const MultiKernel kMulti[2][2][6] = {{HM_MR_ROW(false, 1), HM_MR_ROW(false, 2)},
-                                            {HM_MR_ROW(true, 1), HM_MR_ROW(true, 2)}};
+static const MultiKernel kMulti[2][2][HM_NDTYPES] = {
+    {HM_MR_ROW(k_tasks_multi, false, 1), HM_MR_ROW(k_tasks_multi, false, 2)},
+    {HM_MR_ROW(k_tasks_multi, true, 1), HM_MR_ROW(k_tasks_multi, true, 2)}};
 #undef HM_MR_ROW
 
-// kernel variant for a stage with dtype set `mask`
-static int variant(int mask) {
-    for (int d = 0; d < 5; ++d)
-        if (mask == (1 << d)) return d;
-    return 5;
-}
 
 }  // namespace mr
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -28,14 +29,15 @@ __device__ __forceinline__ float fp8_to_f32(uint8_t b) {
     return (b & 0x80u) ? -mag : mag;
 }
 
-// A 16-byte tile row holds V = 16 / element-size consecutive columns of one
-// slab row.  decode<DT> widens the V stored values (float32 for the
-// narrow formats, float64 for FP64).
+// A 16-byte tile row holds V = floor(16 / element size) consecutive columns
+// of one slab row.  decode<DT> widens the V stored values (float32 for the
+// narrow formats, float64 for FP64 and the wide codecs); e is the AFLP
+// exponent width of the task (ignored by the other formats).
 template <int DT> struct Tile;
 template <> struct Tile<HM_F64> {
     static constexpr int V = 2;
     using R = double;
-    __device__ static void decode(const uint4& q, R* o) {
+    __device__ static void decode(const uint4& q, R* o, int) {
         o[0] = __hiloint2double((int)q.y, (int)q.x);
         o[1] = __hiloint2double((int)q.w, (int)q.z);
     }
@@ -43,7 +45,7 @@ template <> struct Tile<HM_F64> {
 template <> struct Tile<HM_F32> {
     static constexpr int V = 4;
     using R = float;
-    __device__ static void decode(const uint4& q, R* o) {
+    __device__ static void decode(const uint4& q, R* o, int) {
         o[0] = __uint_as_float(q.x);
         o[1] = __uint_as_float(q.y);
         o[2] = __uint_as_float(q.z);
@@ -53,7 +55,7 @@ template <> struct Tile<HM_F32> {
 template <> struct Tile<HM_BF16> {
     static constexpr int V = 8;
     using R = float;
-    __device__ static void decode(const uint4& q, R* o) {
+    __device__ static void decode(const uint4& q, R* o, int) {
         const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -65,7 +67,7 @@ template <> struct Tile<HM_BF16> {
 template <> struct Tile<HM_F16> {
     static constexpr int V = 8;
     using R = float;
-    __device__ static void decode(const uint4& q, R* o) {
+    __device__ static void decode(const uint4& q, R* o, int) {
         const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -88,13 +90,112 @@ __device__ __forceinline__ void fp8x4_to_f32(uint32_t w, float* o) {
 template <> struct Tile<HM_FP8E4M3> {
     static constexpr int V = 16;
     using R = float;
-    __device__ static void decode(const uint4& q, R* o) {
+    __device__ static void decode(const uint4& q, R* o, int) {
         fp8x4_to_f32(q.x, o);
         fp8x4_to_f32(q.y, o + 4);
         fp8x4_to_f32(q.z, o + 8);
         fp8x4_to_f32(q.w, o + 12);
     }
 };
+
+// ---- byte-aligned codecs (Sec. 4.1).  Code c of a B-byte format sits at
+// bytes [cB, cB + B) of the 16-byte row, least significant byte first.
+// bytes_at(w, o): the 32-bit little-endian word starting at byte o of the
+// row (o is a constant once the decode loops are unrolled; bytes past the
+// row read as zero).
+__device__ __forceinline__ uint32_t bytes_at(const uint32_t* w, int o) {
+    const int i = o >> 2, sh = o & 3;
+    const uint32_t lo = w[i], hi = i < 3 ? w[i + 1] : 0u;
+    return sh == 0 ? lo : __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)sh);
+}
+
+// FPX: the leading B bytes of the FP32 (B = 3) or FP64 (B = 5, 6, 7)
+// encoding; the dropped low bytes are zero.
+template <int B> struct FpxCodec {
+    static constexpr int V = 16 / B;
+    using R = typename std::conditional<(B <= 4), float, double>::type;
+    __device__ static R elem(const uint32_t* w, int c) {
+        if constexpr (B == 3) {
+            return __uint_as_float(bytes_at(w, 3 * c) << 8);
+        } else {
+            const uint32_t hi = bytes_at(w, B * c + B - 4);
+            const uint32_t lo = bytes_at(w, B * c) << (32 - 8 * (B - 4));
+            return __hiloint2double((int)hi, (int)lo);
+        }
+    }
+};
+
+// AFLP: code = sign | z (e bits) | M (m' = 8B - 1 - e bits), value (before
+// the column's scale 2^k) 2^(z-1) (1 + M / 2^m'), z = 0 zero.  Left-aligned
+// in a 32-bit (B <= 3) or 64-bit word, the e + m' bits below the sign,
+// shifted right by 8 - e (11 - e), land on the IEEE exponent and mantissa
+// fields: the word then encodes 2^(z-127) (1 + f) (2^(z-1023) (1 + f)), and
+// one exact multiplication by 2^126 (2^1022) gives the value; the zero code
+// stays zero.  e <= 7 (float32) and e <= 10 (float64) are guaranteed by the
+// upload.
+template <int B> struct AflpCodec {
+    static constexpr int V = 16 / B;
+    using R = typename std::conditional<(B <= 3), float, double>::type;
+    __device__ static R elem(const uint32_t* w, int c, int e) {
+        if constexpr (B <= 3) {
+            const uint32_t L = bytes_at(w, B * c) << (32 - 8 * B);
+            const uint32_t t = ((L & 0x7FFFFFFFu) >> (8 - e)) | (L & 0x80000000u);
+            return __uint_as_float(t) * 0x1p126f;
+        } else {
+            const uint32_t hi = bytes_at(w, B * c + B - 4);
+            const uint32_t lo = B > 4 ? bytes_at(w, B * c) << (32 - 8 * (B - 4)) : 0u;
+            const uint32_t hs = hi & 0x7FFFFFFFu;
+            const uint32_t sh = (uint32_t)(11 - e);
+            const uint32_t lo2 = __builtin_amdgcn_alignbit(hs, lo, sh);
+            const uint32_t hi2 = (hs >> sh) | (hi & 0x80000000u);
+            return __hiloint2double((int)hi2, (int)lo2) * 0x1p1022;
+        }
+    }
+};
+
+template <int B> struct FpxTile {
+    static constexpr int V = FpxCodec<B>::V;
+    using R = typename FpxCodec<B>::R;
+    __device__ static R elem(const uint32_t* w, int c, int) { return FpxCodec<B>::elem(w, c); }
+    __device__ static void decode(const uint4& q, R* o, int) {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int c = 0; c < V; ++c) o[c] = FpxCodec<B>::elem(w, c);
+    }
+};
+template <int B> struct AflpTile {
+    static constexpr int V = AflpCodec<B>::V;
+    using R = typename AflpCodec<B>::R;
+    __device__ static R elem(const uint32_t* w, int c, int e) { return AflpCodec<B>::elem(w, c, e); }
+    __device__ static void decode(const uint4& q, R* o, int e) {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int c = 0; c < V; ++c) o[c] = AflpCodec<B>::elem(w, c, e);
+    }
+};
+template <> struct Tile<HM_FPX24> : FpxTile<3> {};
+template <> struct Tile<HM_FPX40> : FpxTile<5> {};
+template <> struct Tile<HM_FPX48> : FpxTile<6> {};
+template <> struct Tile<HM_FPX56> : FpxTile<7> {};
+template <> struct Tile<HM_AFLP8> : AflpTile<1> {};
+template <> struct Tile<HM_AFLP16> : AflpTile<2> {};
+template <> struct Tile<HM_AFLP24> : AflpTile<3> {};
+template <> struct Tile<HM_AFLP32> : AflpTile<4> {};
+template <> struct Tile<HM_AFLP40> : AflpTile<5> {};
+template <> struct Tile<HM_AFLP48> : AflpTile<6> {};
+template <> struct Tile<HM_AFLP56> : AflpTile<7> {};
+
+// float64 decode (wide accumulation whatever the matrix's mode)
+template <int DT> constexpr bool kWide = std::is_same<typename Tile<DT>::R, double>::value;
+
+// AFLP exponent width of a task (bits 8-11 of its mode)
+__device__ __forceinline__ int task_ebits(int16_t mode) { return (mode >> 8) & 15; }
+
+// dtype sets of the kernel instantiations that cover the codecs
+constexpr int kMaskHw = 31;   // HM_F64 .. HM_FP8E4M3
+constexpr int kMaskFpx = (1 << HM_F64) | (1 << HM_F32) | (1 << HM_BF16) | (0xF << HM_FPX24);
+constexpr int kMaskAflp = (1 << HM_F64) | (1 << HM_F32) | (0x7F << HM_AFLP8);
+constexpr int kMaskAll = kMaskHw | (0x7FF << HM_FPX24);
 
 }  // namespace dev
 

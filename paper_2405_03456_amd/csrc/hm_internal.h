@@ -38,6 +38,22 @@ int dtype_bytes(int32_t dtype);
 // encode a value that is already representable in dtype into its bit pattern
 uint64_t encode(int32_t dtype, double v);
 
+// Codecs of Sec. 4.1 (FPX rows, AFLP)
+bool is_fpx(int32_t dt);
+bool is_aflp(int32_t dt);
+int aflp_width(int32_t dt);                 // bytes of an AFLP dtype
+int32_t aflp_dtype(int bytes);
+bool storage_dtype(int32_t dt);             // a format values can be stored in
+int m_eps(double eps);                      // ceil(-log2 eps)
+int32_t fpx_for_eps(double eps);            // FPX row (as a dtype) for accuracy eps
+int aflp_scale_exp(const double* col, int64_t m);      // k of the column scale 2^k
+int aflp_column_ebits(const double* col, int64_t m);   // exponent bits of one column
+int aflp_matrix_ebits(const double* A, int64_t m, int64_t k);
+bool aflp_feasible(int bytes, int e);
+int aflp_direct_width(int e, double eps);   // bytes for direct compression (0: FP64)
+// code word of v (scale 2^k, exponent width e, B bytes); *value = the stored value
+uint64_t aflp_encode(double v, int k, int e, int bytes, double* value);
+
 }  // namespace hm
 
 struct hm_layout {

@@ -47,6 +47,7 @@ struct Source {
     std::vector<double> own;     // storage if A is a host-made copy (transposes)
     int64_t m = 0, k = 0;
     int32_t dtype = HM_F64;
+    int32_t ebits = 0;           // AFLP exponent width (0 for the other formats)
     const double* colfactor = nullptr;   // folded into the column scale (sigma of W_b)
     int32_t scale_off = -1;      // per-column scales c_j * f_j (shared by all uses)
     std::vector<Use> uses;
@@ -55,15 +56,18 @@ struct Source {
 
 // Slabs are stored in 16-byte tiles: tile t of an item holds columns
 // [t*V, t*V+V) of all its rows, row-major (one 16-byte chunk per row), with
-// V = 16 / element size.  Missing columns of the last tile are zero.
+// V = floor(16 / element size) (3-, 5-, 6- and 7-byte codecs leave the end
+// of the chunk zero).  Missing columns of the last tile are zero.
 int tile_cols(int32_t dt) { return 16 / dtype_bytes(dt); }
 int64_t tile_count(int32_t dt, int64_t ncols) { return (ncols + tile_cols(dt) - 1) / tile_cols(dt); }
 
-// formats whose columns carry a range scale (narrow exponent range)
-bool range_scaled(int32_t dt) { return dt == HM_F16 || dt == HM_FP8E4M3; }
+// formats whose columns carry a scale: narrow exponent range (FP16, FP8) or
+// AFLP's power-of-two scale
+bool range_scaled(int32_t dt) { return dt == HM_F16 || dt == HM_FP8E4M3 || is_aflp(dt); }
 
-// Storage scale of one column (1 for FP64/FP32/BF16) and its codes.
+// Storage scale of one column (1 for FP64/FP32/BF16/FPX) and its codes.
 double column_scale(const double* col, int64_t m, int32_t dt) {
+    if (is_aflp(dt)) return std::ldexp(1.0, aflp_scale_exp(col, m));
     if (!range_scaled(dt)) return 1.0;
     double mx = 0.0;
     for (int64_t i = 0; i < m; ++i) mx = std::max(mx, std::fabs(col[i]));
@@ -89,6 +93,58 @@ int32_t valr_choose(const double* col, int64_t m, double delta) {
     }
     return HM_F64;
 }
+
+// VALR (Sec. 4.2) over the codecs of Sec. 4.1: the narrowest AFLP width
+// (exponent width e of the factor) or the first FPX row whose measured
+// column error is at most delta; FP64 otherwise.
+int32_t valr_choose_aflp(const double* col, int64_t m, double delta, int e) {
+    const double d2 = delta * delta;
+    const int k = aflp_scale_exp(col, m);
+    for (int B = 1; B <= 7; ++B) {
+        if (!aflp_feasible(B, e)) continue;
+        double e2 = 0.0;
+        for (int64_t i = 0; i < m; ++i) {
+            double q;
+            aflp_encode(col[i], k, e, B, &q);
+            const double d = col[i] - q;
+            e2 = e2 + d * d;
+        }
+        if (e2 <= d2) return aflp_dtype(B);
+    }
+    return HM_F64;
+}
+
+int32_t valr_choose_fpx(const double* col, int64_t m, double delta) {
+    static const int32_t ladder[6] = {HM_BF16, HM_FPX24, HM_F32, HM_FPX40, HM_FPX48, HM_FPX56};
+    const double d2 = delta * delta;
+    for (int32_t dt : ladder) {
+        double e2 = 0.0;
+        for (int64_t i = 0; i < m; ++i) {
+            const double d = col[i] - round_to(dt, col[i]);
+            e2 = e2 + d * d;
+        }
+        if (e2 <= d2) return dt;
+    }
+    return HM_F64;
+}
+
+// Per-column formats of one factor under an adaptive policy: the codec
+// ladders (e: the factor's AFLP exponent width), or the hardware ladder
+// (valr_formats).
+std::vector<int32_t> valr_formats(const double* A, int64_t m, int64_t k, const std::vector<double>& deltas,
+                                  bool promote);
+std::vector<int32_t> column_formats(int32_t policy, const double* A, int64_t m, int64_t k,
+                                    const std::vector<double>& deltas, bool promote, int e) {
+    if (policy == HM_VALR_AUTO) return valr_formats(A, m, k, deltas, promote);
+    std::vector<int32_t> dts((size_t)k);
+    for (int64_t j = 0; j < k; ++j)
+        dts[(size_t)j] = policy == HM_AFLP_AUTO ? valr_choose_aflp(A + j * m, m, deltas[(size_t)j], e)
+                                                : valr_choose_fpx(A + j * m, m, deltas[(size_t)j]);
+    return dts;
+}
+
+bool adaptive(int32_t dt) { return dt == HM_VALR_AUTO || dt == HM_AFLP_AUTO || dt == HM_FPX_AUTO; }
+bool aflp_kind(int32_t dt) { return dt == HM_AFLP_AUTO || is_aflp(dt); }
 
 // VALR formats of the k columns of one factor: each column's cheapest format
 // (valr_choose, Sec. 4.2).  With `promote` (a storage choice of this
@@ -154,12 +210,30 @@ struct Builder {
         return off;
     }
 
+    // dt may be a codec policy or a fixed AFLP width: resolved here from the
+    // matrix (ebits > 0: the AFLP exponent width already fixed by the whole
+    // factor this source is a run of)
     int32_t add_source(const double* A, int64_t m, int64_t k, int32_t dt, const double* colfactor,
-                       int cls) {
+                       int cls, int ebits = 0) {
         Source s;
         s.A = A;
         s.m = m;
         s.k = k;
+        if (aflp_kind(dt)) {
+            const int e = ebits > 0 ? ebits : (A ? aflp_matrix_ebits(A, m, k) : 1);
+            int B = 0;
+            if (dt == HM_AFLP_AUTO) {
+                B = aflp_direct_width(e, eps);
+            } else {
+                B = aflp_width(dt);
+                while (B <= 7 && !aflp_feasible(B, e)) ++B;
+                if (B > 7) B = 0;
+            }
+            dt = B ? aflp_dtype(B) : HM_F64;
+            s.ebits = B ? e : 0;
+        } else if (dt == HM_FPX_AUTO) {
+            dt = fpx_for_eps(eps);
+        }
         s.dtype = dt;
         s.colfactor = colfactor;
         s.cls = cls;
@@ -182,17 +256,25 @@ struct Builder {
     // deltas: per-column error budget delta_j of VALR (unused otherwise);
     // breaks (optional): brk[j] != 0 forces a run to start at column j
     // dts_in (optional): the formats, already chosen, of the k columns
+    // es_in (optional): their AFLP exponent widths (else one for the factor)
     std::vector<Run> add_factor(const double* A, int64_t m, int64_t k, const double* colfactor, int cls,
                                 const std::vector<double>& deltas, const std::vector<uint8_t>* brk = nullptr,
-                                const std::vector<int32_t>* dts_in = nullptr) {
+                                const std::vector<int32_t>* dts_in = nullptr,
+                                const std::vector<int32_t>* es_in = nullptr) {
         std::vector<Run> runs;
         if (k == 0) return runs;
+        // AFLP: one exponent width for the whole factor (every run of it)
+        const int e = aflp_kind(factor_dt) && !es_in ? aflp_matrix_ebits(A, m, k) : 0;
         std::vector<int32_t> dts(k, factor_dt);
-        if (factor_dt == HM_VALR_AUTO) dts = dts_in ? *dts_in : valr_formats(A, m, k, deltas, opt.valr_promote);
+        if (adaptive(factor_dt))
+            dts = dts_in ? *dts_in : column_formats(factor_dt, A, m, k, deltas, opt.valr_promote, e);
+        std::vector<int32_t> es(k, e);
+        if (es_in) es = *es_in;
         int64_t j0 = 0;
         for (int64_t j = 1; j <= k; ++j)
-            if (j == k || dts[j] != dts[j0] || (brk && (*brk)[(size_t)j])) {
-                runs.push_back(Run{add_source(A + j0 * m, m, j - j0, dts[j0], colfactor ? colfactor + j0 : nullptr, cls),
+            if (j == k || dts[j] != dts[j0] || es[j] != es[j0] || (brk && (*brk)[(size_t)j])) {
+                runs.push_back(Run{add_source(A + j0 * m, m, j - j0, dts[j0], colfactor ? colfactor + j0 : nullptr, cls,
+                                              es[j0]),
                                    (int32_t)j0, (int32_t)(j - j0)});
                 j0 = j;
             }
@@ -235,11 +317,12 @@ struct Builder {
 
     // host transpose (for F^T), stored inside the source
     int32_t add_source_transposed(const double* A, int64_t m, int64_t k, int32_t dt, int cls) {
-        int32_t id = add_source(nullptr, k, m, dt, nullptr, cls);
-        Source& s = src[id];
-        s.own.resize((size_t)(m * k));
+        std::vector<double> T((size_t)(m * k));
         for (int64_t j = 0; j < k; ++j)
-            for (int64_t i = 0; i < m; ++i) s.own[(size_t)(j + i * k)] = A[i + j * m];
+            for (int64_t i = 0; i < m; ++i) T[(size_t)(j + i * k)] = A[i + j * m];
+        int32_t id = add_source(T.data(), k, m, dt, nullptr, cls);
+        Source& s = src[id];
+        s.own = std::move(T);   // the buffer moves with its data
         s.A = s.own.data();
         return id;
     }
@@ -302,7 +385,7 @@ struct Builder {
         it.vec_off = vec_off;
         it.scale_off = (transposed || unscaled) ? -1 : S.scale_off;
         it.dtype = (int16_t)S.dtype;
-        it.acc64 = S.dtype == HM_F64 ? 1 : 0;
+        it.ebits = (int16_t)S.ebits;
         items.push_back(it);
         item_floating.push_back(floats ? 1 : 0);
         item_use.emplace_back(s, (int32_t)S.uses.size());
@@ -311,9 +394,9 @@ struct Builder {
         S.uses.push_back(Use{it.data_off, r0, nr, transposed});
     }
 
-    // Order the owner's items by (floating, dtype), stably, so that each dtype
-    // is one run of columns and tasks (which hold one dtype) are cut only at
-    // the few run boundaries; mixed-format factors would otherwise split an
+    // Order the owner's items by (floating, dtype, AFLP exponent width),
+    // stably, so that each dtype is one run of columns and tasks (which hold
+    // one dtype and one exponent width) are cut only at the few run boundaries; mixed-format factors would otherwise split an
     // owner at every format change.  Columns, tiles and data offsets are
     // reassigned in the new order (the items' data is one contiguous block).
     void group_items() {
@@ -321,7 +404,9 @@ struct Builder {
         if (n < 2) return;
         std::vector<int32_t> order(n);
         for (int32_t i = 0; i < n; ++i) order[i] = i;
-        auto key = [&](int32_t i) { return item_floating[i0 + i] * 8 + items[i0 + i].dtype; };
+        auto key = [&](int32_t i) {
+            return (item_floating[i0 + i] * 32 + items[i0 + i].dtype) * 16 + items[i0 + i].ebits;
+        };
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
         bool same = true;
         for (int32_t i = 0; i < n; ++i) same &= order[i] == i;
@@ -375,9 +460,11 @@ struct Builder {
         for (int32_t i = 0; i < cur.nitems; ++i) {
             const int32_t ii = cur.item0 + i;
             const DItem& it = items[ii];
-            // a task never mixes floating and fixed items, nor two dtypes
+            // a task never mixes floating and fixed items, nor two dtypes or
+            // AFLP exponent widths
             if (i > 0 && start_col < it.col0 &&
-                (item_floating[ii] != item_floating[ii - 1] || it.dtype != items[ii - 1].dtype)) {
+                (item_floating[ii] != item_floating[ii - 1] || it.dtype != items[ii - 1].dtype ||
+                 it.ebits != items[ii - 1].ebits)) {
                 emit(it.col0);
                 start_item = ii;
             }
@@ -430,8 +517,9 @@ struct Builder {
             t.k1 = tile_of(t.c1);
             t.stream = stream;
             t.nrows = cur.nrows;
-            t.mode = (int16_t)cur.mode;
             t.dtype = (int16_t)(t.c0 < t.c1 ? items[t.item_start].dtype : -1);
+            // mode bits 8..11: the AFLP exponent width of the task's items
+            t.mode = (int16_t)(cur.mode | (t.c0 < t.c1 ? items[t.item_start].ebits << 8 : 0));
             t.out_off = cur.out_off;
             t.ntasks = cur.ntasks;
             t.part_off = cur.part_off;
@@ -512,12 +600,12 @@ struct Builder {
         return d;
     }
     bool need_sv(const double* const* sv, int32_t v, int32_t k) {
-        if (factor_dt != HM_VALR_AUTO || k == 0) return true;
+        if (!adaptive(factor_dt) || k == 0) return true;
         return check(sv && sv[v], "VALR storage needs row_sv / col_sv basis weights");
     }
     std::vector<Run> basis_factor(const double* A, int64_t m, int64_t k, const double* const* sv, int32_t v) {
         std::vector<double> d;
-        if (factor_dt == HM_VALR_AUTO) d = deltas_for(sv[v], k, eps * norm2(sv[v], k) / (double)k);
+        if (adaptive(factor_dt)) d = deltas_for(sv[v], k, eps * norm2(sv[v], k) / (double)k);
         return add_factor(A, m, k, nullptr, 1, d);
     }
 
@@ -531,24 +619,27 @@ struct Builder {
     std::vector<Run> grouped_basis(const double* A, int64_t m, int64_t k, const double* const* sv, int32_t v,
                                    std::vector<int32_t>& perm) {
         perm.clear();
-        if (factor_dt != HM_VALR_AUTO || k == 0) return basis_factor(A, m, k, sv, v);
+        if (!adaptive(factor_dt) || k == 0) return basis_factor(A, m, k, sv, v);
         std::vector<double> d = deltas_for(sv[v], k, eps * norm2(sv[v], k) / (double)k);
-        const std::vector<int32_t> dts = valr_formats(A, m, k, d, opt.valr_promote);
+        const int e = aflp_kind(factor_dt) ? aflp_matrix_ebits(A, m, k) : 0;   // of the whole basis
+        const std::vector<int32_t> dts = column_formats(factor_dt, A, m, k, d, opt.valr_promote, e);
         std::vector<int32_t> order((size_t)k);
         for (int64_t j = 0; j < k; ++j) order[(size_t)j] = (int32_t)j;
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return dts[a] < dts[b]; });
         bool same = true;
         for (int64_t j = 0; j < k; ++j) same &= order[(size_t)j] == j;
-        if (same) return add_factor(A, m, k, nullptr, 1, d);
+        if (same) return add_factor(A, m, k, nullptr, 1, d, nullptr, &dts);
         pool.emplace_back((size_t)(m * k));
         std::vector<double>& P = pool.back();
         std::vector<double> dp((size_t)k);
+        std::vector<int32_t> dtp((size_t)k);
         for (int64_t p = 0; p < k; ++p) {
             std::memcpy(P.data() + p * m, A + (int64_t)order[(size_t)p] * m, sizeof(double) * (size_t)m);
             dp[(size_t)p] = d[(size_t)order[(size_t)p]];
+            dtp[(size_t)p] = dts[(size_t)order[(size_t)p]];
         }
         perm = order;
-        return add_factor(P.data(), m, k, nullptr, 1, dp);
+        return add_factor(P.data(), m, k, nullptr, 1, dp, nullptr, &dtp);
     }
     // columns of a (rows x cols) matrix in the order perm (empty: A itself)
     const double* permute_cols(const double* A, int64_t rows, int64_t cols, const std::vector<int32_t>& perm) {
@@ -610,25 +701,35 @@ struct Builder {
                 const int32_t k = V->rank[b];
                 std::memcpy(Xs.data() + c0 * ms, V->X[b], sizeof(double) * (size_t)(ms * k));
                 std::vector<double> d((size_t)k, 0.0);
-                if (factor_dt == HM_VALR_AUTO)
+                if (adaptive(factor_dt))
                     d = deltas_for(V->sigma[b], k, eps * norm2(V->sigma[b], k) / (1.0 + 2.0 * k));
                 Ds.insert(Ds.end(), d.begin(), d.end());
                 c0 += k;
             }
-            // order of the stacked columns: by X's format under VALR
+            // order of the stacked columns: by X's format under VALR (and
+            // AFLP exponent width: each X_b is its own stored matrix, with
+            // its own e, though stacked)
             std::vector<int32_t> order((size_t)K), inv((size_t)K);
             for (int64_t o = 0; o < K; ++o) order[(size_t)o] = (int32_t)o;
             std::vector<int32_t> dtx((size_t)K, factor_dt);   // X's formats, chosen per block
-            if (factor_dt == HM_VALR_AUTO) {
+            std::vector<int32_t> esx((size_t)K, 0);           // X's AFLP exponent widths
+            if (adaptive(factor_dt) || aflp_kind(factor_dt)) {
                 int64_t o0 = 0;
                 for (int32_t b : col_lr[s]) {
                     const int32_t k = V->rank[b];
                     std::vector<double> d(Ds.begin() + o0, Ds.begin() + o0 + k);
-                    const std::vector<int32_t> f = valr_formats(Xs.data() + o0 * ms, ms, k, d, opt.valr_promote);
-                    std::copy(f.begin(), f.end(), dtx.begin() + o0);
+                    const double* Xb = Xs.data() + o0 * ms;
+                    const int e = aflp_kind(factor_dt) ? aflp_matrix_ebits(Xb, ms, k) : 0;
+                    if (adaptive(factor_dt)) {
+                        const std::vector<int32_t> f = column_formats(factor_dt, Xb, ms, k, d, opt.valr_promote, e);
+                        std::copy(f.begin(), f.end(), dtx.begin() + o0);
+                    }
+                    std::fill(esx.begin() + o0, esx.begin() + o0 + k, e);
                     o0 += k;
                 }
-                std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return dtx[a] < dtx[b]; });
+                std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+                    return dtx[a] != dtx[b] ? dtx[a] < dtx[b] : esx[a] < esx[b];
+                });
             }
             for (int64_t p = 0; p < K; ++p) inv[(size_t)order[(size_t)p]] = (int32_t)p;
             const int32_t base = (int32_t)ws;
@@ -651,7 +752,7 @@ struct Builder {
             }
             const double* Xo = Xs.data();
             std::vector<double> Dp = Ds;
-            std::vector<int32_t> dtp = dtx;
+            std::vector<int32_t> dtp = dtx, esp = esx;
             bool same = true;
             for (int64_t p = 0; p < K; ++p) same &= order[(size_t)p] == p;
             if (!same) {
@@ -662,10 +763,11 @@ struct Builder {
                                 sizeof(double) * (size_t)ms);
                     Dp[(size_t)p] = Ds[(size_t)order[(size_t)p]];
                     dtp[(size_t)p] = dtx[(size_t)order[(size_t)p]];
+                    esp[(size_t)p] = esx[(size_t)order[(size_t)p]];
                 }
                 Xo = Xp.data();
             }
-            std::vector<Run> xr = add_factor(Xo, ms, K, nullptr, 1, Dp, nullptr, &dtp);
+            std::vector<Run> xr = add_factor(Xo, ms, K, nullptr, 1, Dp, nullptr, &dtp, &esp);
             for (const Run& r : xr) {
                 // row scale: X's range scale times the U-side column scale
                 // (sigma_j and W's range scale) of the same column
@@ -874,7 +976,7 @@ struct Builder {
         scales.assign((size_t)nscales, 1.0);
         std::vector<int> bad(src.size(), 0);
         auto work = [&](size_t i0, size_t i1) {
-            std::vector<double> codes;
+            std::vector<uint64_t> codes;   // the stored bit pattern of every entry
             std::vector<double> c;
             for (size_t si = i0; si < i1; ++si) {
                 Source& S = src[si];
@@ -882,30 +984,33 @@ struct Builder {
                 const int64_t m = S.m, k = S.k;
                 codes.resize((size_t)(m * k));
                 c.assign((size_t)k, 1.0);
-                const double fmax = dtype_max(S.dtype);
                 for (int64_t j = 0; j < k; ++j) {
                     const double* col = S.A + j * m;
-                    double mx = 0.0;
-                    for (int64_t i = 0; i < m; ++i) {
+                    for (int64_t i = 0; i < m; ++i)
                         if (!std::isfinite(col[i])) bad[si] = 1;
-                        double a = std::fabs(col[i]);
-                        if (a > mx) mx = a;
-                    }
-                    (void)mx;
-                    (void)fmax;
+                    if (bad[si]) break;
                     const double cj = column_scale(col, m, S.dtype);
                     c[(size_t)j] = cj;
+                    if (is_aflp(S.dtype)) {   // codes relative to the column's 2^k
+                        const int kj = aflp_scale_exp(col, m);
+                        double q;
+                        for (int64_t i = 0; i < m; ++i)
+                            codes[(size_t)(i + j * m)] = aflp_encode(col[i], kj, S.ebits, aflp_width(S.dtype), &q);
+                        continue;
+                    }
                     for (int64_t i = 0; i < m; ++i)
-                        codes[(size_t)(i + j * m)] = round_to(S.dtype, cj == 1.0 ? col[i] : col[i] / cj);
+                        codes[(size_t)(i + j * m)] =
+                            encode(S.dtype, round_to(S.dtype, cj == 1.0 ? col[i] : col[i] / cj));
                 }
+                if (bad[si]) continue;
                 if (S.scale_off >= 0)
                     for (int64_t j = 0; j < k; ++j)
                         scales[(size_t)(S.scale_off + j)] = c[(size_t)j] * (S.colfactor ? S.colfactor[j] : 1.0);
                 const int eb = dtype_bytes(S.dtype);
                 const int V = tile_cols(S.dtype);
-                // slab element (row a, column b) of an R-row slab, tiled
-                auto put = [&](uint8_t* dst, int64_t R, int64_t a, int64_t b, double v) {
-                    uint64_t bits = encode(S.dtype, v);
+                // slab element (row a, column b) of an R-row slab, tiled: the
+                // code's eb bytes, least significant first, at byte (b % V) * eb
+                auto put = [&](uint8_t* dst, int64_t R, int64_t a, int64_t b, uint64_t bits) {
                     std::memcpy(dst + (size_t)(((b / V) * R + a) * 16 + (b % V) * eb), &bits, (size_t)eb);
                 };
                 for (const Use& u : S.uses) {
@@ -982,7 +1087,8 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
             }
             tile += (int32_t)tile_count(it.dtype, it.ncols);
             const int64_t padded = tile_count(it.dtype, it.ncols) * (16 / eb);
-            if (it.data_off < 0 || (it.data_off & 15) || it.data_off + (int64_t)ow.nrows * 16 * (padded * eb / 16) > nd) {
+            if (it.data_off < 0 || (it.data_off & 15) ||
+                it.data_off + (int64_t)ow.nrows * 16 * tile_count(it.dtype, it.ncols) > nd) {
                 why = "item data";
                 return false;
             }
@@ -1024,7 +1130,7 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
             const DTask& t = P.tasks[k];
             if (t.owner < 0 || t.owner >= no) { why = "task owner"; return false; }
             const DOwner& ow = P.owners[t.owner];
-            if (t.nrows != ow.nrows || t.mode != ow.mode || t.out_off != ow.out_off || t.ntasks != ow.ntasks ||
+            if (t.nrows != ow.nrows || (t.mode & 0xFF) != ow.mode || t.out_off != ow.out_off || t.ntasks != ow.ntasks ||
                 t.part_off != ow.part_off || t.rscale_off != ow.rscale_off) {
                 why = "task copy of owner fields";
                 return false;
@@ -1050,12 +1156,19 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
                 if (t.item_start < ow.item0 || t.item_start >= ow.item0 + ow.nitems) { why = "task item"; return false; }
                 const DItem& fi = P.items[t.item_start];
                 if (t.k0 != fi.tile0 + (t.c0 - fi.col0) / (16 / dtype_bytes(fi.dtype))) { why = "task first tile"; return false; }
+                if (((t.mode >> 8) & 15) != fi.ebits || (is_aflp(fi.dtype) && !aflp_feasible(aflp_width(fi.dtype), fi.ebits))) {
+                    why = "task AFLP exponent width";
+                    return false;
+                }
                 const DItem& it = P.items[t.item_start];
                 if (t.c0 < it.col0 || t.c0 >= it.col0 + it.ncols) { why = "task first item"; return false; }
                 if ((t.c0 - it.col0) % (16 / dtype_bytes(it.dtype))) { why = "task not tile aligned"; return false; }
                 // one dtype per task; the inputs fit the LDS slice
                 for (int32_t j = t.item_start; j < ow.item0 + ow.nitems && P.items[j].col0 < t.c1; ++j)
-                    if (P.items[j].dtype != it.dtype) { why = "task mixes dtypes"; return false; }
+                    if (P.items[j].dtype != it.dtype || P.items[j].ebits != it.ebits) {
+                        why = "task mixes dtypes";
+                        return false;
+                    }
                 if ((int64_t)(t.k1 - t.k0) * (16 / dtype_bytes(it.dtype)) > MAX_TASK_INPUTS) {
                     why = "task inputs exceed LDS slice";
                     return false;
@@ -1115,14 +1228,14 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
         return HM_EINVAL;
     }
     for (int32_t dt : {p->dense_dtype, p->diag_dtype, p->factor_dtype, p->coupling_dtype})
-        if (dt < HM_F64 || dt > HM_VALR_AUTO) {
+        if (!storage_dtype(dt) && !adaptive(dt)) {
             set_error("hm_upload: unsupported dtype");
             return HM_EINVAL;
         }
-    const bool valr = p->dense_dtype == HM_VALR_AUTO || p->diag_dtype == HM_VALR_AUTO ||
-                      p->factor_dtype == HM_VALR_AUTO || p->coupling_dtype == HM_VALR_AUTO;
+    const bool valr = adaptive(p->dense_dtype) || adaptive(p->diag_dtype) || adaptive(p->factor_dtype) ||
+                      adaptive(p->coupling_dtype);
     if (valr && !(p->eps > 0.0 && std::isfinite(p->eps))) {
-        set_error("hm_upload: VALR_AUTO needs eps > 0");
+        set_error("hm_upload: VALR_AUTO / AFLP_AUTO / FPX_AUTO need eps > 0");
         return HM_EINVAL;
     }
     if (p->accum < HM_ACC_AUTO || p->accum > HM_ACC_F64) {
@@ -1156,7 +1269,7 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
         set_error("hm_upload: " + B.err);
         return HM_ELAYOUT;
     }
-    int64_t per_dtype[6] = {0, 0, 0, 0, 0, 0};
+    int64_t per_dtype[HM_NDTYPES] = {};
     int64_t per_class[4] = {0, 0, 0, 0};
     if (!B.fill(out.data, out.scales, per_dtype, per_class)) {
         set_error("hm_upload: " + B.err);
@@ -1301,7 +1414,7 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
     s.bytes_factors = per_class[1];
     s.bytes_coupling = per_class[2];
     s.bytes_transfer = per_class[3];
-    for (int d = 0; d < 5; ++d) s.bytes_per_dtype[d] = per_dtype[d];
+    for (int d = 0; d < HM_NDTYPES; ++d) s.bytes_per_dtype[d] = per_dtype[d];
     s.bytes_scales = (int64_t)out.scales.size() * 8;
     int64_t meta = (int64_t)(out.owners.size() * sizeof(DOwner) + out.items.size() * sizeof(DItem) +
                              out.tasks.size() * sizeof(DTask));

@@ -147,20 +147,22 @@ __global__ __launch_bounds__(256) void k_gather_reset(const double* __restrict__
     }
 }
 
-// Instantiated dtype sets: the smallest of these containing the matrix's
+// Instantiated dtype sets: the first of these containing the matrix's
 // dtypes is launched (a task switches on its own dtype inside).
-static constexpr int kPersistMasks[7] = {1, 2, 3, 7, 11, 19, 31};
+static constexpr int kNPersist = 10;
+static constexpr int kPersistMasks[kNPersist] = {1, 2, 3, 7, 11, 19, 31, kMaskFpx, kMaskAflp, kMaskAll};
 
 template <bool ACC64, int... I>
 static constexpr std::array<PersistKernel, sizeof...(I)> persist_table(std::integer_sequence<int, I...>) {
     return {{&k_persistent<ACC64, kPersistMasks[I]>...}};
 }
 
-static const std::array<PersistKernel, 7> kPersist[2] = {persist_table<false>(std::make_integer_sequence<int, 7>{}),
-                                                         persist_table<true>(std::make_integer_sequence<int, 7>{})};
+static const std::array<PersistKernel, kNPersist> kPersist[2] = {
+    persist_table<false>(std::make_integer_sequence<int, kNPersist>{}),
+    persist_table<true>(std::make_integer_sequence<int, kNPersist>{})};
 
 PersistKernel persist_kernel(bool acc64, int mask, int* launched_mask) {
-    for (int i = 0; i < 7; ++i)
+    for (int i = 0; i < kNPersist; ++i)
         if ((mask & ~kPersistMasks[i]) == 0) {
             if (launched_mask) *launched_mask = kPersistMasks[i];
             return kPersist[acc64 ? 1 : 0][i];

@@ -29,7 +29,7 @@ struct DItem {            // 32 bytes
     int32_t vec_off;      // workspace index of the input for column 0
     int32_t scale_off;    // index of column 0's scale, -1 = none
     int16_t dtype;
-    int16_t acc64;        // accumulate in float64 even in float32 mode
+    int16_t ebits;        // AFLP exponent width of the item's source (0 for other formats)
     int32_t tile0;        // first tile within the owner's tile stream
 };
 
@@ -53,7 +53,8 @@ struct DTask {            // 64 bytes; carries its owner's fields so a wave
     int32_t item_start;   // absolute index of the item holding column c0
     int32_t local;        // task index within its owner
     int32_t nrows;
-    int16_t mode;
+    int16_t mode;         // bits 0-1 output mode, 2 staged inputs, 3 atomic, 4 private y;
+                          // bits 8-11 the AFLP exponent width of its items
     int16_t dtype;        // dtype of every item the task touches (-1: no columns)
     int32_t out_off, ntasks, part_off, rscale_off;
     int32_t k0, k1;       // owner tiles [k0, k1)

@@ -46,11 +46,22 @@ __global__ __launch_bounds__(256) void k_reduce(const int32_t* __restrict__ list
 }
 
 extern const TaskKernel kTasks32lo[16], kTasks32hi[16], kTasks64lo[16], kTasks64hi[16];
+extern const TaskKernel kTasksCodec32Single[11], kTasksCodec32Family[3], kTasksCodec64Single[11],
+    kTasksCodec64Family[3];
 
+// the instantiation for a stage's dtype set: the exact set for the hardware
+// formats, else the first codec set (kCodecMasks) that contains it
 TaskKernel task_kernel(bool acc64, int mask) {
-    mask &= 31;
-    if (acc64) return mask < 16 ? kTasks64lo[mask] : kTasks64hi[mask - 16];
-    return mask < 16 ? kTasks32lo[mask] : kTasks32hi[mask - 16];
+    if ((mask & ~kMaskHw) == 0) {
+        if (acc64) return mask < 16 ? kTasks64lo[mask] : kTasks64hi[mask - 16];
+        return mask < 16 ? kTasks32lo[mask] : kTasks32hi[mask - 16];
+    }
+    for (int i = 0; i < 14; ++i)
+        if ((mask & ~kCodecMasks[i]) == 0) {
+            if (i < 11) return acc64 ? kTasksCodec64Single[i] : kTasksCodec32Single[i];
+            return acc64 ? kTasksCodec64Family[i - 11] : kTasksCodec32Family[i - 11];
+        }
+    return nullptr;
 }
 
 // x in cluster order: ws[i] = x[perm[i]]  (or a straight copy); the

@@ -24,10 +24,10 @@ namespace dev {
 // w; otherwise float32 accumulator with the float32 mirror of the inputs.
 template <int DT, bool WIDE, bool SCALED, typename WT>
 __device__ __forceinline__ void tile_acc(const uint4& q, const WT* __restrict__ w, const double* __restrict__ sc,
-                                         double& a64, float& a32) {
+                                         double& a64, float& a32, int e) {
     using TT = Tile<DT>;
     typename TT::R v[TT::V];
-    TT::decode(q, v);
+    TT::decode(q, v, e);
 #pragma unroll
     for (int i = 0; i < TT::V; ++i) {
         if (WIDE) {
@@ -91,10 +91,10 @@ __device__ __forceinline__ void finalize(int mode, int out_off, int r, double v,
 
 // Accumulate one tile row with inputs already in registers/LDS (grouped path).
 template <int DT, bool WIDE>
-__device__ __forceinline__ void tile_acc_w(const uint4& q, const double* wv, double& a64, float& a32) {
+__device__ __forceinline__ void tile_acc_w(const uint4& q, const double* wv, double& a64, float& a32, int e) {
     using TT = Tile<DT>;
     typename TT::R v[TT::V];
-    TT::decode(q, v);
+    TT::decode(q, v, e);
 #pragma unroll
     for (int i = 0; i < TT::V; ++i) {
         if (WIDE)
@@ -184,7 +184,7 @@ __device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __r
                                                const double* __restrict__ vin, const float* __restrict__ vin32,
                                                const double* __restrict__ scales, const int64_t* __restrict__ dsrc,
                                                const double* part, double* __restrict__ lw, double& a64,
-                                               float& a32, int nx) {
+                                               float& a32, int nx, int e) {
     constexpr int V = Tile<DT>::V;
     constexpr int U = Tile<DT>::V <= 4 ? 8 : 4;
     const int k0 = tk.k0, k1 = tk.k1;
@@ -199,7 +199,7 @@ __device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __r
         for (int u = 0; u < U; ++u) {
             const int kk = kb + u;
             if (STAGED) {
-                if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw + (kk - k0) * V, a64, a32);
+                if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw + (kk - k0) * V, a64, a32, e);
                 continue;
             }
             if (kk < k1) {
@@ -207,14 +207,14 @@ __device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __r
                 const int c = (kk - st.k0) * V;
                 if (WIDE) {
                     if (st.sc >= 0)
-                        tile_acc<DT, true, true>(q[u], vin + st.vec + c, scales + st.sc + c, a64, a32);
+                        tile_acc<DT, true, true>(q[u], vin + st.vec + c, scales + st.sc + c, a64, a32, e);
                     else
-                        tile_acc<DT, true, false>(q[u], vin + st.vec + c, scales, a64, a32);
+                        tile_acc<DT, true, false>(q[u], vin + st.vec + c, scales, a64, a32, e);
                 } else {
                     if (st.sc >= 0)
-                        tile_acc<DT, false, true>(q[u], vin32 + st.vec + c, scales + st.sc + c, a64, a32);
+                        tile_acc<DT, false, true>(q[u], vin32 + st.vec + c, scales + st.sc + c, a64, a32, e);
                     else
-                        tile_acc<DT, false, false>(q[u], vin32 + st.vec + c, scales, a64, a32);
+                        tile_acc<DT, false, false>(q[u], vin32 + st.vec + c, scales, a64, a32, e);
                 }
             }
         }
@@ -241,7 +241,7 @@ __device__ __forceinline__ void stream_grouped(const DTask& tk, const DItem* __r
                                                bool deferred, const double* __restrict__ vin,
                                                const double* __restrict__ scales, const int64_t* __restrict__ dsrc,
                                                const double* part, double* __restrict__ lw, double& a64,
-                                               float& a32, int nx) {
+                                               float& a32, int nx, int e) {
     constexpr int V = Tile<DT>::V;
     constexpr int U = 4;
     const int k0 = tk.k0, k1 = tk.k1;
@@ -260,7 +260,7 @@ __device__ __forceinline__ void stream_grouped(const DTask& tk, const DItem* __r
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int kk = kb + u * G + g;
-            if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw + (kk - k0) * V, a64, a32);
+            if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw + (kk - k0) * V, a64, a32, e);
         }
     };
     for (int k = k0; k < k1; k += 2 * step) {
@@ -278,17 +278,18 @@ __device__ __forceinline__ void stream_task(const DTask& tk, const DItem* items,
                                             int g, int G, int lane, bool deferred, const double* vin,
                                             const float* vin32, const double* scales, const int64_t* dsrc,
                                             const double* part, double* lw, double& a64, float& a32, int nx) {
-    constexpr bool WIDE = ACC64 || DT == HM_F64;
+    constexpr bool WIDE = ACC64 || kWide<DT>;
+    const int e = task_ebits(tk.mode);
     if (G == 1) {
         if (deferred)
             stream_uniform<DT, WIDE, true, COH>(tk, items, sb, rt, lane, vin, vin32, scales, dsrc, part, lw, a64,
-                                                a32, nx);
+                                                a32, nx, e);
         else
             stream_uniform<DT, WIDE, false, COH>(tk, items, sb, rt, lane, vin, vin32, scales, dsrc, part, lw, a64,
-                                                 a32, nx);
+                                                 a32, nx, e);
     } else {
         stream_grouped<DT, WIDE, COH>(tk, items, sb, rt, g, G, lane, deferred, vin, scales, dsrc, part, lw, a64,
-                                      a32, nx);
+                                      a32, nx, e);
     }
 }
 
@@ -325,26 +326,28 @@ __device__ __forceinline__ void run_task(const DTask& tk, int lane, double* __re
         float a32 = 0.0f;
         const int64_t rt = (int64_t)nrows * 16;
         const uint8_t* sb = data + tk.stream + (uint32_t)(rr * 16);
-        if constexpr ((MASK & (1 << HM_F64)) != 0)
-            if (dt == HM_F64)
-                stream_task<HM_F64, ACC64, COH>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
-                                           a64, a32, nx);
-        if constexpr ((MASK & (1 << HM_F32)) != 0)
-            if (dt == HM_F32)
-                stream_task<HM_F32, ACC64, COH>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
-                                           a64, a32, nx);
-        if constexpr ((MASK & (1 << HM_BF16)) != 0)
-            if (dt == HM_BF16)
-                stream_task<HM_BF16, ACC64, COH>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
-                                            a64, a32, nx);
-        if constexpr ((MASK & (1 << HM_F16)) != 0)
-            if (dt == HM_F16)
-                stream_task<HM_F16, ACC64, COH>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw,
-                                           a64, a32, nx);
-        if constexpr ((MASK & (1 << HM_FP8E4M3)) != 0)
-            if (dt == HM_FP8E4M3)
-                stream_task<HM_FP8E4M3, ACC64, COH>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part,
-                                               lw, a64, a32, nx);
+#define HM_STREAM_CASE(D)                                                                                \
+    if constexpr ((MASK & (1 << D)) != 0)                                                                \
+        if (dt == D)                                                                                     \
+            stream_task<D, ACC64, COH>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw, \
+                                       a64, a32, nx);
+        HM_STREAM_CASE(HM_F64)
+        HM_STREAM_CASE(HM_F32)
+        HM_STREAM_CASE(HM_BF16)
+        HM_STREAM_CASE(HM_F16)
+        HM_STREAM_CASE(HM_FP8E4M3)
+        HM_STREAM_CASE(HM_FPX24)
+        HM_STREAM_CASE(HM_FPX40)
+        HM_STREAM_CASE(HM_FPX48)
+        HM_STREAM_CASE(HM_FPX56)
+        HM_STREAM_CASE(HM_AFLP8)
+        HM_STREAM_CASE(HM_AFLP16)
+        HM_STREAM_CASE(HM_AFLP24)
+        HM_STREAM_CASE(HM_AFLP32)
+        HM_STREAM_CASE(HM_AFLP40)
+        HM_STREAM_CASE(HM_AFLP48)
+        HM_STREAM_CASE(HM_AFLP56)
+#undef HM_STREAM_CASE
         double v = a64 + (double)a32;
         for (int off = P; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);   // across column groups
         if (act && g == 0) {
@@ -442,6 +445,14 @@ __global__ __launch_bounds__(256) void k_owner_tasks(
 using TaskKernel = void (*)(const DTask*, int, const DOwner*, const DItem*, const uint8_t*, const double*,
                             const double*, const float*, double*, float*, double*, const int64_t*, double*,
                             const int64_t*, double, double*, int64_t);
+
+// Instantiated dtype sets for stages holding codec formats (hm_tasks_codec_*):
+// one codec with FP64 (the FP64 diagonal near field beside it), then whole
+// families; task_kernel takes the first that contains a stage's set.
+constexpr int kCodecMasks[14] = {
+    (1 << HM_FPX24) | 1,  (1 << HM_FPX40) | 1,  (1 << HM_FPX48) | 1,  (1 << HM_FPX56) | 1,  (1 << HM_AFLP8) | 1,
+    (1 << HM_AFLP16) | 1, (1 << HM_AFLP24) | 1, (1 << HM_AFLP32) | 1, (1 << HM_AFLP40) | 1, (1 << HM_AFLP48) | 1,
+    (1 << HM_AFLP56) | 1, kMaskFpx,             kMaskAflp,            kMaskAll};
 
 // k_owner_tasks<acc64, mask> (instantiated in hm_tasks_*.hip)
 TaskKernel task_kernel(bool acc64, int mask);

@@ -79,6 +79,14 @@ def test_fpx_table_rows_as_printed():
     assert codecs.fpx_row(2.0 ** -53) is None
 
 
+def test_m_eps_is_the_exact_ceiling():
+    assert codecs.m_eps(1e-6) == 20 and codecs.m_eps(1e-8) == 27 and codecs.m_eps(1e-4) == 14
+    assert codecs.m_eps(2.0 ** -20) == 20
+    assert codecs.m_eps(2.0 ** -20 * (1 - 2.0 ** -53)) == 21       # just below a power of two
+    assert codecs.m_eps(2.0 ** -20 * (1 + 2.0 ** -52)) == 20
+    assert codecs.m_eps(0.75) == 1 and codecs.m_eps(1.0) == 0 and codecs.m_eps(4.0) == 0
+
+
 def _rne_bits(bits: int, drop: int) -> int:
     """Round an unsigned bit pattern to `drop` fewer bits, ties to even
     (integer arithmetic on the IEEE encoding; valid away from overflow)."""
