@@ -1479,8 +1479,9 @@ void build_mr_plan(const std::vector<DOwner>& owners, const std::vector<DItem>& 
             if (!chunks.empty()) {
                 const Chunk& c = chunks.back();
                 const int32_t cdt = c.t.c0 < c.t.c1 ? items[c.t.item_start].dtype : -1;
+                // one dtype and one AFLP exponent width (mode bits 8-11) per task
                 merge = c.stage == si && c.t.owner == t.owner && c.t.c1 == t.c0 && cdt == dt && dt >= 0 &&
-                        c.t.k1 == t.k0 && acc + bytes <= target_bytes;
+                        c.t.mode == t.mode && c.t.k1 == t.k0 && acc + bytes <= target_bytes;
             }
             if (merge) {
                 chunks.back().t.c1 = t.c1;
