@@ -67,13 +67,18 @@ POLICIES = {
     "fp8_nearfield_f64": dict(dense="f64", diag="f64", factor="fp8", coupling="fp8"),
     # uniform FP32 storage of every block (the UH config's FP32 variant)
     "f32_all": dict(dense="f32", diag="f32", factor="f32", coupling="f32"),
+    # the paper's own byte-aligned codecs (Sec. 4.1-4.2) for every class:
+    # direct compression of dense, coupling and transfer matrices at eps,
+    # VALR over the codec's widths for the cluster bases
+    "aflp": dict(dense="aflp", diag="aflp", factor="aflp", coupling="aflp"),
+    "fpx": dict(dense="fpx", diag="fpx", factor="fpx", coupling="fpx"),
     # synchronisation variants of Sec. 3.1 (FP64 storage): atomic updates of
     # shared rows, and thread-local (here: eight private) copies of y
     "f64_sync_atomic": dict(dense="f64", diag="f64", factor="f64", coupling="f64", sync="atomic"),
     "f64_sync_private": dict(dense="f64", diag="f64", factor="f64", coupling="f64", sync="private"),
 }
-DEFAULT_LEGS = {"h2": "f64,f32,bf16,fp8,valr,fp8_nearfield_f64,f64_sync_atomic,f64_sync_private",
-                "uh": "f64,f32_all,valr", "h": "f64,f32_all,valr"}
+DEFAULT_LEGS = {"h2": "f64,f32,bf16,fp8,valr,aflp,fpx,fp8_nearfield_f64,f64_sync_atomic,f64_sync_private",
+                "uh": "f64,f32_all,valr,aflp,fpx", "h": "f64,f32_all,valr,aflp,fpx"}
 
 
 def log(*a):

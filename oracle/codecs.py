@@ -146,38 +146,50 @@ def fpx_bits(q: float, code: int) -> int:
 
 
 # ---------------------------------------------------------------- AFLP
+# Every function works on whole matrices, column by column (numpy along
+# axis 0); a 1-D argument is one column.
+
+def _cols(A) -> np.ndarray:
+    A = np.asarray(A, dtype=np.float64)
+    return A[:, None] if A.ndim == 1 else A
+
+
+def aflp_scale_exps(A) -> np.ndarray:
+    """k of every column's scale c = 2^k: floor(log2 vmin) over the nonzero
+    magnitudes (0 for an all-zero column)."""
+    a = np.abs(_cols(A))
+    vmin = np.where(a > 0, a, np.inf).min(axis=0, initial=np.inf)
+    k = np.zeros(a.shape[1], dtype=np.int64)
+    ok = np.isfinite(vmin)
+    _, E = np.frexp(vmin[ok])                    # vmin = g 2^E, g in [0.5, 1)
+    k[ok] = E - 1
+    return k
+
 
 def aflp_scale_exp(col) -> int:
-    """k of the column's scale c = 2^k: floor(log2 vmin) over the nonzero
-    magnitudes (0 for an all-zero column)."""
-    a = np.abs(np.asarray(col, dtype=np.float64))
-    a = a[a > 0]
-    if a.size == 0:
-        return 0
-    _, E = np.frexp(a.min())
-    return int(E) - 1
+    return int(aflp_scale_exps(col)[0])
+
+
+def aflp_column_ebits_all(A) -> np.ndarray:
+    """Fewest exponent bits of every column: bit length of its largest code
+    z = floor(log2(vmax / c)) + 1 (at least 1)."""
+    a = np.abs(_cols(A))
+    vmax = a.max(axis=0, initial=0.0)
+    _, zmax = np.frexp(np.ldexp(vmax, -aflp_scale_exps(A)))   # vmax/c = f 2^z, f in [0.5, 1)
+    _, bits = np.frexp(zmax.astype(np.float64))                # bit length of z (0 for z = 0)
+    return np.maximum(bits, 1)
 
 
 def aflp_column_ebits(col) -> int:
-    """Fewest exponent bits for one column: bit length of its largest code
-    z = floor(log2(vmax / c)) + 1 (at least 1)."""
-    a = np.abs(np.asarray(col, dtype=np.float64))
-    if not np.any(a > 0):
-        return 1
-    k = aflp_scale_exp(col)
-    _, E = math.frexp(math.ldexp(float(a.max()), -k))   # vmax/c = f 2^E, f in [0.5, 1)
-    zmax = E                                             # floor(log2(vmax/c)) + 1
-    return max(1, zmax.bit_length())
+    return int(aflp_column_ebits_all(col)[0])
 
 
 def aflp_ebits(A) -> int:
     """e of a stored matrix: the largest column requirement."""
-    A = np.asarray(A, dtype=np.float64)
-    if A.ndim == 1:
-        A = A[:, None]
+    A = _cols(A)
     if A.shape[1] == 0:
         return 1
-    return max(aflp_column_ebits(A[:, j]) for j in range(A.shape[1]))
+    return int(aflp_column_ebits_all(A).max())
 
 
 def aflp_feasible(B: int, e: int) -> bool:
@@ -188,16 +200,17 @@ def aflp_feasible(B: int, e: int) -> bool:
     return e <= (7 if B <= 3 else 10)
 
 
-def aflp_encode_column(col, e: int, B: int):
-    """Codes (sign, z, M) of one column and its scale exponent k."""
-    col = np.asarray(col, dtype=np.float64)
+def aflp_encode(A, e: int, B: int):
+    """Codes (sign, z, M) of every entry and the scale exponent k of every
+    column."""
+    A = _cols(A)
     mp = 8 * B - 1 - e
-    k = aflp_scale_exp(col)
-    a = np.ldexp(np.abs(col), -k)                # exact: a power-of-two scale
+    k = aflp_scale_exps(A)
+    a = np.ldexp(np.abs(A), -k[None, :])         # exact: power-of-two scales
     nz = a > 0
-    sign = (np.signbit(col) & nz).astype(np.int64)
-    z = np.zeros(col.shape, dtype=np.int64)
-    M = np.zeros(col.shape, dtype=np.int64)
+    sign = (np.signbit(A) & nz).astype(np.int64)
+    z = np.zeros(A.shape, dtype=np.int64)
+    M = np.zeros(A.shape, dtype=np.int64)
     f, E = np.frexp(a[nz])                       # a = f 2^E, f in [0.5, 1)
     E = E.astype(np.int64) - 1                   # a = 2^E (1 + frac)
     frac = 2.0 * f - 1.0                         # exact
@@ -214,13 +227,25 @@ def aflp_encode_column(col, e: int, B: int):
     return sign, z, M, k
 
 
-def aflp_decode(sign, z, M, k: int, e: int, B: int) -> np.ndarray:
-    """sign * 2^k * 2^(z-1) * (1 + M / 2^m'); z = 0 is zero."""
+def aflp_decode_all(sign, z, M, k, e: int, B: int) -> np.ndarray:
+    """sign * 2^k * 2^(z-1) * (1 + M / 2^m') entry by entry (k per column);
+    z = 0 is zero."""
     mp = 8 * B - 1 - e
     z = np.asarray(z, dtype=np.int64)
-    mag = np.ldexp(1.0 + np.ldexp(np.asarray(M, dtype=np.float64), -mp), z - 1 + k)
+    kk = np.asarray(k, dtype=np.int64)
+    mag = np.ldexp(1.0 + np.ldexp(np.asarray(M, dtype=np.float64), -mp), z - 1 + (kk[None, :] if z.ndim == 2 else kk))
     mag[z == 0] = 0.0
     return np.where(np.asarray(sign) != 0, -mag, mag)
+
+
+def aflp_encode_column(col, e: int, B: int):
+    """Codes (sign, z, M) of one column and its scale exponent k."""
+    s, z, M, k = aflp_encode(col, e, B)
+    return s[:, 0], z[:, 0], M[:, 0], int(k[0])
+
+
+def aflp_decode(sign, z, M, k: int, e: int, B: int) -> np.ndarray:
+    return aflp_decode_all(sign, z, M, k, e, B)
 
 
 def aflp_code_word(s: int, z: int, M: int, e: int, B: int) -> int:
@@ -229,18 +254,14 @@ def aflp_code_word(s: int, z: int, M: int, e: int, B: int) -> int:
     return (s << (8 * B - 1)) | (z << mp) | M
 
 
-def aflp_stored_column(col, e: int, B: int) -> np.ndarray:
-    s, z, M, k = aflp_encode_column(col, e, B)
-    return aflp_decode(s, z, M, k, e, B)
-
-
 def aflp_stored(A, e: int, B: int) -> np.ndarray:
     """Every column of A stored in AFLP width B with exponent width e."""
-    A = np.asarray(A, dtype=np.float64)
-    out = np.zeros_like(A, order="F")
-    for j in range(A.shape[1]):
-        out[:, j] = aflp_stored_column(A[:, j], e, B)
-    return out
+    s_, z, M, k = aflp_encode(A, e, B)
+    return np.asfortranarray(aflp_decode_all(s_, z, M, k, e, B))
+
+
+def aflp_stored_column(col, e: int, B: int) -> np.ndarray:
+    return aflp_stored(col, e, B)[:, 0]
 
 
 def aflp_direct_width(e: int, eps: float):
@@ -256,40 +277,41 @@ def aflp_direct_width(e: int, eps: float):
 
 def column_error2(w, s) -> float:
     """Squared 2-norm of w - s, squares summed in row order."""
-    d = np.asarray(w, dtype=np.float64) - np.asarray(s, dtype=np.float64)
-    return float(np.cumsum(d * d)[-1]) if len(d) else 0.0
+    return float(column_errors2(w, s)[0])
+
+
+def column_errors2(A, S) -> np.ndarray:
+    """Squared 2-norms of the columns of A - S, squares summed in row order."""
+    d = _cols(A) - _cols(S)
+    if d.shape[0] == 0:
+        return np.zeros(d.shape[1])
+    return np.cumsum(d * d, axis=0)[-1]
 
 
 def valr_aflp_widths(A, deltas, e: int):
     """VALR (Sec. 4.2) with AFLP: column j takes the narrowest feasible
     width whose stored column differs from it by at most deltas[j] in the
     2-norm (None: FP64)."""
-    A = np.asarray(A, dtype=np.float64)
-    out = []
-    for j in range(A.shape[1]):
-        w = A[:, j]
-        pick = None
-        for B in range(1, 8):
-            if not aflp_feasible(B, e):
-                continue
-            if column_error2(w, aflp_stored_column(w, e, B)) <= deltas[j] * deltas[j]:
-                pick = B
-                break
-        out.append(pick)
+    A = _cols(A)
+    d2 = np.asarray(deltas, dtype=np.float64) ** 2
+    out = [None] * A.shape[1]
+    for B in range(7, 0, -1):                    # narrower widths overwrite wider ones
+        if not aflp_feasible(B, e):
+            continue
+        ok = column_errors2(A, aflp_stored(A, e, B)) <= d2
+        for j in np.flatnonzero(ok):
+            out[j] = B
     return out
 
 
 def valr_fpx_codes(A, deltas):
     """VALR with FPX: column j takes the first row of the table whose stored
     column meets its budget (the last row is FP64)."""
-    A = np.asarray(A, dtype=np.float64)
-    out = []
-    for j in range(A.shape[1]):
-        w = A[:, j]
-        pick = quant.F64
-        for code in FPX_LADDER[:-1]:
-            if column_error2(w, fpx_stored(w[:, None], code)[:, 0]) <= deltas[j] * deltas[j]:
-                pick = code
-                break
-        out.append(pick)
+    A = _cols(A)
+    d2 = np.asarray(deltas, dtype=np.float64) ** 2
+    out = [quant.F64] * A.shape[1]
+    for code in reversed(FPX_LADDER[:-1]):       # earlier rows overwrite later ones
+        ok = column_errors2(A, fpx_stored(A, code)) <= d2
+        for j in np.flatnonzero(ok):
+            out[j] = code
     return out

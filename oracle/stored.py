@@ -165,18 +165,22 @@ class _Store:
                 self._count(fj, A.shape[0])
                 out[:, j] = quant.stored(A[:, j:j + 1], fj)[:, 0]
         elif f == codecs.FPX_AUTO:
-            for j, fj in enumerate(codecs.valr_fpx_codes(A, deltas)):
-                self._count(fj, A.shape[0])
-                out[:, j] = codecs.fpx_stored(A[:, j], fj)
+            codes = codecs.valr_fpx_codes(A, deltas)
+            for fj in sorted(set(codes)):
+                cols = [j for j, c in enumerate(codes) if c == fj]
+                self._count(fj, A.shape[0] * len(cols))
+                out[:, cols] = codecs.fpx_stored(A[:, cols], fj)
         else:
-            e = codecs.aflp_ebits(A)
-            for j, B in enumerate(codecs.valr_aflp_widths(A, deltas, e)):
+            e = codecs.aflp_ebits(A)                  # one exponent width per factor
+            widths = codecs.valr_aflp_widths(A, deltas, e)
+            for B in sorted(set(widths), key=lambda b: 8 if b is None else b):
+                cols = [j for j, b in enumerate(widths) if b == B]
                 if B is None:
-                    self._count(quant.F64, A.shape[0])
-                    out[:, j] = A[:, j]
+                    self._count(quant.F64, A.shape[0] * len(cols))
+                    out[:, cols] = A[:, cols]
                 else:
-                    self._count(codecs.AFLP[B], A.shape[0])
-                    out[:, j] = codecs.aflp_stored_column(A[:, j], e, B)
+                    self._count(codecs.AFLP[B], A.shape[0] * len(cols))
+                    out[:, cols] = codecs.aflp_stored(A[:, cols], e, B)
         return out
 
 

@@ -21,7 +21,7 @@ import time
 import numpy as np
 import pytest
 
-from conftest import cached
+from conftest import cached, say
 from oracle import omp, stored, trees
 from synth import (KERNEL_EXPR, KERNEL_LAPLACE, cache, compress_h, gaussian_matrix, gaussian_vector,
                    sphere_points, to_h2, to_uh)
@@ -42,9 +42,13 @@ def workload(fmt, n, seed, eps=1e-6, kernel=KERNEL_LAPLACE):
         assert np.array_equal(e["blk_sigma"], st.blk_sigma) and np.array_equal(e["blk_adm"], st.blk_adm)
 
         def gen():
+            say(f"  building {fmt} n={n}: H compression")
             h = compress_h(p, kernel, st, eps, method="auto")
+            if fmt != "h":
+                say(f"  building {fmt} n={n}: nested bases")
             return h if fmt == "h" else to_uh(h, st) if fmt == "uh" else to_h2(h, st)
         vals = cache.cached(("test-full", fmt, n, seed, eps, kernel), gen)
+        say(f"  {fmt} n={n} ready")
         return st, lay, vals
     return cached(("full", fmt, n, seed, eps, kernel), build)
 
@@ -54,10 +58,12 @@ def graph_parity(fmt, n, seed, pol, tol, copies=2):
     import paper_2405_03456_amd as hm
     st, lay, vals = workload(fmt, n, seed)
     x = gaussian_vector(n, 2000 + seed % 1000)
+    say("  oracle: stored values and product")
     sv = stored.stored_values(st, fmt, vals, dense=pol["dense"], diag=pol.get("diag"), factor=pol["factor"],
                               coupling=pol.get("coupling"), eps=pol["eps"])
     ref = omp.product(st, fmt, sv, 1.0, x, np.zeros(n))
     del sv
+    say("  upload and tune")
     Ms = [hm.Matrix(lay, fmt, vals, **pol) for _ in range(copies)]     # rotated copies, as in bench.py
     for M in Ms:
         M.tune_mvm(reps=3)
@@ -70,7 +76,7 @@ def graph_parity(fmt, n, seed, pol, tol, copies=2):
     torch.cuda.synchronize()
     for y in ys:
         err = float(np.linalg.norm(y.cpu().numpy() / 3.0 - ref) / np.linalg.norm(ref))
-        print(f"  rel err {err:.3e} (tol {tol:g})", flush=True)
+        say(f"  rel err {err:.3e} (tol {tol:g})")
         assert err <= tol
     for g in gs:
         g.free()
@@ -88,7 +94,7 @@ CASES = [("uh", 32768, 1002, "f64", dict(dense="f64", factor="f64", eps=1e-6), 1
 
 @pytest.mark.parametrize("fmt,n,seed,pname,pol,tol", CASES, ids=[f"{c[0]}{c[1]}-{c[3]}" for c in CASES])
 def test_fullsize_graph_parity(fmt, n, seed, pname, pol, tol):
-    print(f"case fullsize {fmt} n={n} policy={pname}", flush=True)
+    say(f"case fullsize {fmt} n={n} policy={pname}")
     graph_parity(fmt, n, seed, pol, tol)
 
 
@@ -97,12 +103,14 @@ H2_CASES = [("f64", dict(dense="f64", diag="f64", factor="f64", coupling="f64", 
             ("f32", dict(dense="f32", diag="f64", factor="f32", coupling="f32", eps=1e-6), 1e-6),
             ("bf16", dict(dense="f32", diag="f64", factor="bf16", coupling="bf16", eps=1e-6), 1e-6),
             ("fp8", dict(dense="f32", diag="f64", factor="fp8", coupling="fp8", eps=1e-6), 1e-6),
-            ("valr", dict(dense="valr", diag="valr", factor="valr", coupling="valr", eps=1e-6), 1e-6)]
+            ("valr", dict(dense="valr", diag="valr", factor="valr", coupling="valr", eps=1e-6), 1e-6),
+            ("aflp", dict(dense="aflp", diag="aflp", factor="aflp", coupling="aflp", eps=1e-6), 1e-6),
+            ("fpx", dict(dense="fpx", diag="fpx", factor="fpx", coupling="fpx", eps=1e-6), 1e-6)]
 
 
 @pytest.mark.parametrize("pname,pol,tol", H2_CASES, ids=[c[0] for c in H2_CASES])
 def test_fullsize_h2_262144(pname, pol, tol):
-    print(f"case fullsize h2 n=262144 policy={pname}", flush=True)
+    say(f"case fullsize h2 n=262144 policy={pname}")
     graph_parity("h2", 262144, 1003, pol, tol, copies=1)
 
 
@@ -120,7 +128,7 @@ def test_fullsize_many_rhs_h131072(pname):
     M = hm.Matrix(lay, "h", vals, **pol)
     X = gaussian_matrix(n, 128, 2004)
     for r in (8, 32, 128):
-        print(f"case fullsize many-rhs h131072 {pname} r={r}", flush=True)
+        say(f"case fullsize many-rhs h131072 {pname} r={r}")
         M.tune(r, reps=2)
         Xd = torch.from_numpy(np.ascontiguousarray(X[:, :r].T)).cuda().T
         Yd = torch.zeros((r, n), dtype=torch.float64, device="cuda").T
@@ -132,7 +140,7 @@ def test_fullsize_many_rhs_h131072(pname):
         for j in range(r):
             ref = P.product(1.0, X[:, j], np.zeros(n))[0]
             worst = max(worst, float(np.linalg.norm(Y[:, j] - ref) / np.linalg.norm(ref)))
-        print(f"  worst column rel err {worst:.3e}", flush=True)
+        say(f"  worst column rel err {worst:.3e}")
         assert worst <= 1e-6
         g.free()
     M.free()
@@ -168,14 +176,14 @@ def test_fullsize_serving_mix():
         Ps.append(omp.Prepared(st, fmt, sv))
         Ms.append(hm.Matrix(lay, fmt, vals, **pol))
         ns.append(n)
-        print(f"  matrix {fmt} n={n} eps={eps:g} ready ({time.perf_counter() - t0:.0f}s)", flush=True)
+        say(f"  matrix {fmt} n={n} eps={eps:g} ready ({time.perf_counter() - t0:.0f}s)")
     S = hm.Server(mem_budget=2 << 30, max_slots=32, max_queue=1000, max_cols=32)
     ids = [S.register(M) for M in Ms]
     rng = np.random.default_rng(4400)
     reqs = [(int(rng.integers(0, 16)), int(rng.integers(1, 33)), float(rng.exponential(0.0003)),
              float(rng.choice([1.0, -0.5]))) for _ in range(48)]
     Xs = [gaussian_matrix(ns[m], r, 7100 + i) for i, (m, r, _, _) in enumerate(reqs)]
-    print(f"case serving mix: 16 matrices, {len(reqs)} requests", flush=True)
+    say(f"case serving mix: 16 matrices, {len(reqs)} requests")
     alone = []
     for (m, r, _, a), X in zip(reqs, Xs):
         t, Y = S.submit(ids[m], X, alpha=a)
@@ -200,7 +208,7 @@ def test_fullsize_serving_mix():
             err = float(np.linalg.norm(Ya[:, j] - ref) / np.linalg.norm(ref))
             worst = max(worst, err / tol)
             assert err <= tol, (m, j, err)
-    print(f"  worst error / tolerance {worst:.3e}; server {st}", flush=True)
+    say(f"  worst error / tolerance {worst:.3e}; server {st}")
     S.close()
     for M in Ms:
         M.free()
