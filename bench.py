@@ -202,7 +202,9 @@ def summarize(res, steps):
 def kernel_sources_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("hm_runtime.hip", "hm_device.h", "hm_plan.h", "hm_pack.cpp", "hm_pack.h"):
+    for f in ("hm_runtime.hip", "hm_device.h", "hm_stream.h", "hm_plan.h", "hm_pack.cpp", "hm_pack.h",
+              "hm_quant.cpp", "hm_tasks_a32_lo.hip", "hm_tasks_a32_hi.hip", "hm_tasks_a64_lo.hip",
+              "hm_tasks_a64_hi.hip"):
         with open(os.path.join(ROOT, "paper_2405_03456_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
