@@ -89,23 +89,28 @@ __device__ __forceinline__ void finalize(int mode, int out_off, int r, double v,
     }
 }
 
-// Accumulate one tile row with inputs already in registers/LDS (grouped path).
+// Accumulate one tile row with its inputs staged in LDS: entries [off,
+// off + V) of the wave's slice, float64 (WIDE) or float32 values.
 template <int DT, bool WIDE>
-__device__ __forceinline__ void tile_acc_w(const uint4& q, const double* wv, double& a64, float& a32, int e) {
+__device__ __forceinline__ void tile_acc_w(const uint4& q, const double* lw, int off, double& a64, float& a32,
+                                           int e) {
     using TT = Tile<DT>;
     typename TT::R v[TT::V];
     TT::decode(q, v, e);
+    const float* lw32 = reinterpret_cast<const float*>(lw);
 #pragma unroll
     for (int i = 0; i < TT::V; ++i) {
         if (WIDE)
-            a64 = fma((double)v[i], wv[i], a64);
+            a64 = fma((double)v[i], lw[off + i], a64);
         else
-            a32 = fmaf((float)v[i], (float)wv[i], a32);
+            a32 = fmaf((float)v[i], lw32[off + i], a32);
     }
 }
 
 // Stage a task's inputs (times their column scales) in this wave's LDS slice
-// in tile order: lw[(t - k0) * V + i] = input of column i of tile t.  With
+// in tile order: entry (t - k0) * V + i = input of column i of tile t, a
+// float64 value for WIDE tasks, else a float32 value (the slice read as
+// float).  With
 // `deferred`, an input that is an unreduced sum (dsrc entry != 0) is formed
 // here from its partial sums, added in task order.  Past an item's last
 // column the values are not needed (its data is zero) but are finite.
@@ -166,7 +171,12 @@ __device__ __forceinline__ void stage_inputs(const DTask& tk, const DItem* __res
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int idx = base + u * 64;
-            if (idx < nval) lw[idx] = WIDE ? v[u] * f[u] : (double)((float)v[u] * (float)f[u]);
+            if (idx < nval) {
+                if (WIDE)
+                    lw[idx] = v[u] * f[u];
+                else
+                    reinterpret_cast<float*>(lw)[idx] = (float)v[u] * (float)f[u];
+            }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -175,16 +185,18 @@ __device__ __forceinline__ void stage_inputs(const DTask& tk, const DItem* __res
 }
 
 // Wide owners (more than 32 rows): the wave walks the task's tiles together,
-// a prefetched batch of U tiles always in flight; item bookkeeping is
-// uniform and the inputs are scalar loads (lgkmcnt), so waiting for them
-// never drains the data prefetch (vmcnt).
+// a prefetched batch of U tiles always in flight.  Unstaged, the item
+// bookkeeping is uniform and the inputs are scalar loads (lgkmcnt), so
+// waiting for them never drains the data prefetch (vmcnt); STAGED, the
+// inputs (times their scales) are first staged in LDS, after the first
+// tiles have been requested.
 template <int DT, bool WIDE, bool STAGED, bool COH>
 __device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __restrict__ items,
                                                const uint8_t* __restrict__ sb, int64_t rt, int lane,
                                                const double* __restrict__ vin, const float* __restrict__ vin32,
                                                const double* __restrict__ scales, const int64_t* __restrict__ dsrc,
                                                const double* part, double* __restrict__ lw, double& a64,
-                                               float& a32, int nx, int e) {
+                                               float& a32, int nx, int e, bool deferred) {
     constexpr int V = Tile<DT>::V;
     constexpr int U = Tile<DT>::V <= 4 ? 8 : 4;
     const int k0 = tk.k0, k1 = tk.k1;
@@ -199,7 +211,7 @@ __device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __r
         for (int u = 0; u < U; ++u) {
             const int kk = kb + u;
             if (STAGED) {
-                if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw + (kk - k0) * V, a64, a32, e);
+                if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw, (kk - k0) * V, a64, a32, e);
                 continue;
             }
             if (kk < k1) {
@@ -220,7 +232,7 @@ __device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __r
         }
     };
     issue(qa, k0);
-    if (STAGED) stage_inputs<DT, WIDE, COH>(tk, items, lane, true, vin, scales, dsrc, part, lw, nx);
+    if (STAGED) stage_inputs<DT, WIDE, COH>(tk, items, lane, deferred, vin, scales, dsrc, part, lw, nx);
     for (int k = k0; k < k1; k += 2 * U) {
         issue(qb, k + U);
         __builtin_amdgcn_sched_barrier(0);
@@ -260,7 +272,7 @@ __device__ __forceinline__ void stream_grouped(const DTask& tk, const DItem* __r
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int kk = kb + u * G + g;
-            if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw + (kk - k0) * V, a64, a32, e);
+            if (kk < k1) tile_acc_w<DT, WIDE>(q[u], lw, (kk - k0) * V, a64, a32, e);
         }
     };
     for (int k = k0; k < k1; k += 2 * step) {
@@ -279,14 +291,18 @@ __device__ __forceinline__ void stream_task(const DTask& tk, const DItem* items,
                                             const float* vin32, const double* scales, const int64_t* dsrc,
                                             const double* part, double* lw, double& a64, float& a32, int nx) {
     constexpr bool WIDE = ACC64 || kWide<DT>;
+    // formats whose columns carry a scale (FP16, FP8, AFLP) stage their
+    // weights (input times scale, once per column and wave) instead of
+    // loading every column's scale in every lane's loop: measured faster
+    constexpr bool kScaled = DT == HM_F16 || DT == HM_FP8E4M3 || DT >= HM_AFLP8;
     const int e = task_ebits(tk.mode);
     if (G == 1) {
-        if (deferred)
+        if (deferred || kScaled)
             stream_uniform<DT, WIDE, true, COH>(tk, items, sb, rt, lane, vin, vin32, scales, dsrc, part, lw, a64,
-                                                a32, nx, e);
+                                                a32, nx, e, deferred);
         else
             stream_uniform<DT, WIDE, false, COH>(tk, items, sb, rt, lane, vin, vin32, scales, dsrc, part, lw, a64,
-                                                 a32, nx, e);
+                                                 a32, nx, e, false);
     } else {
         stream_grouped<DT, WIDE, COH>(tk, items, sb, rt, g, G, lane, deferred, vin, scales, dsrc, part, lw, a64,
                                       a32, nx, e);
