@@ -583,6 +583,9 @@ def main():
         "roofline": roof,
         "legs": main_w["legs"],
         "phases_f64": main_w["phases"]["f64"],
+        # every leg's launches: [phase, tasks, average us]
+        "phases_by_leg": {leg: [[p["name"], p["ntasks"], p["us_avg"]] for p in ph]
+                          for leg, ph in main_w["phases"].items()},
     }
     if "cpu" in main_w:
         c = main_w["cpu"]

@@ -315,6 +315,7 @@ typedef struct {
     int32_t max_rank;
     int32_t accum;                  /* resolved accumulation (HM_ACC_F32 / HM_ACC_F64) */
     int32_t nlaunch;                /* kernel launches per hm_mvm (persistent schedule: 2) */
+    int64_t nowners, nitems, ntasks; /* single-vector plan: output owners, stored slices, wavefront tasks */
     double algorithmic_bytes;       /* bytes one hm_mvm moves: stored data (16-byte tiles, padding
                                        included) + scales + vectors + coefficients + plan metadata */
     double method_bytes;            /* bytes the product itself needs: every stored entry once at its

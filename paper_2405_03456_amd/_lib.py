@@ -84,6 +84,7 @@ class Stats(ctypes.Structure):
                 ("bytes_workspace", c_int64), ("bytes_per_dtype", c_int64 * HM_NDTYPES),
                 ("entries_per_dtype", c_int64 * HM_NDTYPES), ("sum_rank", c_int64),
                 ("max_rank", c_int32), ("accum", c_int32), ("nlaunch", c_int32),
+                ("nowners", c_int64), ("nitems", c_int64), ("ntasks", c_int64),
                 ("algorithmic_bytes", c_double), ("method_bytes", c_double)]
 
 

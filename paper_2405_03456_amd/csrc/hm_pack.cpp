@@ -1435,6 +1435,9 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
     }
     s.accum = out.acc64 ? HM_ACC_F64 : HM_ACC_F32;
     for (const Source& S : B.src) s.entries_per_dtype[S.dtype] += S.m * S.k;
+    s.nowners = (int64_t)out.owners.size();
+    s.nitems = (int64_t)out.items.size();
+    s.ntasks = (int64_t)out.tasks.size();
     s.nlaunch = 1;   // gather
     for (auto& st : out.stages) s.nlaunch += (st.t1 > st.t0) + !st.reduce_launch.empty();
     s.algorithmic_bytes = (double)(s.bytes_dense + s.bytes_factors + s.bytes_coupling + s.bytes_transfer +
