@@ -284,6 +284,12 @@ typedef struct {
                                product over block columns) for HM_ADJOINT products: every block
                                transposed, stored under the same precision policy; doubles the
                                device memory of the matrix */
+    int32_t h2_levels;      /* H2 downward pass: 0 = the coupling products of every level in one
+                               launch right after the upward pass (each row cluster's couplings as
+                               partial sums of its coefficients), then one small launch per level
+                               for the transfers (default); 1 = couplings and transfers together,
+                               one launch per level.  The same products; the transfer product is
+                               its own partial sum in the first, so results agree to rounding. */
 } hm_upload_opts;
 
 #define HM_SCHED_STAGED 0

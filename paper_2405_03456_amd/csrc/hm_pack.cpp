@@ -340,6 +340,7 @@ struct Builder {
     std::vector<int64_t> stage_bytes;
     std::vector<std::string> stage_names;
     std::vector<std::pair<DTask, int64_t>> floating;   // (task, bytes)
+    int32_t early_stage = -1;                           // stage of the tasks of early items
     int64_t part_elems = 0;
     int32_t cur_stage = -1;
     DOwner cur{};
@@ -369,8 +370,10 @@ struct Builder {
     // item = rows [r0, r0+nr) of source s (all its columns), or the transpose
     // unscaled: the source's column scales were folded into the producer of
     // the item's input vector (see fold_scales), so the item multiplies none.
+    // early: the item's tasks run in early_stage (see build_h2), not in the
+    // stage the owner was begun in
     void add_item(int32_t s, int64_t r0, bool transposed, int32_t vec_off, bool unscaled = false,
-                  bool floats = false) {
+                  bool floats = false, bool early = false) {
         Source& S = src[s];
         const int64_t nr = cur.nrows;
         const int64_t ncols = transposed ? S.m : S.k;
@@ -387,7 +390,7 @@ struct Builder {
         it.dtype = (int16_t)S.dtype;
         it.ebits = (int16_t)S.ebits;
         items.push_back(it);
-        item_floating.push_back(floats ? 1 : 0);
+        item_floating.push_back(floats ? 1 : early ? 2 : 0);
         item_use.emplace_back(s, (int32_t)S.uses.size());
         cur.nitems++;
         cur_cols += (int32_t)ncols;
@@ -524,12 +527,13 @@ struct Builder {
             t.ntasks = cur.ntasks;
             t.part_off = cur.part_off;
             t.rscale_off = cur.rscale_off;
-            const bool fl = t.c0 < t.c1 && item_floating[t.item_start];
-            if (fl) {
+            const uint8_t cls = t.c0 < t.c1 ? item_floating[t.item_start] : 0;
+            if (cls == 1) {
                 floating.push_back(tb);
             } else {
-                stage_tasks[cur_stage].push_back(t);
-                stage_bytes[cur_stage] += tb.second;
+                const int32_t si = cls == 2 ? early_stage : cur_stage;
+                stage_tasks[si].push_back(t);
+                stage_bytes[si] += tb.second;
             }
         }
         owners.push_back(cur);
@@ -924,6 +928,15 @@ struct Builder {
         for (int32_t rho : leaves)
             if (V->row_rank[rho] > 0)
                 lrun[rho] = basis_factor(V->row_basis[rho], L.size(rho), V->row_rank[rho], V->row_sv, rho);
+        // The coupling products S_b s_s of every level depend only on the
+        // upward pass, so (by default) they all run in one launch right after
+        // it, as partial sums of their row cluster's coefficient owner; the
+        // downward recursion t_t = E_t t_parent + (those partial sums) then
+        // only adds the small transfer products level by level (Alg. 7's
+        // recursion; each owner's partial sums are added in a fixed task
+        // order, so the result is deterministic).
+        const bool early = opt.coupling_first;
+        if (early) early_stage = new_stage("h2_coup");
         for (int32_t lv = 0; lv <= L.depth; ++lv) {
             bool any = false;
             for (int32_t v : by_level[lv]) any |= V->row_rank[v] > 0;
@@ -952,7 +965,7 @@ struct Builder {
                     if (kc == 0) continue;
                     if (!V->coupling[b]) return check(false, "missing coupling");
                     int32_t cs = add_source(permute_cols(V->coupling[b], kr, kc, cperm[s]), kr, kc, coup_dt, nullptr, 2);
-                    add_item(cs, 0, false, s_off[s]);
+                    add_item(cs, 0, false, s_off[s], false, false, early);
                 }
                 end_owner();
             }
@@ -1123,6 +1136,13 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
         if (P.dsrc[e] != 0 && deferred_owner[e] < 0) { why = "deferred-sum entry without owner"; return false; }
     std::vector<int32_t> seen(no, 0), stage_of(no, -1), reduced(no, -1);
     const int32_t ns = (int32_t)P.stages.size();
+    // last stage holding a task of each owner: a coefficient owner may have
+    // tasks in several stages (the H2 couplings run before the transfers);
+    // its entries are complete only after the last
+    std::vector<int32_t> last_of(no, -1);
+    for (int32_t si = 0; si < ns; ++si)
+        for (int64_t k = P.stages[si].t0; k < P.stages[si].t1 && k < (int64_t)P.tasks.size(); ++k)
+            if (P.tasks[k].owner >= 0 && P.tasks[k].owner < no) last_of[P.tasks[k].owner] = si;
     for (int32_t si = 0; si < ns; ++si) {
         const Stage& st = P.stages[si];
         if (st.t0 < 0 || st.t0 > st.t1 || st.t1 > (int64_t)P.tasks.size()) { why = "stage range"; return false; }
@@ -1182,7 +1202,7 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
                         const int32_t src = deferred_owner[dj.vec_off + c];
                         if (src < 0) continue;
                         if (!P.staged[k]) { why = "unreduced input read without staging"; return false; }
-                        if (st.aux || stage_of[src] < 0 || stage_of[src] >= si) {
+                        if (st.aux || last_of[src] < 0 || last_of[src] >= si) {
                             why = "unreduced input not produced by an earlier stage";
                             return false;
                         }
@@ -1191,7 +1211,7 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
             }
             ++seen[t.owner];
             if (ow.mode == 0) {
-                if (stage_of[t.owner] >= 0 && stage_of[t.owner] != si) { why = "coefficient owner spans stages"; return false; }
+                if (st.aux && last_of[t.owner] != si) { why = "coefficient owner spans the second stream"; return false; }
                 stage_of[t.owner] = si;
             }
         }
@@ -1588,6 +1608,11 @@ hm_status pack_options(const hm_upload_opts* o, PackOptions& opt) {
     if (o->task_bytes) opt.task_bytes = o->task_bytes;
     opt.concurrent_dense = o->spread_dense == 0;
     opt.valr_promote = o->valr_promote != 0;
+    if (o->h2_levels & ~1) {
+        set_error("hm_upload: h2_levels must be 0 or 1");
+        return HM_EINVAL;
+    }
+    opt.coupling_first = o->h2_levels == 0;
     return HM_OK;
 }
 

@@ -16,6 +16,7 @@ struct PackOptions {
     int32_t tickets_per_grab = 4;
     bool adjoint = false;         // also upload M^T for HM_ADJOINT products
     int32_t sync = HM_SYNC_OWNER; // how tasks sharing output rows combine them
+    bool coupling_first = true;   // H2: every level's couplings in one launch after the up pass
 };
 
 // Validated PackOptions from the ABI's hm_upload_opts (NULL = defaults).
