@@ -76,8 +76,12 @@ POLICIES = {
     # shared rows, and thread-local (here: eight private) copies of y
     "f64_sync_atomic": dict(dense="f64", diag="f64", factor="f64", coupling="f64", sync="atomic"),
     "f64_sync_private": dict(dense="f64", diag="f64", factor="f64", coupling="f64", sync="private"),
+    # H2 downward pass with each level's couplings in that level's launch
+    # (the default runs every level's couplings in one launch first)
+    "f64_per_level": dict(dense="f64", diag="f64", factor="f64", coupling="f64", h2_levels="per_level"),
 }
-DEFAULT_LEGS = {"h2": "f64,f32,bf16,fp8,valr,aflp,fpx,fp8_nearfield_f64,f64_sync_atomic,f64_sync_private",
+DEFAULT_LEGS = {"h2": "f64,f32,bf16,fp8,valr,aflp,fpx,fp8_nearfield_f64,f64_sync_atomic,f64_sync_private,"
+                      "f64_per_level",
                 "uh": "f64,f32_all,valr,aflp,fpx", "h": "f64,f32_all,valr,aflp,fpx"}
 
 
