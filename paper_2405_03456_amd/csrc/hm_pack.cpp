@@ -340,7 +340,7 @@ struct Builder {
     std::vector<int64_t> stage_bytes;
     std::vector<std::string> stage_names;
     std::vector<std::pair<DTask, int64_t>> floating;   // (task, bytes)
-    int32_t early_stage = -1;                           // stage of the tasks of early items
+    std::vector<int32_t> item_stage;                    // per item: its tasks' stage (-1: the owner's)
     int64_t part_elems = 0;
     int32_t cur_stage = -1;
     DOwner cur{};
@@ -370,10 +370,10 @@ struct Builder {
     // item = rows [r0, r0+nr) of source s (all its columns), or the transpose
     // unscaled: the source's column scales were folded into the producer of
     // the item's input vector (see fold_scales), so the item multiplies none.
-    // early: the item's tasks run in early_stage (see build_h2), not in the
-    // stage the owner was begun in
+    // stage >= 0: the item's tasks run in that (earlier) stage, not in the
+    // stage the owner was begun in (see build_h2)
     void add_item(int32_t s, int64_t r0, bool transposed, int32_t vec_off, bool unscaled = false,
-                  bool floats = false, bool early = false) {
+                  bool floats = false, int32_t stage = -1) {
         Source& S = src[s];
         const int64_t nr = cur.nrows;
         const int64_t ncols = transposed ? S.m : S.k;
@@ -390,7 +390,8 @@ struct Builder {
         it.dtype = (int16_t)S.dtype;
         it.ebits = (int16_t)S.ebits;
         items.push_back(it);
-        item_floating.push_back(floats ? 1 : early ? 2 : 0);
+        item_floating.push_back(floats ? 1 : 0);
+        item_stage.push_back(stage);
         item_use.emplace_back(s, (int32_t)S.uses.size());
         cur.nitems++;
         cur_cols += (int32_t)ncols;
@@ -408,7 +409,8 @@ struct Builder {
         std::vector<int32_t> order(n);
         for (int32_t i = 0; i < n; ++i) order[i] = i;
         auto key = [&](int32_t i) {
-            return (item_floating[i0 + i] * 32 + items[i0 + i].dtype) * 16 + items[i0 + i].ebits;
+            return ((int64_t)(item_floating[i0 + i] * 32 + items[i0 + i].dtype) * 16 + items[i0 + i].ebits) *
+                       (1 << 20) + (item_stage[i0 + i] + 1);
         };
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
         bool same = true;
@@ -416,6 +418,7 @@ struct Builder {
         if (same) return;
         std::vector<DItem> it(n);
         std::vector<uint8_t> fl(n);
+        std::vector<int32_t> sg(n);
         std::vector<std::pair<int32_t, int32_t>> us(n);
         int64_t off = items[i0].data_off;
         int32_t col = 0, tile = 0;
@@ -431,12 +434,14 @@ struct Builder {
             tile += (int32_t)tiles;
             it[k] = d;
             fl[k] = item_floating[i];
+            sg[k] = item_stage[i];
             us[k] = item_use[i];
             src[us[k].first].uses[us[k].second].data_off = d.data_off;
         }
         for (int32_t k = 0; k < n; ++k) {
             items[i0 + k] = it[k];
             item_floating[i0 + k] = fl[k];
+            item_stage[i0 + k] = sg[k];
             item_use[i0 + k] = us[k];
         }
     }
@@ -467,7 +472,7 @@ struct Builder {
             // AFLP exponent widths
             if (i > 0 && start_col < it.col0 &&
                 (item_floating[ii] != item_floating[ii - 1] || it.dtype != items[ii - 1].dtype ||
-                 it.ebits != items[ii - 1].ebits)) {
+                 it.ebits != items[ii - 1].ebits || item_stage[ii] != item_stage[ii - 1])) {
                 emit(it.col0);
                 start_item = ii;
             }
@@ -527,11 +532,11 @@ struct Builder {
             t.ntasks = cur.ntasks;
             t.part_off = cur.part_off;
             t.rscale_off = cur.rscale_off;
-            const uint8_t cls = t.c0 < t.c1 ? item_floating[t.item_start] : 0;
-            if (cls == 1) {
+            const bool fl = t.c0 < t.c1 && item_floating[t.item_start];
+            if (fl) {
                 floating.push_back(tb);
             } else {
-                const int32_t si = cls == 2 ? early_stage : cur_stage;
+                const int32_t si = t.c0 < t.c1 && item_stage[t.item_start] >= 0 ? item_stage[t.item_start] : cur_stage;
                 stage_tasks[si].push_back(t);
                 stage_bytes[si] += tb.second;
             }
@@ -892,6 +897,7 @@ struct Builder {
             if (kr > 0) { t_off[v] = (int32_t)ws; ws += kr; }
         }
         const int32_t pl = new_stage("h2_up_leaf");
+        std::vector<int32_t> prod_stage(N, -1);   // stage that produces s_v
         std::vector<std::vector<int32_t>> cperm(N);
         for (int32_t g : leaves) {
             const int32_t kc = V->col_rank[g];
@@ -901,6 +907,7 @@ struct Builder {
                 add_item(r.src, 0, true, (int32_t)L.node_begin[g]);
                 end_owner();
             }
+            prod_stage[g] = pl;
         }
         std::vector<std::vector<int32_t>> by_level(L.depth + 1);
         for (int32_t v = 0; v < N; ++v) by_level[L.node_level[v]].push_back(v);
@@ -913,6 +920,7 @@ struct Builder {
                 const int32_t kc = V->col_rank[v];
                 if (L.leaf(v) || kc == 0) continue;
                 begin_owner(pu, kc, 0, s_off[v], -1);
+                prod_stage[v] = pu;
                 for (int32_t c : {L.node_son0[v], L.node_son1[v]}) {
                     const int32_t kcc = V->col_rank[c];
                     if (kcc == 0) continue;
@@ -928,15 +936,18 @@ struct Builder {
         for (int32_t rho : leaves)
             if (V->row_rank[rho] > 0)
                 lrun[rho] = basis_factor(V->row_basis[rho], L.size(rho), V->row_rank[rho], V->row_sv, rho);
-        // The coupling products S_b s_s of every level depend only on the
-        // upward pass, so (by default) they all run in one launch right after
-        // it, as partial sums of their row cluster's coefficient owner; the
-        // downward recursion t_t = E_t t_parent + (those partial sums) then
-        // only adds the small transfer products level by level (Alg. 7's
-        // recursion; each owner's partial sums are added in a fixed task
-        // order, so the result is deterministic).
+        // The coupling products S_b s_s depend only on the upward pass, so
+        // (by default) they run during it, as partial sums of their row
+        // cluster's coefficient owner; the downward recursion
+        // t_t = E_t t_parent + (those partial sums) then only adds the small
+        // transfer products level by level (Alg. 7's recursion; each owner's
+        // partial sums are added in a fixed task order, so the result is
+        // deterministic).
+        // A coupling reading s_s runs in the launch right after the one that
+        // produced s_s: the next (coarser) upward level, whose own work is
+        // small, or a last launch for the coarsest level's couplings.
         const bool early = opt.coupling_first;
-        if (early) early_stage = new_stage("h2_coup");
+        const int32_t pc = early ? new_stage("h2_coup") : -1;
         for (int32_t lv = 0; lv <= L.depth; ++lv) {
             bool any = false;
             for (int32_t v : by_level[lv]) any |= V->row_rank[v] > 0;
@@ -965,7 +976,8 @@ struct Builder {
                     if (kc == 0) continue;
                     if (!V->coupling[b]) return check(false, "missing coupling");
                     int32_t cs = add_source(permute_cols(V->coupling[b], kr, kc, cperm[s]), kr, kc, coup_dt, nullptr, 2);
-                    add_item(cs, 0, false, s_off[s], false, false, early);
+                    add_item(cs, 0, false, s_off[s], false, false,
+                             early ? std::min(prod_stage[s] + 1, pc) : -1);
                 }
                 end_owner();
             }
