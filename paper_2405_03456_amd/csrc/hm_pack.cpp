@@ -897,7 +897,6 @@ struct Builder {
             if (kr > 0) { t_off[v] = (int32_t)ws; ws += kr; }
         }
         const int32_t pl = new_stage("h2_up_leaf");
-        std::vector<int32_t> prod_stage(N, -1);   // stage that produces s_v
         std::vector<std::vector<int32_t>> cperm(N);
         for (int32_t g : leaves) {
             const int32_t kc = V->col_rank[g];
@@ -907,7 +906,6 @@ struct Builder {
                 add_item(r.src, 0, true, (int32_t)L.node_begin[g]);
                 end_owner();
             }
-            prod_stage[g] = pl;
         }
         std::vector<std::vector<int32_t>> by_level(L.depth + 1);
         for (int32_t v = 0; v < N; ++v) by_level[L.node_level[v]].push_back(v);
@@ -920,7 +918,6 @@ struct Builder {
                 const int32_t kc = V->col_rank[v];
                 if (L.leaf(v) || kc == 0) continue;
                 begin_owner(pu, kc, 0, s_off[v], -1);
-                prod_stage[v] = pu;
                 for (int32_t c : {L.node_son0[v], L.node_son1[v]}) {
                     const int32_t kcc = V->col_rank[c];
                     if (kcc == 0) continue;
@@ -937,15 +934,16 @@ struct Builder {
             if (V->row_rank[rho] > 0)
                 lrun[rho] = basis_factor(V->row_basis[rho], L.size(rho), V->row_rank[rho], V->row_sv, rho);
         // The coupling products S_b s_s depend only on the upward pass, so
-        // (by default) they run during it, as partial sums of their row
-        // cluster's coefficient owner; the downward recursion
+        // (by default) they run before the downward pass, as partial sums of
+        // their row cluster's coefficient owner; the downward recursion
         // t_t = E_t t_parent + (those partial sums) then only adds the small
         // transfer products level by level (Alg. 7's recursion; each owner's
         // partial sums are added in a fixed task order, so the result is
         // deterministic).
-        // A coupling reading s_s runs in the launch right after the one that
-        // produced s_s: the next (coarser) upward level, whose own work is
-        // small, or a last launch for the coarsest level's couplings.
+        // All of them run in one launch right after the upward pass (measured
+        // faster than running each in the upward launch after its input's:
+        // the long coarse-level coupling tasks then set those launches'
+        // tails, while in one launch they overlap the rest).
         const bool early = opt.coupling_first;
         const int32_t pc = early ? new_stage("h2_coup") : -1;
         for (int32_t lv = 0; lv <= L.depth; ++lv) {
@@ -977,7 +975,7 @@ struct Builder {
                     if (!V->coupling[b]) return check(false, "missing coupling");
                     int32_t cs = add_source(permute_cols(V->coupling[b], kr, kc, cperm[s]), kr, kc, coup_dt, nullptr, 2);
                     add_item(cs, 0, false, s_off[s], false, false,
-                             early ? std::min(prod_stage[s] + 1, pc) : -1);
+                             early ? pc : -1);
                 }
                 end_owner();
             }
