@@ -321,7 +321,11 @@ MANY_POLICIES = {
     "f32": dict(dense="f32", factor="f32", coupling="f32"),
     "bf16": dict(dense="bf16", factor="bf16", coupling="bf16"),
     "valr": dict(dense="valr", diag="valr", factor="valr", coupling="valr"),
+    "aflp": dict(dense="aflp", diag="aflp", factor="aflp", coupling="aflp"),
+    "fpx": dict(dense="fpx", diag="fpx", factor="fpx", coupling="fpx"),
 }
+# bytes of one stored value per dtype code (include/hm.h; code 5 is a policy)
+DTYPE_BYTES = (8, 4, 2, 2, 1, 0, 3, 5, 6, 7, 1, 2, 3, 4, 5, 6, 7)
 
 
 def many_rhs(args, hm, torch, lay, fmt, vals, eps, n, points, st, desc):
@@ -344,8 +348,7 @@ def many_rhs(args, hm, torch, lay, fmt, vals, eps, n, points, st, desc):
             del sv
         s = M.stats()
         entries = sum(s["entries_per_dtype"])
-        esize = (8, 4, 2, 2, 1)
-        stored_b = float(sum(c * esize[d] for d, c in enumerate(s["entries_per_dtype"])))
+        stored_b = float(sum(c * DTYPE_BYTES[d] for d, c in enumerate(s["entries_per_dtype"])))
         vec_b = float(s["method_bytes"]) - stored_b        # x, y, coefficients (+ FP16/FP8 column scales)
         acc64 = s["accum"] == hm.HM_ACC_F64
         for r in widths:
