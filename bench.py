@@ -173,7 +173,8 @@ def run_variant(hm, torch, lay, fmt, vals, eps, pol, steps, warmup, x, target):
     for m in mats:
         m.free()
     return dict(stats=s0, ncopies=ncopies, times=times, wall=wall, phases=phases, y=y_out,
-                fork_after=[t["fork_after"] for t in tuned])
+                fork_after=[t["fork_after"] for t in tuned],
+                dense_split=[[t["fork2"], t["dense_split"]] if t["dense_split"] else None for t in tuned])
 
 
 def summarize(res, steps):
@@ -196,7 +197,7 @@ def summarize(res, steps):
     return dict(ms_per_step=ms, p10_ms=float(np.percentile(t, 10)), p90_ms=float(np.percentile(t, 90)),
                 wall_ms_per_step=res["wall"] * 1e3 / steps, gbs=gbs, matvecs_per_s=1e3 / ms, roofline=roof,
                 method_bytes=mb, overhead_bytes=float(s["algorithmic_bytes"]) - mb,
-                copies=res["ncopies"], fork_after=res["fork_after"],
+                copies=res["ncopies"], fork_after=res["fork_after"], dense_split=res["dense_split"],
                 phases=[{"name": p["name"], "ntasks": p["ntasks"],
                          "us_avg": round(p["ms_total"] * 1e3 / max(p["launches"], 1), 2),
                          "GBs": (round(p["method_bytes"] / (p["ms_total"] / p["launches"]) / 1e6, 1)
@@ -294,7 +295,8 @@ def single_vector(args, hm, torch, name, legs, with_cpu, with_parity):
                "method_bytes_per_matvec": int(sm["method_bytes"]),
                "overhead_bytes_per_matvec": int(sm["overhead_bytes"]),
                "bytes_per_dtype": r["stats"]["bytes_per_dtype"], "entries_per_dtype": r["stats"]["entries_per_dtype"],
-               "fork_after": sm["fork_after"], "copies": sm["copies"], "roofline": sm["roofline"],
+               "fork_after": sm["fork_after"], "dense_split": sm["dense_split"], "copies": sm["copies"],
+               "roofline": sm["roofline"],
                "policy": pol}
         if base is None:
             base = sm

@@ -453,7 +453,11 @@ hm_status hm_tune_batch(hm_matrix* m, int32_t nrhs, int32_t vec_dtype, int32_t r
  * complete before the dense stage starts (0 = right after x is gathered).
  * Persistent schedule: the free parameter is dense_after, the first boundary
  * between chain stages from which the dense tasks are interleaved into the
- * queue.  hm_tune_mvm times every candidate of both schedules (`reps`
+ * queue.  In the staged schedule the dense stage may also run as two
+ * launches on the second stream: its first dense_split tasks from the fork
+ * point, the rest once fork2 chain stages are done (after the first part);
+ * the tuner tries split fractions 1/4, 1/2, 3/4 at later second fork
+ * points.  hm_tune_mvm times every candidate of both schedules (`reps`
  * replays of a captured graph of the product on a zero vector, allocated and
  * freed here; a matrix uploaded with HM_SCHED_STAGED has no persistent
  * candidates) and keeps the fastest for this matrix.  No candidate changes
@@ -470,6 +474,9 @@ typedef struct {
     int32_t dense_after;    /* persistent schedule: chosen interleave point */
     double ms_staged;       /* best staged candidate */
     double ms_persistent;   /* best persistent candidate (0 if none) */
+    int32_t fork2;          /* staged schedule: chain stages completed before the second part of the
+                               dense stage starts (meaningful when dense_split > 0) */
+    int32_t dense_split;    /* staged schedule: dense tasks in the first part (0 = one launch) */
 } hm_tune_mvm_result;
 hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream, hm_tune_mvm_result* out);
 
@@ -480,11 +487,20 @@ hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream, hm_tune_mv
  * The graph records no memset nodes.  Errors: HM_EINVAL, HM_EDEVICE. */
 /* Sets the single-vector schedule of a matrix without timing anything:
  * HM_SCHED_STAGED with param = fork point (0 ... number of dependent
- * stages), or HM_SCHED_PERSISTENT with param = dense_after (any value >= 0;
+ * stages; the dense stage as one launch), or HM_SCHED_PERSISTENT with param = dense_after (any value >= 0;
  * a matrix uploaded with HM_SCHED_STAGED has no persistent queue).  Changes
  * no arithmetic.  Synchronous (the queue order is copied); not inside graph
  * capture.  Errors: HM_EINVAL, HM_ELAYOUT, HM_EDEVICE. */
 hm_status hm_set_schedule(hm_matrix* m, int32_t schedule, int32_t param);
+
+/* Staged schedule: run the dense stage as two launches on the second stream,
+ * its first `first_tasks` tasks from the fork point and the rest once `fork2`
+ * dependent stages are done (first_tasks = 0: one launch).  The dense tasks
+ * are independent, so the products are bitwise identical for every choice;
+ * hm_tune_mvm picks these values by timing.  Not inside graph capture
+ * (graphs keep the schedule they were captured with).  Errors: HM_EINVAL
+ * (negative values, or first_tasks not below the dense stage's tasks). */
+hm_status hm_set_dense_split(hm_matrix* m, int32_t fork2, int32_t first_tasks);
 
 typedef struct hm_graph hm_graph;
 hm_status hm_graph_create(hm_matrix* m, double alpha, const double* x, double* y, uint32_t flags,

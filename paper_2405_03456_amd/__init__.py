@@ -251,12 +251,19 @@ class Matrix:
         _lib.check(_lib.lib().hm_tune_mvm(self._h, int(reps), _stream_ptr(stream), ctypes.byref(r)))
         return dict(fork_after=r.fork_after, ncandidates=r.ncandidates, ms=r.ms, ms_first=r.ms_first,
                     schedule="persistent" if r.schedule == _lib.HM_SCHED_PERSISTENT else "staged",
-                    dense_after=r.dense_after, ms_staged=r.ms_staged, ms_persistent=r.ms_persistent)
+                    dense_after=r.dense_after, ms_staged=r.ms_staged, ms_persistent=r.ms_persistent,
+                    fork2=r.fork2, dense_split=r.dense_split)
 
     def set_schedule(self, schedule: str, param: int = 0):
         """hm_set_schedule: "staged" (param = fork point) or "persistent"
         (param = dense_after)."""
         _lib.check(_lib.lib().hm_set_schedule(self._h, SCHEDULES[schedule], int(param)))
+
+    def set_dense_split(self, fork2: int, first_tasks: int):
+        """hm_set_dense_split: the dense stage as two launches (first_tasks
+        tasks from the fork point, the rest after fork2 dependent stages);
+        first_tasks = 0 restores one launch."""
+        _lib.check(_lib.lib().hm_set_dense_split(self._h, int(fork2), int(first_tasks)))
 
     def check(self):
         """Wait for the device; raise if a persistent launch of this matrix

@@ -102,7 +102,7 @@ class TuneResult(ctypes.Structure):
 class TuneMvmResult(ctypes.Structure):
     _fields_ = [("fork_after", c_int32), ("ncandidates", c_int32), ("ms", c_double), ("ms_first", c_double),
                 ("schedule", c_int32), ("dense_after", c_int32), ("ms_staged", c_double),
-                ("ms_persistent", c_double)]
+                ("ms_persistent", c_double), ("fork2", c_int32), ("dense_split", c_int32)]
 
 
 class ServeOpts(ctypes.Structure):
@@ -155,6 +155,7 @@ SIGNATURES = {
     "hm_serve_stats_read": (c_int32, [c_void_p, P(ServeStats)]),
     "hm_serve_destroy": (None, [c_void_p]),
     "hm_round_host": (c_int32, [c_int32, P(c_double), P(c_double), c_int64]),
+    "hm_set_dense_split": (c_int32, [c_void_p, c_int32, c_int32]),
     "hm_codec_column": (c_int32, [c_int32, c_double, c_int32, P(c_double), c_int64, P(c_double), P(ctypes.c_uint64),
                                   P(c_int32)]),
     "hm_last_error": (ctypes.c_char_p, []),

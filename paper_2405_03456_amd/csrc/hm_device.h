@@ -218,6 +218,7 @@ struct DevStage {
     std::string name;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;   // HM_TIMING event pairs
     int32_t timed_nrhs = 1;                                    // block width of the pending pairs
+    int32_t timed_parts = 1;                                   // launches per product of the pending pairs
 };
 
 }  // namespace hm
@@ -238,6 +239,8 @@ struct hm_matrix {
     double* part = nullptr;
     const int64_t* dsrc = nullptr;   // per workspace entry: 0 or the partial sums forming it
     int32_t fork_after = 0;          // main-stream stages before the second stream starts
+    int32_t fork2 = 0;               // ... before the second part of a split dense stage starts
+    int32_t dense_split = 0;         // tasks of the dense stage's first launch (0 = not split)
     const hm::DOwner* owners = nullptr;
     const hm::DItem* items = nullptr;
     const hm::DTask* tasks = nullptr;
@@ -245,7 +248,7 @@ struct hm_matrix {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
     // second stream for the independent dense stage, with fork/join events
     hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_fork2 = nullptr;
     int32_t aux_grid = 0;      // workgroup cap of the second-stream stage (0 = one wave per task)
     hm_stats stats{};
     int64_t ws_elems = 0;      // x in cluster order + coefficient vectors

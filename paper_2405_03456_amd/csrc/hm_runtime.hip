@@ -298,6 +298,7 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         e = hipStreamCreateWithFlags(&m->aux, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_fork2, hipEventDisableTiming);
         if (e != hipSuccess) {
             hm_matrix_free(m);
             return hip_fail("hm_upload: stream/event creation", e);
@@ -410,6 +411,7 @@ extern "C" void hm_matrix_free(hm_matrix* m) {
     }
     if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
     if (m->ev_join) (void)hipEventDestroy(m->ev_join);
+    if (m->ev_fork2) (void)hipEventDestroy(m->ev_fork2);
     if (m->aux) (void)hipStreamDestroy(m->aux);
     if (m->arena) (void)hipFree(m->arena);
     if (m->mr_arena) (void)hipFree(m->mr_arena);
@@ -495,6 +497,9 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
         (void)hipEventRecord(m->ev_fork, main_stream);
         (void)hipStreamWaitEvent(m->aux, m->ev_fork, 0);
     };
+    // split dense stage: its second part waits for fork2 chain stages
+    int fork2_left = m->dense_split > 0 ? m->fork2 : -1;
+    bool fork2_recorded = m->dense_split <= 0 || m->aux == nullptr;
     bool forked = m->aux == nullptr;
     if (!forked && fork_left <= 0) {
         fork();
@@ -513,8 +518,9 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
             (void)hipStreamWaitEvent(main_stream, m->ev_join, 0);
             joined = true;
         }
-        if (ph.ntasks > 0) {
-            unsigned blocks = (unsigned)((ph.ntasks + 3) / 4);
+        // tasks [t0, t0 + nt) of this stage as one launch on `stream`
+        auto launch = [&](int64_t t0, int32_t nt) -> bool {
+            unsigned blocks = (unsigned)((nt + 3) / 4);
             if (ph.aux && m->aux_grid > 0) blocks = std::min<unsigned>(blocks, (unsigned)m->aux_grid);
             dim3 grid(blocks);
             const hm::dev::TaskKernel kern = hm::dev::task_kernel(m->acc64 != 0, ph.dtype_mask);
@@ -522,19 +528,39 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
                 // the event pair is part of the dispatch: it brackets the
                 // kernel's execution, as a kernel trace does
                 std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-                if (!hm::timing_acquire(m, ph, 1, ev)) {
-                    hm::set_error("hm_mvm: timing events failed");
-                    return HM_EDEVICE;
-                }
-                hipExtLaunchKernelGGL(kern, grid, dim3(256), 0, stream, ev.first, ev.second, 0, m->tasks + ph.t0,
-                                      ph.ntasks, m->owners, m->items, m->data, m->scales, (const double*)m->ws,
+                if (!hm::timing_acquire(m, ph, 1, ev)) return false;
+                hipExtLaunchKernelGGL(kern, grid, dim3(256), 0, stream, ev.first, ev.second, 0, m->tasks + t0, nt,
+                                      m->owners, m->items, m->data, m->scales, (const double*)m->ws,
                                       (const float*)m->ws32, m->ws, m->ws32, m->part, (const int64_t*)m->dsrc, y,
                                       perm, alpha, m->ypriv, n);
                 ph.pending.push_back(ev);
             } else {
-                hipLaunchKernelGGL(kern, grid, dim3(256), 0, stream, m->tasks + ph.t0, ph.ntasks, m->owners,
-                                   m->items, m->data, m->scales, m->ws, m->ws32, m->ws, m->ws32, m->part, m->dsrc, y,
-                                   perm, alpha, m->ypriv, n);
+                hipLaunchKernelGGL(kern, grid, dim3(256), 0, stream, m->tasks + t0, nt, m->owners, m->items, m->data,
+                                   m->scales, m->ws, m->ws32, m->ws, m->ws32, m->part, m->dsrc, y, perm, alpha,
+                                   m->ypriv, n);
+            }
+            return true;
+        };
+        if (ph.ntasks > 0) {
+            const bool split = ph.aux && m->dense_split > 0 && m->dense_split < ph.ntasks;
+            ph.timed_parts = split ? 2 : 1;
+            bool ok = true;
+            if (split) {
+                // first part from the fork point; the second after fork2
+                // chain stages (recorded on the main stream in order)
+                ok = launch(ph.t0, m->dense_split);
+                if (!fork2_recorded) {
+                    (void)hipEventRecord(m->ev_fork2, main_stream);
+                    fork2_recorded = true;
+                }
+                (void)hipStreamWaitEvent(m->aux, m->ev_fork2, 0);
+                if (ok) ok = launch(ph.t0 + m->dense_split, ph.ntasks - m->dense_split);
+            } else {
+                ok = launch(ph.t0, ph.ntasks);
+            }
+            if (!ok) {
+                hm::set_error("hm_mvm: timing events failed");
+                return HM_EDEVICE;
             }
         }
         if (ph.nreduce > 0) {
@@ -545,6 +571,10 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
         if (!forked && !ph.aux && ph.ntasks > 0 && --fork_left == 0) {
             fork();
             forked = true;
+        }
+        if (!fork2_recorded && !ph.aux && ph.ntasks > 0 && --fork2_left == 0) {
+            (void)hipEventRecord(m->ev_fork2, main_stream);
+            fork2_recorded = true;
         }
     }
     if (!joined) {   // no final reduction stage: still join the second stream
@@ -603,7 +633,7 @@ extern "C" hm_status hm_timing_read(hm_matrix* m, hm_phase_timing* out, int32_t 
         if (i < cap) {
             out[i].name = ph.name.c_str();
             out[i].ms_total = ms;
-            out[i].launches = cnt;
+            out[i].launches = cnt / std::max(ph.timed_parts, 1);   // a split stage counts once per product
             out[i].algorithmic_bytes = ph.alg_bytes;
             out[i].ntasks = ph.ntasks;
             out[i].nowners = ph.nowners;
@@ -694,6 +724,20 @@ static hm_status set_dense_after(hm_matrix* m, int32_t dense_after) {
     return HM_OK;
 }
 
+extern "C" hm_status hm_set_dense_split(hm_matrix* m, int32_t fork2, int32_t first_tasks) {
+    int32_t nd = 0;
+    if (m)
+        for (auto& ph : m->phases)
+            if (ph.aux) nd += ph.ntasks;
+    if (!m || fork2 < 0 || first_tasks < 0 || (first_tasks > 0 && first_tasks >= nd)) {
+        hm::set_error("hm_set_dense_split: null matrix, negative value, or first_tasks not below the dense tasks");
+        return HM_EINVAL;
+    }
+    m->fork2 = fork2;
+    m->dense_split = first_tasks;
+    return HM_OK;
+}
+
 extern "C" hm_status hm_set_schedule(hm_matrix* m, int32_t schedule, int32_t param) {
     if (!m || param < 0 || (schedule != HM_SCHED_STAGED && schedule != HM_SCHED_PERSISTENT) ||
         (schedule == HM_SCHED_PERSISTENT && !m->p_ctl)) {
@@ -702,6 +746,7 @@ extern "C" hm_status hm_set_schedule(hm_matrix* m, int32_t schedule, int32_t par
     }
     if (schedule == HM_SCHED_STAGED) {
         m->fork_after = param;
+        m->dense_split = 0;   // one dense launch
     } else {
         hipError_t e = hipDeviceSynchronize();   // no product may be reading the queue being replaced
         if (e != hipSuccess) return hip_fail("hm_set_schedule: synchronize", e);
@@ -788,6 +833,37 @@ extern "C" hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream_
         }
     }
     m->fork_after = best_sched == HM_SCHED_STAGED ? best_fork : keep_fork;
+    // split dense stage: with the best fork point, the second part from a
+    // later chain stage (at most 8 second fork points, spread), a quarter,
+    // half or three quarters of the dense tasks in the first part
+    const int32_t keep_f2 = m->fork2, keep_split = m->dense_split;
+    int32_t best_f2 = keep_f2, best_split = 0;
+    m->dense_split = 0;
+    int32_t nd = 0;
+    for (auto& ph : m->phases)
+        if (ph.aux) nd += ph.ntasks;
+    if (m->aux && nd >= 8 && best_sched == HM_SCHED_STAGED && st == HM_OK) {
+        const int32_t span = last - best_fork;
+        for (int32_t i = 1; i <= std::min(span, 8) && st == HM_OK; ++i) {
+            const int32_t f2 = best_fork + (span <= 8 ? i : (int32_t)((int64_t)i * span / 8));
+            for (int32_t q = 1; q <= 3 && st == HM_OK; ++q) {
+                m->fork2 = f2;
+                m->dense_split = (int32_t)((int64_t)nd * q / 4);
+                double t = 0.0;
+                st = time_it(t);
+                if (st != HM_OK) break;
+                ++out->ncandidates;
+                if (out->ms_staged == 0.0 || t < out->ms_staged) out->ms_staged = t;
+                if (t < best_ms) {
+                    best_f2 = f2;
+                    best_split = m->dense_split;
+                    best_ms = t;
+                }
+            }
+        }
+    }
+    m->fork2 = best_split > 0 ? best_f2 : keep_f2;
+    m->dense_split = st == HM_OK ? best_split : keep_split;
     // persistent schedule: interleave points of the dense tasks (at most 17,
     // spread over 0 ... nchain of the queue)
     if (m->p_ctl && st == HM_OK) {
@@ -819,6 +895,8 @@ extern "C" hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream_
         m->schedule = best_sched;
         out->schedule = best_sched;
         out->fork_after = m->fork_after;
+        out->fork2 = m->fork2;
+        out->dense_split = m->schedule == HM_SCHED_STAGED ? m->dense_split : 0;
         out->dense_after = m->p_dense_after;
         out->ms = best_ms;
     } else {

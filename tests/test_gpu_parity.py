@@ -146,7 +146,9 @@ def test_tune_mvm_keeps_results_bitwise(fmt):
     # staged: one candidate per fork point 0 ... number of chain stages with
     # tasks; persistent: at most 17 interleave points
     nchain = sum(1 for ph in M.timing() if ph["ntasks"] > 0 and ph["name"] not in ("dense", "persistent"))
-    assert nchain + 2 <= r["ncandidates"] <= nchain + 1 + 17 and 0 <= r["fork_after"] <= nchain
+    # (+ at most 24 split candidates: 8 second fork points x 3 fractions)
+    assert nchain + 2 <= r["ncandidates"] <= nchain + 1 + 24 + 17 and 0 <= r["fork_after"] <= nchain
+    assert r["dense_split"] == 0 or (r["schedule"] == "staged" and r["fork2"] > r["fork_after"])
     assert r["ms"] > 0 and r["ms"] <= r["ms_first"] and r["ms"] == min(r["ms_staged"], r["ms_persistent"])
     assert r["schedule"] == ("staged" if r["ms"] == r["ms_staged"] else "persistent")
     M.check()
@@ -201,3 +203,41 @@ def test_valr_tile_promotion_within_budget(fmt, eps):
     assert rel(plain, ref, y) <= TOL32                       # paper rule: parity
     assert rel(out, ref, y) <= 3.0 * eps                     # promotion: within the budget
     assert rel(out, exact, y) <= 3.0 * eps                   # ... of the float64 product too
+
+
+@pytest.mark.parametrize("fmt", ["h", "uh", "h2"])
+def test_split_dense_stage_is_bitwise_neutral(fmt):
+    """The dense stage as two launches (hm_set_dense_split) at several split
+    points and second fork points: eager products and graph replays equal
+    the one-launch product bit for bit, and per-phase timing counts the two
+    launches as one per product."""
+    import paper_2405_03456_amd as hm
+    torch = torch_cuda()
+    n = 2048
+    p, st, lay, vals = make(n, 1e-8)
+    x, y = gaussian_vector(n, 22), gaussian_vector(n, 23)
+    print(f"case split dense stage {fmt}", flush=True)
+    M = hm.Matrix(lay, fmt, vals[fmt], dense="f64", factor="f64", eps=1e-8)
+    xd = torch.from_numpy(x).cuda()
+    y0 = torch.from_numpy(y.copy()).cuda()
+    M.mvm(xd, y0, alpha=-1.5)
+    nd = sum(ph["ntasks"] for ph in M.timing() if ph["name"] == "dense")
+    nchain = sum(1 for ph in M.timing() if ph["ntasks"] > 0 and ph["name"] != "dense")
+    assert nd >= 4
+    for f2 in (0, 1, nchain, nchain + 5):
+        for first in (1, nd // 2, nd - 1):
+            M.set_dense_split(f2, first)
+            y1 = torch.from_numpy(y.copy()).cuda()
+            M.mvm(xd, y1, alpha=-1.5, timing=True)
+            y2 = torch.from_numpy(y.copy()).cuda()
+            g = M.graph(xd, y2, alpha=-1.5)
+            g.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(y0, y1) and torch.equal(y0, y2), (f2, first)
+            g.free()
+            dense = [ph for ph in M.timing() if ph["name"] == "dense"][0]
+            assert dense["launches"] == 1
+    with pytest.raises(hm.HMError):
+        M.set_dense_split(1, nd)
+    M.set_dense_split(0, 0)
+    M.free()
