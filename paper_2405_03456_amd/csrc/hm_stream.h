@@ -367,18 +367,16 @@ __device__ __forceinline__ void run_task(const DTask& tk, int lane, double* __re
             HM_STREAM_CASE(HM_AFLP56)
 #undef HM_STREAM_CASE
         };
-        // A task streams one run of items of one format, or (mode bit 5)
-        // several in turn, each with its own decoder into the same
-        // accumulators; the run bounds come from the item table (uniform
-        // loads).  One call site keeps the register budget of the decoders.
-        const bool multi = (tk.mode & 32) != 0;
-        DTask sg = tk;
-        int sdt = dt;
-        int it = tk.item_start, c = tk.c0;
-        for (;;) {
-            int last = it;
-            if (multi) {
+        if (!(tk.mode & 32)) {
+            run_seg(tk, dt);
+        } else {
+            // the task spans several runs (mode bit 5): each is streamed with
+            // its own decoder into the same accumulators; the run bounds come
+            // from the item table (uniform loads)
+            int it = tk.item_start, c = tk.c0;
+            while (c < tk.c1) {
                 const DItem d0 = items[it];
+                int last = it;
                 int cend = min(d0.col0 + d0.ncols, tk.c1);
                 while (cend < tk.c1) {
                     const DItem dn = items[last + 1];
@@ -388,20 +386,18 @@ __device__ __forceinline__ void run_task(const DTask& tk, int lane, double* __re
                 }
                 const DItem dl = items[last];
                 const int V = tile_cols_of(d0.dtype);
+                DTask sg = tk;
                 sg.c0 = c;
                 sg.c1 = cend;
                 sg.item_start = it;
                 sg.k0 = d0.tile0 + (c - d0.col0) / V;
-                sg.k1 = cend == dl.col0 + dl.ncols ? dl.tile0 + (dl.ncols + V - 1) / V
-                                                   : dl.tile0 + (cend - dl.col0) / V;
+                sg.k1 = cend == dl.col0 + dl.ncols ? dl.tile0 + (dl.ncols + V - 1) / V : dl.tile0 + (cend - dl.col0) / V;
                 sg.dtype = d0.dtype;
                 sg.mode = (int16_t)((tk.mode & ~0x0F20) | (d0.ebits << 8));
-                sdt = d0.dtype;
+                run_seg(sg, d0.dtype);
+                c = cend;
+                it = last + 1;
             }
-            run_seg(sg, sdt);
-            if (!multi || sg.c1 >= tk.c1) break;
-            c = sg.c1;
-            it = last + 1;
         }
         double v = a64 + (double)a32;
         for (int off = P; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);   // across column groups
