@@ -188,18 +188,6 @@ template <> struct Tile<HM_AFLP56> : AflpTile<7> {};
 // float64 decode (wide accumulation whatever the matrix's mode)
 template <int DT> constexpr bool kWide = std::is_same<typename Tile<DT>::R, double>::value;
 
-// columns per 16-byte tile of a dtype (runtime form of Tile<DT>::V)
-__device__ __forceinline__ int tile_cols_of(int dt) {
-    switch (dt) {
-        case HM_F64: case HM_FPX48: case HM_FPX56: case HM_AFLP48: case HM_AFLP56: return 2;
-        case HM_F32: case HM_AFLP32: return 4;
-        case HM_BF16: case HM_F16: case HM_AFLP16: return 8;
-        case HM_FPX24: case HM_AFLP24: return 5;
-        case HM_FPX40: case HM_AFLP40: return 3;
-        default: return 16;   // HM_FP8E4M3, HM_AFLP8
-    }
-}
-
 // AFLP exponent width of a task (bits 8-11 of its mode)
 __device__ __forceinline__ int task_ebits(int16_t mode) { return (mode >> 8) & 15; }
 

@@ -454,7 +454,6 @@ struct Builder {
         std::vector<std::pair<DTask, int64_t>> made;
         int32_t start_col = 0, start_item = cur.item0;
         int64_t acc = 0;
-        int64_t acc_in = 0;   // input values the task may stage in LDS (tiles * V over its items)
         auto emit = [&](int32_t c1) {
             DTask t{};
             t.owner = owner_id;
@@ -465,42 +464,36 @@ struct Builder {
             made.push_back({t, acc});
             start_col = c1;
             acc = 0;
-            acc_in = 0;
         };
         for (int32_t i = 0; i < cur.nitems; ++i) {
             const int32_t ii = cur.item0 + i;
             const DItem& it = items[ii];
-            // a task never mixes floating and fixed items nor items of
-            // different stages; it may span several dtypes and AFLP widths
-            // (the kernel streams each run of one format in turn)
+            // a task never mixes floating and fixed items, nor two dtypes or
+            // AFLP exponent widths
             if (i > 0 && start_col < it.col0 &&
-                (item_floating[ii] != item_floating[ii - 1] || item_stage[ii] != item_stage[ii - 1])) {
+                (item_floating[ii] != item_floating[ii - 1] || it.dtype != items[ii - 1].dtype ||
+                 it.ebits != items[ii - 1].ebits || item_stage[ii] != item_stage[ii - 1])) {
                 emit(it.col0);
                 start_item = ii;
             }
             const int V = tile_cols(it.dtype);
             const int64_t bpt = (int64_t)cur.nrows * 16;     // bytes per tile
+            // a task may stage its inputs in LDS (narrow owners always, wide
+            // ones when they read unreduced sums): at most MAX_TASK_INPUTS
+            // input values (tiles * V) per task
+            const int64_t cap = (int64_t)(MAX_TASK_INPUTS / V) * bpt;
             // default task size by storage format (measured on the single-
             // vector product): 32 KiB of float64 tiles, 16 KiB of narrower ones
             const int64_t tb = opt.task_bytes ? opt.task_bytes : (it.dtype == HM_F64 ? 32768 : 16384);
+            const int64_t target = std::min<int64_t>(tb, cap);
             int32_t j = 0;
             while (j < it.ncols) {
-                // a task may stage its inputs in LDS (narrow owners always,
-                // wide ones when they read unreduced sums or scaled formats):
-                // at most MAX_TASK_INPUTS input values (tiles * V) per task
-                const int64_t tiles_in = (MAX_TASK_INPUTS - acc_in) / V;
-                if (tiles_in < 1) {
-                    emit(it.col0 + j);
-                    start_item = ii;
-                    continue;
-                }
-                const int64_t tiles = std::min<int64_t>(std::max<int64_t>(1, (tb - acc) / bpt), tiles_in);
-                const int64_t take = std::min<int64_t>(tiles * V, it.ncols - j);   // whole tiles
-                const int64_t nt = (take + V - 1) / V;
-                acc += nt * bpt;
-                acc_in += nt * V;
+                int64_t room = target - acc;
+                int64_t take = std::max<int64_t>(1, room / bpt) * V;   // whole tiles
+                take = std::min<int64_t>(take, it.ncols - j);
+                acc += ((take + V - 1) / V) * bpt;
                 j += (int32_t)take;
-                if (acc >= tb || acc_in + V > MAX_TASK_INPUTS) {
+                if (acc >= target) {
                     emit(it.col0 + j);
                     start_item = (j == it.ncols) ? ii + 1 : ii;
                 }
@@ -533,12 +526,8 @@ struct Builder {
             t.stream = stream;
             t.nrows = cur.nrows;
             t.dtype = (int16_t)(t.c0 < t.c1 ? items[t.item_start].dtype : -1);
-            // mode bits 8..11: the AFLP exponent width of the task's (first)
-            // items; bit 5: the task spans several runs of one format
+            // mode bits 8..11: the AFLP exponent width of the task's items
             t.mode = (int16_t)(cur.mode | (t.c0 < t.c1 ? items[t.item_start].ebits << 8 : 0));
-            for (int32_t it2 = t.item_start + 1; t.c0 < t.c1 && it2 < cur.item0 + cur.nitems && items[it2].col0 < t.c1; ++it2)
-                if (items[it2].dtype != items[t.item_start].dtype || items[it2].ebits != items[t.item_start].ebits)
-                    t.mode = (int16_t)(t.mode | 32);
             t.out_off = cur.out_off;
             t.ntasks = cur.ntasks;
             t.part_off = cur.part_off;
@@ -1171,7 +1160,7 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
             const DTask& t = P.tasks[k];
             if (t.owner < 0 || t.owner >= no) { why = "task owner"; return false; }
             const DOwner& ow = P.owners[t.owner];
-            if (t.nrows != ow.nrows || (t.mode & 3) != ow.mode || t.out_off != ow.out_off || t.ntasks != ow.ntasks ||
+            if (t.nrows != ow.nrows || (t.mode & 0xFF) != ow.mode || t.out_off != ow.out_off || t.ntasks != ow.ntasks ||
                 t.part_off != ow.part_off || t.rscale_off != ow.rscale_off) {
                 why = "task copy of owner fields";
                 return false;
@@ -1204,23 +1193,13 @@ bool validate(const Packed& P, int64_t n, std::string& why) {
                 const DItem& it = P.items[t.item_start];
                 if (t.c0 < it.col0 || t.c0 >= it.col0 + it.ncols) { why = "task first item"; return false; }
                 if ((t.c0 - it.col0) % (16 / dtype_bytes(it.dtype))) { why = "task not tile aligned"; return false; }
-                // several formats only with mode bit 5; the inputs of the
-                // task's tiles fit the LDS slice
-                bool several = false;
-                int64_t inputs = 0;
-                for (int32_t j = t.item_start; j < ow.item0 + ow.nitems && P.items[j].col0 < t.c1; ++j) {
-                    const DItem& dj = P.items[j];
-                    several |= dj.dtype != it.dtype || dj.ebits != it.ebits;
-                    if (is_aflp(dj.dtype) && !aflp_feasible(aflp_width(dj.dtype), dj.ebits)) {
-                        why = "item AFLP exponent width";
+                // one dtype per task; the inputs fit the LDS slice
+                for (int32_t j = t.item_start; j < ow.item0 + ow.nitems && P.items[j].col0 < t.c1; ++j)
+                    if (P.items[j].dtype != it.dtype || P.items[j].ebits != it.ebits) {
+                        why = "task mixes dtypes";
                         return false;
                     }
-                    const int Vj = tile_cols(dj.dtype);
-                    const int32_t jb = std::max(t.c0 - dj.col0, 0), je = std::min(dj.ncols, t.c1 - dj.col0);
-                    inputs += (int64_t)((je + Vj - 1) / Vj - jb / Vj) * Vj;
-                }
-                if (several != ((t.mode & 32) != 0)) { why = "task format runs flag"; return false; }
-                if (inputs > MAX_TASK_INPUTS) {
+                if ((int64_t)(t.k1 - t.k0) * (16 / dtype_bytes(it.dtype)) > MAX_TASK_INPUTS) {
                     why = "task inputs exceed LDS slice";
                     return false;
                 }
@@ -1524,41 +1503,8 @@ void build_mr_plan(const std::vector<DOwner>& owners, const std::vector<DItem>& 
     for (int32_t si = 0; si < nst; ++si) {
         const Stage& st = stages[si];
         int64_t acc = 0;
-        // the many-RHS kernels stream one format per task: a task spanning
-        // several runs of one format is split into one task per run
-        std::vector<DTask> runs;
         for (int64_t k = st.t0; k < st.t1; ++k) {
-            const DTask& tk = tasks[k];
-            if (!(tk.mode & 32)) {
-                runs.push_back(tk);
-                continue;
-            }
-            const DOwner& ow = owners[tk.owner];
-            int32_t it = tk.item_start, c = tk.c0;
-            while (c < tk.c1) {
-                const DItem& d0 = items[it];
-                int32_t last = it, cend = std::min(d0.col0 + d0.ncols, tk.c1);
-                while (cend < tk.c1 && last + 1 < ow.item0 + ow.nitems && items[last + 1].dtype == d0.dtype &&
-                       items[last + 1].ebits == d0.ebits) {
-                    ++last;
-                    cend = std::min(items[last].col0 + items[last].ncols, tk.c1);
-                }
-                const DItem& dl = items[last];
-                const int V = tile_cols(d0.dtype);
-                DTask r = tk;
-                r.c0 = c;
-                r.c1 = cend;
-                r.item_start = it;
-                r.k0 = d0.tile0 + (c - d0.col0) / V;
-                r.k1 = cend == dl.col0 + dl.ncols ? dl.tile0 + (dl.ncols + V - 1) / V : dl.tile0 + (cend - dl.col0) / V;
-                r.dtype = d0.dtype;
-                r.mode = (int16_t)((tk.mode & ~0x0F20) | (d0.ebits << 8));
-                runs.push_back(r);
-                c = cend;
-                it = last + 1;
-            }
-        }
-        for (const DTask& t : runs) {
+            const DTask& t = tasks[k];
             const DOwner& ow = owners[t.owner];
             const int32_t dt = t.c0 < t.c1 ? items[t.item_start].dtype : -1;
             const int64_t bytes = (int64_t)(t.k1 - t.k0) * std::min(ow.nrows, 64) * 16;

@@ -66,8 +66,7 @@ hm_status build_queue(const Packed& P, int64_t n, Queue& q) {
         if (!tmp.empty() || P.staged[(size_t)k]) t.mode = (int16_t)(t.mode | 4);
         q.deps.insert(q.deps.end(), tmp.begin(), tmp.end());
         q.dep_first[(size_t)k + 1] = (int32_t)q.deps.size();
-        for (int32_t it = t.item_start; t.c0 < t.c1 && it < ow.item0 + ow.nitems && P.items[it].col0 < t.c1; ++it)
-            q.dtype_mask |= 1 << P.items[it].dtype;   // every format the task streams
+        if (t.c0 < t.c1) q.dtype_mask |= 1 << t.dtype;
     }
     // chain stages in plan order, the dense tasks aside, the final reductions last
     for (const Stage& st : P.stages) {

@@ -342,63 +342,28 @@ __device__ __forceinline__ void run_task(const DTask& tk, int lane, double* __re
         float a32 = 0.0f;
         const int64_t rt = (int64_t)nrows * 16;
         const uint8_t* sb = data + tk.stream + (uint32_t)(rr * 16);
-        // one run of items of one dtype and AFLP width
-        auto run_seg = [&](const DTask& sg, int sdt) {
 #define HM_STREAM_CASE(D)                                                                                \
     if constexpr ((MASK & (1 << D)) != 0)                                                                \
-        if (sdt == D)                                                                                    \
-            stream_task<D, ACC64, COH>(sg, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw, \
+        if (dt == D)                                                                                     \
+            stream_task<D, ACC64, COH>(tk, items, sb, rt, g, G, lane, deferred, vin, vin32, scales, dsrc, part, lw, \
                                        a64, a32, nx);
-            HM_STREAM_CASE(HM_F64)
-            HM_STREAM_CASE(HM_F32)
-            HM_STREAM_CASE(HM_BF16)
-            HM_STREAM_CASE(HM_F16)
-            HM_STREAM_CASE(HM_FP8E4M3)
-            HM_STREAM_CASE(HM_FPX24)
-            HM_STREAM_CASE(HM_FPX40)
-            HM_STREAM_CASE(HM_FPX48)
-            HM_STREAM_CASE(HM_FPX56)
-            HM_STREAM_CASE(HM_AFLP8)
-            HM_STREAM_CASE(HM_AFLP16)
-            HM_STREAM_CASE(HM_AFLP24)
-            HM_STREAM_CASE(HM_AFLP32)
-            HM_STREAM_CASE(HM_AFLP40)
-            HM_STREAM_CASE(HM_AFLP48)
-            HM_STREAM_CASE(HM_AFLP56)
+        HM_STREAM_CASE(HM_F64)
+        HM_STREAM_CASE(HM_F32)
+        HM_STREAM_CASE(HM_BF16)
+        HM_STREAM_CASE(HM_F16)
+        HM_STREAM_CASE(HM_FP8E4M3)
+        HM_STREAM_CASE(HM_FPX24)
+        HM_STREAM_CASE(HM_FPX40)
+        HM_STREAM_CASE(HM_FPX48)
+        HM_STREAM_CASE(HM_FPX56)
+        HM_STREAM_CASE(HM_AFLP8)
+        HM_STREAM_CASE(HM_AFLP16)
+        HM_STREAM_CASE(HM_AFLP24)
+        HM_STREAM_CASE(HM_AFLP32)
+        HM_STREAM_CASE(HM_AFLP40)
+        HM_STREAM_CASE(HM_AFLP48)
+        HM_STREAM_CASE(HM_AFLP56)
 #undef HM_STREAM_CASE
-        };
-        if (!(tk.mode & 32)) {
-            run_seg(tk, dt);
-        } else {
-            // the task spans several runs (mode bit 5): each is streamed with
-            // its own decoder into the same accumulators; the run bounds come
-            // from the item table (uniform loads)
-            int it = tk.item_start, c = tk.c0;
-            while (c < tk.c1) {
-                const DItem d0 = items[it];
-                int last = it;
-                int cend = min(d0.col0 + d0.ncols, tk.c1);
-                while (cend < tk.c1) {
-                    const DItem dn = items[last + 1];
-                    if (dn.dtype != d0.dtype || dn.ebits != d0.ebits) break;
-                    ++last;
-                    cend = min(dn.col0 + dn.ncols, tk.c1);
-                }
-                const DItem dl = items[last];
-                const int V = tile_cols_of(d0.dtype);
-                DTask sg = tk;
-                sg.c0 = c;
-                sg.c1 = cend;
-                sg.item_start = it;
-                sg.k0 = d0.tile0 + (c - d0.col0) / V;
-                sg.k1 = cend == dl.col0 + dl.ncols ? dl.tile0 + (dl.ncols + V - 1) / V : dl.tile0 + (cend - dl.col0) / V;
-                sg.dtype = d0.dtype;
-                sg.mode = (int16_t)((tk.mode & ~0x0F20) | (d0.ebits << 8));
-                run_seg(sg, d0.dtype);
-                c = cend;
-                it = last + 1;
-            }
-        }
         double v = a64 + (double)a32;
         for (int off = P; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);   // across column groups
         if (act && g == 0) {
