@@ -157,3 +157,39 @@ def test_codec_adjoint_parity():
     print(f"  rel err {err:.3e}", flush=True)
     M.free()
     assert err <= tol
+
+
+def _scaled(vals, fmt, f):
+    """The values of every stored matrix times f (a power of two: exact)."""
+    import copy
+    out = copy.copy(vals)
+    for name in ("dense", "W", "coupling"):
+        if hasattr(vals, name) and getattr(vals, name) is not None:
+            setattr(out, name, [None if a is None else a * f for a in getattr(vals, name)])
+    return out
+
+
+@pytest.mark.parametrize("fmt", ["h", "uh", "h2"])
+@pytest.mark.parametrize("pol", ["aflp_e6", "fpx_e6", "aflp_e8", "aflp16", "fpx40"])
+@pytest.mark.parametrize("shift", [-90, 90])
+def test_codec_extreme_magnitudes(fmt, pol, shift):
+    """Matrices scaled by 2^-90 and 2^90 (exactly): AFLP's per-column scale
+    exponents and FPX's exponents far from 1; the product stays within the
+    tolerance of the oracle's product of the same stored values, and equals
+    2^shift times the unscaled product's increment to rounding."""
+    import paper_2405_03456_amd as hm
+    st, lay, vals = case()
+    pp, tol = POLICIES[pol]
+    f = 2.0 ** shift
+    sv0 = _scaled(vals[fmt], fmt, f)
+    print(f"case codec magnitude {fmt} {pol} 2^{shift}", flush=True)
+    sv = stored.stored_values(st, fmt, sv0, dense=pp["dense"], diag=pp.get("diag"), factor=pp["factor"],
+                              coupling=pp.get("coupling"), eps=pp["eps"])
+    M = hm.Matrix(lay, fmt, sv0, **pp)
+    x, y = gaussian_vector(st.n, 4501), gaussian_vector(st.n, 5501) * f
+    out = product(M, x, y, 1.0)
+    ref = stored.product(st, fmt, sv, 1.0, x, y)
+    err = np.linalg.norm(out - ref) / np.linalg.norm(ref - y)
+    print(f"  rel err {err:.3e} (tol {tol:g})", flush=True)
+    assert np.all(np.isfinite(out)) and err <= tol
+    M.free()
