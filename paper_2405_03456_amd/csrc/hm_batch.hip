@@ -88,13 +88,13 @@ template <> struct Mfma<true> {
 };
 
 struct ItemPos {
-    int it, k0, k1, vec, sc;
+    int it, k0, k1, vec, sc, nc;
 };
 
 template <int V>
 __device__ __forceinline__ ItemPos item_pos(const DItem* __restrict__ items, int it) {
     const DItem d = items[it];
-    return ItemPos{it, d.tile0, d.tile0 + (d.ncols + V - 1) / V, d.vec_off, d.scale_off};
+    return ItemPos{it, d.tile0, d.tile0 + (d.ncols + V - 1) / V, d.vec_off, d.scale_off, d.ncols};
 }
 
 // Coefficient vectors (mode-0 outputs) are kept in one precision only: float64
@@ -162,7 +162,7 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
     ItemPos cur = item_pos<V>(items, tk.item_start);
     auto load = [&](Buf& f, int kb) {
         // uniform: the item of each of the 4 tiles of this step
-        int vec[4], sc[4], t0[4];
+        int vec[4], sc[4], t0[4], nc[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int t = min(kb + u, k1 - 1);
@@ -170,6 +170,7 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
             vec[u] = cur.vec;
             sc[u] = cur.sc;
             t0[u] = cur.k0;
+            nc[u] = cur.nc;
         }
         const int tt = kb + kq;
         const bool valid = tt < k1;
@@ -177,6 +178,7 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
         const int myvec = kq == 0 ? vec[0] : kq == 1 ? vec[1] : kq == 2 ? vec[2] : vec[3];
         const int mysc = kq == 0 ? sc[0] : kq == 1 ? sc[1] : kq == 2 ? sc[2] : sc[3];
         const int myt0 = kq == 0 ? t0[0] : kq == 1 ? t0[1] : kq == 2 ? t0[2] : t0[3];
+        const int mync = kq == 0 ? nc[0] : kq == 1 ? nc[1] : kq == 2 ? nc[2] : nc[3];
 #pragma unroll
         for (int g = 0; g < 4; ++g)
             if (g < nrg) f.q[g] = *reinterpret_cast<const uint4*>(base + (int64_t)tc * rt + rows[g] * 16);
@@ -186,7 +188,11 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
             const int64_t wi = (int64_t)(myvec + cb + c) * R + j0 + NRB * rl;
             T s = (T)1;
             if (mysc >= 0) s = (T)o.scales[mysc + cb + c];
-            if (!valid) s = (T)0;
+            // a step past the task's last tile, and the zero data past an
+            // item's last column, take weight zero (selected, not multiplied:
+            // the neighbouring input times the neighbouring scale there can
+            // overflow float32, and zero times infinity is NaN)
+            const bool in = valid && cb + c < mync;
             // float64 products read float64 inputs where they exist: always
             // in a float64 matrix, only x in a float32 one
             const bool wide_in = ACC64 && (o.mat64 || myvec + cb + c < o.n);
@@ -194,17 +200,17 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
                 // R and j0 are multiples of 32: wi is even, the pair aligned
                 if (wide_in) {
                     const double2 w = *reinterpret_cast<const double2*>(wsm + wi);
-                    f.b[c][0] = (T)w.x * s;
-                    f.b[c][1] = (T)w.y * s;
+                    f.b[c][0] = in ? (T)w.x * s : (T)0;
+                    f.b[c][1] = in ? (T)w.y * s : (T)0;
                 } else {
                     const float2 w = *reinterpret_cast<const float2*>(wsm32 + wi);
-                    f.b[c][0] = (T)w.x * s;
-                    f.b[c][1] = (T)w.y * s;
+                    f.b[c][0] = in ? (T)w.x * s : (T)0;
+                    f.b[c][1] = in ? (T)w.y * s : (T)0;
                 }
             } else {
 #pragma unroll
                 for (int b = 0; b < NRB; ++b)
-                    f.b[c][b] = (wide_in ? (T)wsm[wi + b] : (T)wsm32[wi + b]) * s;
+                    f.b[c][b] = in ? (wide_in ? (T)wsm[wi + b] : (T)wsm32[wi + b]) * s : (T)0;
             }
         }
     };

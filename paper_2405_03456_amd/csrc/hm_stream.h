@@ -22,9 +22,12 @@ namespace dev {
 
 // Accumulate one tile row.  WIDE: float64 accumulator with float64 inputs
 // w; otherwise float32 accumulator with the float32 mirror of the inputs.
+// Columns from `lim` on are the zero data past the item's last column: in
+// float32 their weight (a neighbouring input, times a neighbouring scale)
+// can overflow, so it is replaced by zero; float64 weights stay finite.
 template <int DT, bool WIDE, bool SCALED, typename WT>
 __device__ __forceinline__ void tile_acc(const uint4& q, const WT* __restrict__ w, const double* __restrict__ sc,
-                                         double& a64, float& a32, int e) {
+                                         double& a64, float& a32, int e, int lim) {
     using TT = Tile<DT>;
     typename TT::R v[TT::V];
     TT::decode(q, v, e);
@@ -37,6 +40,7 @@ __device__ __forceinline__ void tile_acc(const uint4& q, const WT* __restrict__ 
         } else {
             float wi = (float)w[i];
             if (SCALED) wi *= (float)sc[i];
+            if (i >= lim) wi = 0.0f;
             a32 = fmaf((float)v[i], wi, a32);
         }
     }
@@ -44,14 +48,14 @@ __device__ __forceinline__ void tile_acc(const uint4& q, const WT* __restrict__ 
 
 // Where the current item sits in the owner's tile stream.
 struct ItemPos {
-    int it, k0, k1, vec, sc;
+    int it, k0, k1, vec, sc, nc;
 };
 
 template <int DT>
 __device__ __forceinline__ ItemPos item_pos(const DItem* __restrict__ items, int it) {
     const DItem d = items[it];
     constexpr int V = Tile<DT>::V;
-    return ItemPos{it, d.tile0, d.tile0 + (d.ncols + V - 1) / V, d.vec_off, d.scale_off};
+    return ItemPos{it, d.tile0, d.tile0 + (d.ncols + V - 1) / V, d.vec_off, d.scale_off, d.ncols};
 }
 
 // Data produced and consumed inside one launch (the persistent schedule:
@@ -113,7 +117,10 @@ __device__ __forceinline__ void tile_acc_w(const uint4& q, const double* lw, int
 // float).  With
 // `deferred`, an input that is an unreduced sum (dsrc entry != 0) is formed
 // here from its partial sums, added in task order.  Past an item's last
-// column the values are not needed (its data is zero) but are finite.
+// column (the zero data of its last tile) the staged weight is exactly zero:
+// the neighbouring input times the neighbouring scale there can overflow
+// float32 (a large coefficient next to a large scale), and zero data times
+// an infinite weight would be NaN.
 // Each lane takes four entries per pass and loads up to four partial sums of
 // each at once, so the loads of a pass overlap instead of queueing.  With
 // COH, entries at or above nx (coefficients) and partial sums are read with
@@ -133,6 +140,7 @@ __device__ __forceinline__ void stage_inputs(const DTask& tk, const DItem* __res
     ItemPos st = item_pos<DT>(items, tk.item_start);
     for (int base = lane; base < nval; base += 64 * CH) {
         int e[CH], sc[CH];
+        bool in[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             const int idx = min(base + u * 64, nval - 1);   // a clamped entry is staged twice, same value
@@ -141,12 +149,13 @@ __device__ __forceinline__ void stage_inputs(const DTask& tk, const DItem* __res
             const int c = (t - st.k0) * V + idx % V;
             e[u] = st.vec + c;
             sc[u] = st.sc >= 0 ? st.sc + c : -1;
+            in[u] = c < st.nc;
         }
         int64_t d[CH];
         double v[CH], f[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-            d[u] = deferred ? dsrc[e[u]] : 0;
+            d[u] = deferred && in[u] ? dsrc[e[u]] : 0;
             v[u] = (COH && e[u] >= nx) ? ld_dev<true>(vin + e[u]) : vin[e[u]];
             f[u] = sc[u] >= 0 ? scales[sc[u]] : 1.0;
         }
@@ -173,9 +182,9 @@ __device__ __forceinline__ void stage_inputs(const DTask& tk, const DItem* __res
             const int idx = base + u * 64;
             if (idx < nval) {
                 if (WIDE)
-                    lw[idx] = v[u] * f[u];
+                    lw[idx] = in[u] ? v[u] * f[u] : 0.0;
                 else
-                    reinterpret_cast<float*>(lw)[idx] = (float)v[u] * (float)f[u];
+                    reinterpret_cast<float*>(lw)[idx] = in[u] ? (float)v[u] * (float)f[u] : 0.0f;
             }
         }
     }
@@ -217,16 +226,17 @@ __device__ __forceinline__ void stream_uniform(const DTask& tk, const DItem* __r
             if (kk < k1) {
                 while (kk >= st.k1) st = item_pos<DT>(items, st.it + 1);
                 const int c = (kk - st.k0) * V;
+                const int lim = st.nc - c;
                 if (WIDE) {
                     if (st.sc >= 0)
-                        tile_acc<DT, true, true>(q[u], vin + st.vec + c, scales + st.sc + c, a64, a32, e);
+                        tile_acc<DT, true, true>(q[u], vin + st.vec + c, scales + st.sc + c, a64, a32, e, lim);
                     else
-                        tile_acc<DT, true, false>(q[u], vin + st.vec + c, scales, a64, a32, e);
+                        tile_acc<DT, true, false>(q[u], vin + st.vec + c, scales, a64, a32, e, lim);
                 } else {
                     if (st.sc >= 0)
-                        tile_acc<DT, false, true>(q[u], vin32 + st.vec + c, scales + st.sc + c, a64, a32, e);
+                        tile_acc<DT, false, true>(q[u], vin32 + st.vec + c, scales + st.sc + c, a64, a32, e, lim);
                     else
-                        tile_acc<DT, false, false>(q[u], vin32 + st.vec + c, scales, a64, a32, e);
+                        tile_acc<DT, false, false>(q[u], vin32 + st.vec + c, scales, a64, a32, e, lim);
                 }
             }
         }
