@@ -457,7 +457,9 @@ hm_status hm_tune_batch(hm_matrix* m, int32_t nrhs, int32_t vec_dtype, int32_t r
  * launches on the second stream: its first dense_split tasks from the fork
  * point, the rest once fork2 chain stages are done (after the first part);
  * the tuner tries split fractions 1/4, 1/2, 3/4 at later second fork
- * points.  hm_tune_mvm times every candidate of both schedules (`reps`
+ * points.  Every fork point is timed with the upload's dense_grid and with
+ * caps of 1, 2 and 3 workgroups per compute unit on the dense stage; the
+ * chosen cap replaces dense_grid.  hm_tune_mvm times every candidate of both schedules (`reps`
  * replays of a captured graph of the product on a zero vector, allocated and
  * freed here; a matrix uploaded with HM_SCHED_STAGED has no persistent
  * candidates) and keeps the fastest for this matrix.  No candidate changes
@@ -477,6 +479,7 @@ typedef struct {
     int32_t fork2;          /* staged schedule: chain stages completed before the second part of the
                                dense stage starts (meaningful when dense_split > 0) */
     int32_t dense_split;    /* staged schedule: dense tasks in the first part (0 = one launch) */
+    int32_t dense_grid;     /* staged schedule: workgroup cap of the dense stage's launches (0 = none) */
 } hm_tune_mvm_result;
 hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream, hm_tune_mvm_result* out);
 

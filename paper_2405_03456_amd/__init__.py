@@ -252,7 +252,7 @@ class Matrix:
         return dict(fork_after=r.fork_after, ncandidates=r.ncandidates, ms=r.ms, ms_first=r.ms_first,
                     schedule="persistent" if r.schedule == _lib.HM_SCHED_PERSISTENT else "staged",
                     dense_after=r.dense_after, ms_staged=r.ms_staged, ms_persistent=r.ms_persistent,
-                    fork2=r.fork2, dense_split=r.dense_split)
+                    fork2=r.fork2, dense_split=r.dense_split, dense_grid=r.dense_grid)
 
     def set_schedule(self, schedule: str, param: int = 0):
         """hm_set_schedule: "staged" (param = fork point) or "persistent"

@@ -102,7 +102,8 @@ class TuneResult(ctypes.Structure):
 class TuneMvmResult(ctypes.Structure):
     _fields_ = [("fork_after", c_int32), ("ncandidates", c_int32), ("ms", c_double), ("ms_first", c_double),
                 ("schedule", c_int32), ("dense_after", c_int32), ("ms_staged", c_double),
-                ("ms_persistent", c_double), ("fork2", c_int32), ("dense_split", c_int32)]
+                ("ms_persistent", c_double), ("fork2", c_int32), ("dense_split", c_int32),
+                ("dense_grid", c_int32)]
 
 
 class ServeOpts(ctypes.Structure):

@@ -185,32 +185,34 @@ __device__ __forceinline__ void task_rows(const DTask& tk, const DItem* __restri
         const int cb = (tc - myt0) * V;
 #pragma unroll
         for (int c = 0; c < V; ++c) {
-            const int64_t wi = (int64_t)(myvec + cb + c) * R + j0 + NRB * rl;
+            // the zero data past an item's last column takes the weight of
+            // that last column (its own input and scale: finite), not the
+            // neighbouring entry's, whose input times scale can overflow
+            // float32 (zero times infinity is NaN); the index is clamped so
+            // the loads stay unconditional
+            const int cc = min(cb + c, mync - 1);
+            const int64_t wi = (int64_t)(myvec + cc) * R + j0 + NRB * rl;
             T s = (T)1;
-            if (mysc >= 0) s = (T)o.scales[mysc + cb + c];
-            // a step past the task's last tile, and the zero data past an
-            // item's last column, take weight zero (selected, not multiplied:
-            // the neighbouring input times the neighbouring scale there can
-            // overflow float32, and zero times infinity is NaN)
-            const bool in = valid && cb + c < mync;
+            if (mysc >= 0) s = (T)o.scales[mysc + cc];
+            if (!valid) s = (T)0;
             // float64 products read float64 inputs where they exist: always
             // in a float64 matrix, only x in a float32 one
-            const bool wide_in = ACC64 && (o.mat64 || myvec + cb + c < o.n);
+            const bool wide_in = ACC64 && (o.mat64 || myvec + cc < o.n);
             if constexpr (NRB == 2) {
                 // R and j0 are multiples of 32: wi is even, the pair aligned
                 if (wide_in) {
                     const double2 w = *reinterpret_cast<const double2*>(wsm + wi);
-                    f.b[c][0] = in ? (T)w.x * s : (T)0;
-                    f.b[c][1] = in ? (T)w.y * s : (T)0;
+                    f.b[c][0] = (T)w.x * s;
+                    f.b[c][1] = (T)w.y * s;
                 } else {
                     const float2 w = *reinterpret_cast<const float2*>(wsm32 + wi);
-                    f.b[c][0] = in ? (T)w.x * s : (T)0;
-                    f.b[c][1] = in ? (T)w.y * s : (T)0;
+                    f.b[c][0] = (T)w.x * s;
+                    f.b[c][1] = (T)w.y * s;
                 }
             } else {
 #pragma unroll
                 for (int b = 0; b < NRB; ++b)
-                    f.b[c][b] = in ? (wide_in ? (T)wsm[wi + b] : (T)wsm32[wi + b]) * s : (T)0;
+                    f.b[c][b] = (wide_in ? (T)wsm[wi + b] : (T)wsm32[wi + b]) * s;
             }
         }
     };

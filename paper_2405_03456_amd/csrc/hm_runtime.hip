@@ -812,27 +812,41 @@ extern "C" hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream_
         return HM_OK;
     };
     const int32_t keep_sched = m->schedule, keep_fork = m->fork_after, keep_da = m->p_dense_after;
-    int32_t best_sched = keep_sched, best_fork = keep_fork, best_da = keep_da;
+    const int32_t keep_grid = m->aux_grid;
+    int32_t best_sched = keep_sched, best_fork = keep_fork, best_da = keep_da, best_grid = keep_grid;
     double best_ms = 0.0;
     bool have = false;
-    // staged schedule: every fork point of the dense stage
+    // staged schedule: every fork point of the dense stage, with the upload's
+    // workgroup cap of that stage and with caps of 1, 2 and 3 workgroups per
+    // compute unit (fewer dense waves leave the latency-bound chain stages
+    // room on every compute unit)
+    std::vector<int32_t> grids{keep_grid};
+    int ncu = 0;
+    if (m->aux && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        for (int32_t g = 1; g <= 3; ++g)
+            if (g * ncu != keep_grid) grids.push_back(g * ncu);
     m->schedule = HM_SCHED_STAGED;
-    for (int32_t f = 0; f <= last && st == HM_OK; ++f) {
-        m->fork_after = f;
-        double t = 0.0;
-        st = time_it(t);
-        if (st != HM_OK) break;
-        ++out->ncandidates;
-        if (f == 0) out->ms_first = t;
-        if (out->ms_staged == 0.0 || t < out->ms_staged) out->ms_staged = t;
-        if (!have || t < best_ms) {
-            best_sched = HM_SCHED_STAGED;
-            best_fork = f;
-            best_ms = t;
-            have = true;
+    for (int32_t grid : grids) {
+        m->aux_grid = grid;
+        for (int32_t f = 0; f <= last && st == HM_OK; ++f) {
+            m->fork_after = f;
+            double t = 0.0;
+            st = time_it(t);
+            if (st != HM_OK) break;
+            ++out->ncandidates;
+            if (f == 0 && grid == keep_grid) out->ms_first = t;
+            if (out->ms_staged == 0.0 || t < out->ms_staged) out->ms_staged = t;
+            if (!have || t < best_ms) {
+                best_sched = HM_SCHED_STAGED;
+                best_fork = f;
+                best_grid = grid;
+                best_ms = t;
+                have = true;
+            }
         }
     }
     m->fork_after = best_sched == HM_SCHED_STAGED ? best_fork : keep_fork;
+    m->aux_grid = best_sched == HM_SCHED_STAGED && st == HM_OK ? best_grid : keep_grid;
     // split dense stage: with the best fork point, the second part from a
     // later chain stage (at most 8 second fork points, spread), a quarter,
     // half or three quarters of the dense tasks in the first part
@@ -898,10 +912,12 @@ extern "C" hm_status hm_tune_mvm(hm_matrix* m, int32_t reps, hm_stream_t stream_
         out->fork2 = m->fork2;
         out->dense_split = m->schedule == HM_SCHED_STAGED ? m->dense_split : 0;
         out->dense_after = m->p_dense_after;
+        out->dense_grid = m->aux_grid;
         out->ms = best_ms;
     } else {
         m->schedule = keep_sched;
         m->fork_after = keep_fork;
+        m->aux_grid = keep_grid;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

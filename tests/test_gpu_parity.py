@@ -144,10 +144,14 @@ def test_tune_mvm_keeps_results_bitwise(fmt):
     M.mvm(xd, y0, alpha=0.5)
     r = M.tune_mvm(reps=3)
     # staged: one candidate per fork point 0 ... number of chain stages with
-    # tasks; persistent: at most 17 interleave points
+    # tasks, for each of four caps on the dense stage's workgroups (none, 1,
+    # 2 and 3 per compute unit); persistent: at most 17 interleave points
     nchain = sum(1 for ph in M.timing() if ph["ntasks"] > 0 and ph["name"] not in ("dense", "persistent"))
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
     # (+ at most 24 split candidates: 8 second fork points x 3 fractions)
-    assert nchain + 2 <= r["ncandidates"] <= nchain + 1 + 24 + 17 and 0 <= r["fork_after"] <= nchain
+    nstaged = 4 * (nchain + 1)
+    assert nstaged + 1 <= r["ncandidates"] <= nstaged + 24 + 17 and 0 <= r["fork_after"] <= nchain
+    assert r["dense_grid"] in (0, ncu, 2 * ncu, 3 * ncu)
     assert r["dense_split"] == 0 or (r["schedule"] == "staged" and r["fork2"] > r["fork_after"])
     assert r["ms"] > 0 and r["ms"] <= r["ms_first"] and r["ms"] == min(r["ms_staged"], r["ms_persistent"])
     assert r["schedule"] == ("staged" if r["ms"] == r["ms_staged"] else "persistent")
