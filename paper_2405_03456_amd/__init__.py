@@ -159,13 +159,14 @@ SYNCS = {"owner": 0, "atomic": 1, "private": 2}
 def make_opts(task_bytes: int = 0, spread_dense: bool = False, dense_grid: int = 0, fork_after: int = 0,
               valr_promote: bool = False, schedule: str = "staged", dense_after: int = 0,
               spin_limit_us: int = 0, tickets_per_grab: int = 0, adjoint: bool = False, sync: str = "owner",
-              h2_levels: str = "coupling_first"):
+              h2_levels: str = "coupling_first", chain_task_bytes: int = 0):
     """hm_upload_opts (all zero = the library's defaults).  h2_levels:
     "coupling_first" (every level's couplings in one launch after the up
     pass) or "per_level" (couplings with the transfers of their level)."""
     return _lib.UploadOpts(int(task_bytes), int(bool(spread_dense)), int(dense_grid), int(fork_after),
                            int(bool(valr_promote)), SCHEDULES[schedule], int(dense_after), int(spin_limit_us),
-                           int(tickets_per_grab), SYNCS[sync], int(bool(adjoint)), H2_LEVELS[h2_levels])
+                           int(tickets_per_grab), SYNCS[sync], int(bool(adjoint)), H2_LEVELS[h2_levels],
+                           int(chain_task_bytes))
 
 
 def _stats_dict(s) -> dict:

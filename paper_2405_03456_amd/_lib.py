@@ -61,7 +61,8 @@ class UploadOpts(ctypes.Structure):
     _fields_ = [("task_bytes", c_int64), ("spread_dense", c_int32), ("dense_grid", c_int32),
                 ("fork_after", c_int32), ("valr_promote", c_int32), ("schedule", c_int32),
                 ("dense_after", c_int32), ("spin_limit_us", c_int32), ("tickets_per_grab", c_int32),
-                ("sync", c_int32), ("adjoint", c_int32), ("h2_levels", c_int32)]
+                ("sync", c_int32), ("adjoint", c_int32), ("h2_levels", c_int32),
+                ("chain_task_bytes", c_int64)]
 
 
 class Values(ctypes.Structure):

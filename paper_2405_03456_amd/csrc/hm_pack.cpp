@@ -483,8 +483,14 @@ struct Builder {
             // input values (tiles * V) per task
             const int64_t cap = (int64_t)(MAX_TASK_INPUTS / V) * bpt;
             // default task size by storage format (measured on the single-
-            // vector product): 32 KiB of float64 tiles, 16 KiB of narrower ones
-            const int64_t tb = opt.task_bytes ? opt.task_bytes : (it.dtype == HM_F64 ? 32768 : 16384);
+            // vector product): the dense near field 32 KiB of float64 tiles
+            // and 16 KiB of narrower ones, the dependent stages twice that
+            // (fewer tasks and partial sums on the chain)
+            const int64_t base = it.dtype == HM_F64 ? 32768 : 16384;
+            const int64_t tb = item_floating[ii] ? (opt.task_bytes ? opt.task_bytes : base)
+                               : opt.chain_task_bytes ? opt.chain_task_bytes
+                               : opt.task_bytes       ? opt.task_bytes
+                                                      : 2 * base;
             const int64_t target = std::min<int64_t>(tb, cap);
             int32_t j = 0;
             while (j < it.ncols) {
@@ -1584,8 +1590,8 @@ namespace hm {
 hm_status pack_options(const hm_upload_opts* o, PackOptions& opt) {
     opt = PackOptions{};
     if (!o) return HM_OK;
-    if (o->task_bytes != 0 && o->task_bytes < 1024) {
-        set_error("hm_upload: task_bytes must be 0 (default) or at least 1024");
+    if ((o->task_bytes != 0 && o->task_bytes < 1024) || (o->chain_task_bytes != 0 && o->chain_task_bytes < 1024)) {
+        set_error("hm_upload: task_bytes and chain_task_bytes must be 0 (default) or at least 1024");
         return HM_EINVAL;
     }
     if (o->dense_grid < 0 || o->fork_after < 0 || (o->spread_dense & ~1) || (o->valr_promote & ~1) ||
@@ -1616,6 +1622,7 @@ hm_status pack_options(const hm_upload_opts* o, PackOptions& opt) {
     opt.dense_after = o->dense_after;
     if (o->spin_limit_us) opt.spin_limit_us = o->spin_limit_us;
     if (o->task_bytes) opt.task_bytes = o->task_bytes;
+    if (o->chain_task_bytes) opt.chain_task_bytes = o->chain_task_bytes;
     opt.concurrent_dense = o->spread_dense == 0;
     opt.valr_promote = o->valr_promote != 0;
     if (o->h2_levels & ~1) {
