@@ -198,7 +198,8 @@ def test_upload_options_are_validated():
     lay = hm.Layout(p)
     h = compress_h(p, KERNEL_LAPLACE, st, 1e-6, method="svd")
     hm.plan_stats(lay, "h", h, eps=1e-6, task_bytes=1024)
-    for bad in (dict(task_bytes=100), dict(task_bytes=-5), dict(dense_grid=-1), dict(fork_after=-2)):
+    for bad in (dict(task_bytes=100), dict(task_bytes=-5), dict(dense_grid=-1), dict(fork_after=-2),
+                dict(chain_task_bytes=100), dict(chain_task_bytes=-1)):
         with pytest.raises(hm.HMError) as ex:
             hm.plan_stats(lay, "h", h, eps=1e-6, **bad)
         assert ex.value.status == _lib.HM_EINVAL, bad
@@ -213,6 +214,26 @@ def test_upload_options_are_validated():
     assert _lib.lib().hm_plan_stats(lay.handle, 0, ctypes.byref(v), ctypes.byref(prec), None,
                                     ctypes.byref(s)) == _lib.HM_OK
     assert s.nlaunch == hm.plan_stats(lay, "h", h, eps=1e-6)["nlaunch"]
+
+
+def test_chain_task_size_defaults():
+    """The dependent stages' tasks default to twice the per-format size of
+    the dense near field's (64 KiB of float64 tiles); task_bytes, when set,
+    sizes both unless chain_task_bytes is set too."""
+    from synth import KERNEL_LAPLACE, compress_h, to_h2
+    p = sphere_points(4096, 7)
+    st = trees.build_structure(p)
+    lay = hm.Layout(p)
+    v = to_h2(compress_h(p, KERNEL_LAPLACE, st, 1e-6, method="svd"), st)
+
+    def ntasks(**kw):
+        return hm.plan_stats(lay, "h2", v, eps=1e-6, **kw)["ntasks"]
+    base = ntasks()
+    assert base == ntasks(chain_task_bytes=65536)
+    assert ntasks(chain_task_bytes=32768) > base        # the old uniform default: more chain tasks
+    assert ntasks(task_bytes=32768) == ntasks(chain_task_bytes=32768)
+    assert ntasks(task_bytes=2000) == ntasks(task_bytes=2000, chain_task_bytes=2000)
+    assert ntasks(task_bytes=2000, chain_task_bytes=65536) < ntasks(task_bytes=2000)
 
 
 @pytest.mark.parametrize("tb", [0, 2000])
