@@ -246,8 +246,9 @@ typedef struct hm_matrix hm_matrix;
  *                  float64 data and 16384 for the narrower formats, else at
  *                  least 1024 (for every format)
  *   chain_task_bytes  the same for the tasks of the dependent stages only;
- *                  0 = task_bytes when that is set, else twice the format's
- *                  default (65536 / 32768)
+ *                  0 = task_bytes when that is set, else the format's
+ *                  default, doubled for matrices with at least 2048 leaf
+ *                  clusters
  *   spread_dense   1 = spread the dense leaves over the dependent stages
  *                  instead of one stage on a second stream
  *   dense_grid     cap on the workgroups of that second-stream stage (0 = none)
@@ -294,8 +295,8 @@ typedef struct {
                                one launch per level.  The same products; the transfer product is
                                its own partial sum in the first, so results agree to rounding. */
     int64_t chain_task_bytes; /* target stored bytes per task of the dependent stages (every task but
-                                 the dense near field's); 0 = task_bytes if set, else twice the
-                                 format's default; else at least 1024 */
+                                 the dense near field's); 0 = task_bytes if set, else the format's
+                                 default, doubled from 2048 leaf clusters on; else at least 1024 */
 } hm_upload_opts;
 
 #define HM_SCHED_STAGED 0

@@ -189,6 +189,9 @@ int32_t direct_for_eps(double eps) {
     return HM_F64;
 }
 
+// leaf clusters from which the dependent stages' default task size doubles
+constexpr int64_t kChainDoubleLeaves = 2048;
+
 struct Builder {
     const Layout& L;
     int32_t fmt;
@@ -483,14 +486,18 @@ struct Builder {
             // input values (tiles * V) per task
             const int64_t cap = (int64_t)(MAX_TASK_INPUTS / V) * bpt;
             // default task size by storage format (measured on the single-
-            // vector product): the dense near field 32 KiB of float64 tiles
-            // and 16 KiB of narrower ones, the dependent stages twice that
-            // (fewer tasks and partial sums on the chain)
+            // vector product): 32 KiB of float64 tiles, 16 KiB of narrower
+            // ones; the dependent stages of a matrix with at least
+            // kChainDoubleLeaves leaf clusters take twice that (fewer tasks
+            // and partial sums on the chain pay once its stages still have
+            // enough tasks to fill the chip; on smaller matrices they cost
+            // parallelism)
             const int64_t base = it.dtype == HM_F64 ? 32768 : 16384;
+            const int64_t chain = (int64_t)leaves.size() >= kChainDoubleLeaves ? 2 * base : base;
             const int64_t tb = item_floating[ii] ? (opt.task_bytes ? opt.task_bytes : base)
                                : opt.chain_task_bytes ? opt.chain_task_bytes
                                : opt.task_bytes       ? opt.task_bytes
-                                                      : 2 * base;
+                                                      : chain;
             const int64_t target = std::min<int64_t>(tb, cap);
             int32_t j = 0;
             while (j < it.ncols) {

@@ -8,7 +8,7 @@ namespace hm {
 
 struct PackOptions {
     int64_t task_bytes = 0;       // target matrix bytes per task (one wavefront); 0 = by format
-    int64_t chain_task_bytes = 0; // ... of the dependent stages' tasks (0 = task_bytes, else twice the format's)
+    int64_t chain_task_bytes = 0; // ... of the dependent stages' tasks (0 = task_bytes, else by format and size)
     bool concurrent_dense = true; // dense leaves as one independent stage (else spread over the stages)
     bool valr_promote = false;    // VALR: fill the 16-byte tiles of short format runs (see valr_formats)
     int32_t schedule = HM_SCHED_STAGED;

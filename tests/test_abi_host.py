@@ -217,23 +217,32 @@ def test_upload_options_are_validated():
 
 
 def test_chain_task_size_defaults():
-    """The dependent stages' tasks default to twice the per-format size of
-    the dense near field's (64 KiB of float64 tiles); task_bytes, when set,
-    sizes both unless chain_task_bytes is set too."""
+    """The dependent stages' tasks default to the dense near field's
+    per-format size (32 KiB of float64 tiles), doubled for matrices with at
+    least 2048 leaf clusters; task_bytes, when set, sizes both unless
+    chain_task_bytes is set too."""
     from synth import KERNEL_LAPLACE, compress_h, to_h2
-    p = sphere_points(4096, 7)
-    st = trees.build_structure(p)
-    lay = hm.Layout(p)
-    v = to_h2(compress_h(p, KERNEL_LAPLACE, st, 1e-6, method="svd"), st)
 
-    def ntasks(**kw):
-        return hm.plan_stats(lay, "h2", v, eps=1e-6, **kw)["ntasks"]
-    base = ntasks()
-    assert base == ntasks(chain_task_bytes=65536)
-    assert ntasks(chain_task_bytes=32768) > base        # the old uniform default: more chain tasks
-    assert ntasks(task_bytes=32768) == ntasks(chain_task_bytes=32768)
-    assert ntasks(task_bytes=2000) == ntasks(task_bytes=2000, chain_task_bytes=2000)
-    assert ntasks(task_bytes=2000, chain_task_bytes=65536) < ntasks(task_bytes=2000)
+    def case(n, leaf, seed):
+        p = sphere_points(n, seed)
+        st = trees.build_structure(p, leaf_size=leaf)
+        lay = hm.Layout(p, leaf_size=leaf)
+        nleaves = int((st.son0 < 0).sum())
+        return lay, compress_h(p, KERNEL_LAPLACE, st, 1e-4, method="aca"), nleaves
+
+    def ntasks(lay, v, **kw):
+        return hm.plan_stats(lay, "h", v, eps=1e-4, **kw)["ntasks"]
+    lay, v, nleaves = case(4096, 64, 7)
+    assert nleaves < 2048
+    base = ntasks(lay, v)
+    assert base == ntasks(lay, v, chain_task_bytes=32768) < ntasks(lay, v, chain_task_bytes=8192)
+    assert ntasks(lay, v, task_bytes=2000) == ntasks(lay, v, task_bytes=2000, chain_task_bytes=2000)
+    assert ntasks(lay, v, task_bytes=2000, chain_task_bytes=32768) < ntasks(lay, v, task_bytes=2000)
+    lay, v, nleaves = case(16384, 6, 9)
+    assert nleaves >= 2048
+    base = ntasks(lay, v)
+    assert base == ntasks(lay, v, chain_task_bytes=65536) < ntasks(lay, v, chain_task_bytes=32768)
+    assert ntasks(lay, v, task_bytes=32768) == ntasks(lay, v, chain_task_bytes=32768)
 
 
 @pytest.mark.parametrize("tb", [0, 2000])
