@@ -1343,6 +1343,12 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
             // the dense leaves read only x: one stage of their own, run on a
             // second stream next to the chain of dependent stages
             dense_stage = B.new_stage("dense");
+            // by dtype, so that the stage can run as one launch per dtype
+            // (aux_split_by_dtype); each owner's tasks keep their order
+            std::stable_sort(B.floating.begin(), B.floating.end(),
+                             [](const std::pair<DTask, int64_t>& a, const std::pair<DTask, int64_t>& b) {
+                                 return a.first.dtype < b.first.dtype;
+                             });
             for (auto& tb : B.floating) B.stage_tasks[dense_stage].push_back(tb.first);
         } else {
             for (auto& tb : B.floating) {
@@ -1482,7 +1488,11 @@ hm_status pack(const Layout& L, int32_t format, const hm_values* v, const hm_pre
     s.nitems = (int64_t)out.items.size();
     s.ntasks = (int64_t)out.tasks.size();
     s.nlaunch = 1;   // gather
-    for (auto& st : out.stages) s.nlaunch += (st.t1 > st.t0) + !st.reduce_launch.empty();
+    for (auto& st : out.stages) {
+        s.nlaunch += (st.t1 > st.t0) + !st.reduce_launch.empty();
+        if (st.aux && st.t1 > st.t0 && aux_split_by_dtype(st.dtype_mask))
+            s.nlaunch += __builtin_popcount(st.dtype_mask) - 1;   // one launch per dtype
+    }
     s.algorithmic_bytes = (double)(s.bytes_dense + s.bytes_factors + s.bytes_coupling + s.bytes_transfer +
                                    s.bytes_scales + s.bytes_meta) +
                           24.0 * L.n + 16.0 * (out.ws_elems - L.n);

@@ -20,6 +20,8 @@
 #include <string>
 #include <vector>
 
+#include "../../include/hm.h"
+
 namespace hm {
 
 struct DItem {            // 32 bytes
@@ -90,6 +92,16 @@ struct Stage {
     std::vector<int32_t> reduce_launch;   // the owners of `reduce` the single-vector product
                                           // reduces with a launch (y owners)
 };
+
+// The second-stream stage (the dense near field, independent tasks) runs as
+// one launch per dtype when its tasks hold more than one codec: each launch
+// then takes the task kernel compiled for that codec alone (fewer registers,
+// more waves per SIMD than the kernel of the whole codec family).  Its tasks
+// are sorted by dtype for that; results do not depend on the order.
+inline bool aux_split_by_dtype(int32_t mask) {
+    const int32_t codecs = mask >> HM_FPX24;
+    return codecs != 0 && __builtin_popcount(mask & ~1) > 1;
+}
 
 // A workspace entry that the single-vector product leaves as the partial
 // sums of its split owner: value = sum over l < count of part[base + l * stride],

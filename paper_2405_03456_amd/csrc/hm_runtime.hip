@@ -290,6 +290,16 @@ extern "C" hm_status hm_upload(const hm_layout* layout, int32_t format, const hm
         d.method_bytes = st.method_bytes;
         d.name = st.name;
         nlaunch += (d.ntasks > 0) + (d.nreduce > 0);
+        if (d.aux && d.ntasks > 0 && hm::aux_split_by_dtype(d.dtype_mask)) {
+            // one launch per run of one dtype (the packer sorted the tasks)
+            for (int64_t k = st.t0; k < st.t1; ++k) {
+                const int32_t dt = P.tasks[(size_t)k].dtype;
+                if (d.subs.empty() || d.subs.back().dtype != dt)
+                    d.subs.push_back(hm::DevStage::Sub{dt, (int32_t)(k - st.t0), 0});
+                d.subs.back().ntasks++;
+            }
+            nlaunch += (int32_t)d.subs.size() - 1;
+        }
         m->phases.push_back(d);
     }
     bool any_aux = false;
@@ -518,12 +528,15 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
             (void)hipStreamWaitEvent(main_stream, m->ev_join, 0);
             joined = true;
         }
-        // tasks [t0, t0 + nt) of this stage as one launch on `stream`
-        auto launch = [&](int64_t t0, int32_t nt) -> bool {
+        // tasks [t0, t0 + nt) of this stage as one launch on `stream` (of
+        // the kernel for `mask`)
+        int32_t nlaunched = 0;
+        auto launch1 = [&](int64_t t0, int32_t nt, int32_t mask) -> bool {
+            ++nlaunched;
             unsigned blocks = (unsigned)((nt + 3) / 4);
             if (ph.aux && m->aux_grid > 0) blocks = std::min<unsigned>(blocks, (unsigned)m->aux_grid);
             dim3 grid(blocks);
-            const hm::dev::TaskKernel kern = hm::dev::task_kernel(m->acc64 != 0, ph.dtype_mask);
+            const hm::dev::TaskKernel kern = hm::dev::task_kernel(m->acc64 != 0, mask);
             if (timing) {
                 // the event pair is part of the dispatch: it brackets the
                 // kernel's execution, as a kernel trace does
@@ -541,9 +554,21 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
             }
             return true;
         };
+        // tasks [t0, t0 + nt): one launch, or one per run of one dtype
+        // (sub-runs of a split second-stream stage; F64 runs with the
+        // hardware kernel, a codec run with that codec's own kernel)
+        auto launch = [&](int64_t t0, int32_t nt) -> bool {
+            if (ph.subs.empty()) return launch1(t0, nt, ph.dtype_mask);
+            bool ok = true;
+            for (const auto& sb : ph.subs) {
+                const int64_t a = std::max<int64_t>(t0, ph.t0 + sb.t0);
+                const int64_t b = std::min<int64_t>(t0 + nt, ph.t0 + sb.t0 + sb.ntasks);
+                if (ok && a < b) ok = launch1(a, (int32_t)(b - a), sb.dtype < 0 ? 1 : (1 << sb.dtype) | 1);
+            }
+            return ok;
+        };
         if (ph.ntasks > 0) {
             const bool split = ph.aux && m->dense_split > 0 && m->dense_split < ph.ntasks;
-            ph.timed_parts = split ? 2 : 1;
             bool ok = true;
             if (split) {
                 // first part from the fork point; the second after fork2
@@ -558,6 +583,7 @@ extern "C" hm_status hm_mvm(hm_matrix* m, double alpha, const double* x, double*
             } else {
                 ok = launch(ph.t0, ph.ntasks);
             }
+            ph.timed_parts = std::max(nlaunched, 1);   // launches of this stage per product
             if (!ok) {
                 hm::set_error("hm_mvm: timing events failed");
                 return HM_EDEVICE;
