@@ -556,8 +556,8 @@ def main():
     ap.add_argument("--serve-budget", type=float, default=4e9)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
-              "multi-GPU sharding is described in DESIGN.md but not run", file=sys.stderr)
+        print(f"bench.py: the product runs on one GPU only (--gpus {args.gpus} requested); "
+              "sharding over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
